@@ -1,0 +1,92 @@
+"""Oracle: the self-consistent Maxwell-Schroedinger step.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section "Efficient numerical implementation ...": each molecule is driven by
+the local electric field; its induced dipole, multiplied by the molecular
+number density (mean-field approximation), gives the macroscopic
+polarisation P, and J = dP/dt enters Ampere's law (Eq. (1)).
+
+One coupled step n -> n+1, in this order:
+  1. H^{n+1/2} from E^n                                      (Eq. (1))
+  2. E_mol,i = E_x^n at the molecule's E_x edge, in atomic units
+  3. every molecule: psi^n -> psi^{n+1} under E_mol,i held over the step
+  4. d_i^{n+1}; P_c^{n+1} = (w / dx^3) sum_{i in c} d_i (e a0), summed cell by
+     cell in molecule-index order; J_mol,c = (P_c^{n+1} - P_c^n) / dt
+  5. E^{n+1} with the Drude, molecular and source currents    (Eqs. (1), (2))
+  6. flux-monitor sample
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from workloads.geometry import eps_table, material_map
+from workloads.molecule_inputs import morse_v0, potentials
+
+from .fdtd import FluxMonitor, yee_from_config
+from .maps import cells_from_config, csr
+from .molecule import model_from_config
+
+E_AU = 5.14220674763e11      # V/m
+EA0 = 8.4783536255e-30       # C m
+
+
+class CoupledOracle:
+    def __init__(self, cfg, n_mol=None, cells=None, mat=None, yee=None):
+        self.cfg = cfg
+        if mat is None:
+            mat = material_map(cfg)
+        self.mat = mat
+        self.yee = yee if yee is not None else yee_from_config(cfg, mat, eps_table(cfg))
+        ug, ue, mu = potentials(cfg)
+        self.mol = model_from_config(cfg, ug, ue, mu)
+        if cells is None:
+            cells = cells_from_config(cfg)
+        if n_mol is not None:
+            cells = cells[:n_mol]
+        self.cells = np.asarray(cells, dtype=np.int64)
+        self.n_mol = len(self.cells)
+        self.occ, self.ptr, self.perm = csr(self.cells)
+        self.psi = self.mol.initial_state(self.n_mol, morse_v0(cfg))
+        self.absorbed = np.zeros(self.n_mol)
+        self.P = np.zeros(len(self.occ))
+        self.Jmol = np.zeros(len(self.occ))
+        self.monitor = FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k, cfg.freqs, cfg.dt, cfg.mon_every)
+        self.d = np.zeros(self.n_mol)
+
+    def cell_sums(self, d):
+        """Per occupied cell, the sum of its molecules' dipoles in CSR order."""
+        out = np.zeros(len(self.occ))
+        for c in range(len(self.occ)):
+            acc = 0.0
+            for idx in range(self.ptr[c], self.ptr[c + 1]):
+                acc += d[self.perm[idx]]
+            out[c] = acc
+        return out
+
+    def step(self, n, src_value):
+        cfg = self.cfg
+        yee = self.yee
+        yee.update_H()
+        e_mol = yee.E[0].reshape(-1)[self.cells] / E_AU
+        self.psi, self.absorbed = self.mol.step(self.psi, e_mol, self.absorbed)
+        self.d = self.mol.dipole(self.psi)
+        P_new = cfg.mol_weight * self.cell_sums(self.d) * EA0 / cfg.dx ** 3
+        self.Jmol = (P_new - self.P) / cfg.dt
+        self.P = P_new
+        yee.update_E(src_value, cfg.src_k, self.occ, self.Jmol)
+        self.monitor.sample(yee, n)
+        return e_mol
+
+    def run(self, src_values, n0=0, record_fields=False):
+        """Run len(src_values) steps from step n0; returns per-step traces."""
+        nst = len(src_values)
+        trace = {"D": np.zeros(nst), "d": np.zeros((nst, self.n_mol)),
+                 "E_mol": np.zeros((nst, self.n_mol))}
+        for s in range(nst):
+            e_mol = self.step(n0 + s, src_values[s])
+            trace["D"][s] = self.d.sum()
+            trace["d"][s] = self.d
+            trace["E_mol"][s] = e_mol
+        return trace
