@@ -1,0 +1,219 @@
+/*
+ * msqd.h - C ABI of the MI355X library for the coupled Maxwell-Schroedinger
+ * step of Sukharev, "Efficient parallel strategy for molecular plasmonics"
+ * (arXiv 2209.04487).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers are caller-owned (PyTorch allocations), contiguous and
+ *    at least 16-byte aligned.  The library never allocates or frees device
+ *    memory.  Host pointers are read during the call only.
+ *  - `stream` is a hipStream_t passed as void*.  Calls only enqueue work on it
+ *    (init calls also wait for their own host-to-device table copies); results
+ *    land in device buffers.
+ *  - Return value: MSQD_OK (0) or a negative MSQD_E* code.  On a negative
+ *    return nothing was launched; msqd_last_error() gives a thread-local
+ *    message.
+ *  - Units: the molecule side is in Hartree atomic units, the field side in
+ *    SI (the paper gives its potential parameters in a.u. and writes Maxwell's
+ *    equations in SI).  Conversions use CODATA 2018 values.
+ *  - Precision `prec`: MSQD_FP64 (complex128 wavepackets, float64 fields),
+ *    MSQD_FP32 (complex64 wavepackets and FP32 J<->angle transform, float32
+ *    fields), MSQD_MIXED (complex64 wavepackets, the J<->angle transform on
+ *    BF16 matrix cores with a hi/lo split and FP32 accumulation, float32
+ *    fields).  Per-molecule and per-cell reductions (absorbed norm, dipole,
+ *    norm, yield, cell polarisation) are float64 in every form.
+ *
+ * Wavepacket layout: psi[mol][s][J][r] complex (interleaved re, im), s = 0
+ * ground, 1 excited, J = 0..j_max (m = 0), r = 0..n_r-1 on the periodic grid
+ * r_k = r_min + k (r_max - r_min)/n_r.
+ * Field layout: every component is [nz][ny][nx] with x fastest; E_x sits at
+ * (i+1/2, j, k), E_y (i, j+1/2, k), E_z (i, j, k+1/2), H_x (i, j+1/2, k+1/2),
+ * H_y (i+1/2, j, k+1/2), H_z (i+1/2, j+1/2, k) in cell units.
+ */
+#ifndef MSQD_H
+#define MSQD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MSQD_OK = 0,
+  MSQD_EINVAL = -1,     /* null pointer, bad extent or alignment            */
+  MSQD_ESHAPE = -2,     /* sizes inconsistent with each other / workspace   */
+  MSQD_EPREC = -3,      /* unknown precision                                */
+  MSQD_EUNSUP = -4,     /* unsupported size (n_r not 2^k in [64,512], ...)  */
+  MSQD_EDEVICE = -5,    /* HIP runtime error                                */
+  MSQD_ENONFINITE = -6  /* a readout found NaN/Inf                          */
+};
+
+enum { MSQD_FP64 = 0, MSQD_FP32 = 1, MSQD_MIXED = 2 };
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* msqd_last_error(void);
+/* Library version (major*10000 + minor*100 + patch). */
+int msqd_version(void);
+
+/* ------------------------------------------------------------------------
+ * Molecules: two-state ro-vibrational wavepackets, Eqs. (3)-(5).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_mol;          /* molecules in the batch                        */
+  int32_t n_r;            /* radial points: 64, 128, 256 or 512            */
+  int32_t j_max;          /* rotational basis J = 0..j_max (m = 0), <= 15  */
+  int32_t prec;           /* MSQD_FP64 | MSQD_FP32 | MSQD_MIXED            */
+  double r_min, r_max;    /* periodic radial box, bohr (r_max excluded)    */
+  double mass_au;         /* reduced mass, electron masses                 */
+  double dt_au;           /* molecular time step, atomic units             */
+  double absorb_width_au; /* cos^(1/8) absorber over [r_max - w, r_max); 0 = none */
+  double r_diss_au;       /* dissociated population counts r > r_diss      */
+} qd_desc;
+
+/* Bytes of device workspace (tables and a status word) for qd_* calls. */
+size_t qd_workspace_bytes(const qd_desc* d);
+
+/* Build the split-operator tables (Eq. (5) phases on the grid, the
+ * Gauss-Legendre angular grid that integrates the angular part of Eq. (4)
+ * exactly on the truncated basis, absorber mask) into `ws` and set every
+ * molecule to (g, J=0) with radial function psi0 (host [n_r], real),
+ * all other channels 0; absorbed[] := 0.
+ * U_g, U_e: host [n_r] surfaces (hartree); mu12: host [n_r] transition
+ * dipole (e a0), all sampled on the grid. */
+int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double* mu12,
+            const double* psi0, void* ws, size_t ws_bytes, void* psi, double* absorbed,
+            void* stream);
+
+/* Advance every molecule n_steps split-operator steps (K/2 V/2 C(E) V/2 K/2,
+ * then the absorber) under a field held constant over the call.
+ * E_mol: device [n_mol] float64 field along the quantisation axis (au).
+ * absorbed: device [n_mol] float64, accumulated.  d_mol: device [n_mol]
+ * float64 dipole <mu12 cos(theta) sigma_x> (e a0) after the last step, or
+ * NULL. */
+int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
+            double* absorbed, double* d_mol, int32_t n_steps, void* stream);
+
+/* Per-molecule readouts of the current state (float64, device):
+ * d_mol (e a0), norm_mol (sum |psi|^2 dr), yield_mol (norm beyond r_diss
+ * plus absorbed).  Any output may be NULL.  The state is not modified. */
+int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
+                   double* d_mol, double* norm_mol, double* yield_mol, void* stream);
+
+/* Synchronise `stream`, then report MSQD_ENONFINITE (and clear the flag) if
+ * any molecular step since the last check produced a non-finite dipole,
+ * norm or absorbed norm; MSQD_OK otherwise.  ws is a qd workspace. */
+int msqd_check_status(const void* ws, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Fields: Yee leap-frog of Eq. (1) with the Drude current of Eq. (2).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz;     /* cells; x and y periodic                        */
+  int32_t npml;           /* CPML thickness (cells) at each z end, >= 1     */
+  int32_t prec;           /* MSQD_FP64 | MSQD_FP32 | MSQD_MIXED (FP32 fields) */
+  int32_t metal_id;       /* material id that carries the Drude current     */
+  double dx;              /* cell size (m)                                  */
+  double dt;              /* time step (s)                                  */
+  double eps_r[4];        /* relative permittivity per material id (eps_inf for the metal) */
+  double drude_wp;        /* plasma frequency (rad/s), Eq. (2)              */
+  double drude_gamma;     /* damping (rad/s), Eq. (2)                       */
+  double cpml_m;          /* polynomial grading order                       */
+  double sigma_max_lo, sigma_max_hi;  /* CPML sigma_max at the low / high z end (S/m) */
+  double kappa_max, alpha_max;        /* CPML kappa_max (>= 1), alpha_max (S/m) */
+  int32_t src_k;          /* plane of the soft current sheet on E_x         */
+  int32_t mon_k;          /* detection plane (npml < mon_k < nz - npml)     */
+  int32_t n_freq;         /* monitor frequencies (0 = no monitor)           */
+  int32_t mon_every;      /* monitor sampling interval in steps             */
+} fdtd_desc;
+
+/* Device buffers of the field solver; element type is double (FP64) or
+ * float (FP32/MIXED) for the field arrays. */
+typedef struct {
+  void *Ex, *Ey, *Ez, *Hx, *Hy, *Hz;   /* [nz][ny][nx] each                 */
+  void *JDx, *JDy, *JDz;               /* Drude currents, [nz][ny][nx] each */
+  void* psi;       /* CPML auxiliaries: 4 x [2*npml][ny][nx] (psi_Ex, psi_Ey, psi_Hx, psi_Hy),
+                      planes k < npml then k >= nz - npml                    */
+  uint8_t* mat;    /* [3][nz][ny][nx] material id per E-component location  */
+  double* dft;     /* [4][n_freq][ny][nx] complex128 (E_x, E_y, H_x, H_y) or NULL */
+} fdtd_fields;
+
+size_t fdtd_workspace_bytes(const fdtd_desc* d);
+/* Bytes of the CPML auxiliary buffer `psi` and of the monitor buffer `dft`. */
+size_t fdtd_psi_bytes(const fdtd_desc* d);
+size_t fdtd_dft_bytes(const fdtd_desc* d);
+
+/* Zero every field, copy the host material map mat_host [3][nz][ny][nx] to
+ * f->mat, and build the CPML coefficient profiles and monitor frequencies
+ * (host [n_freq], rad/s) into ws. */
+int fdtd_init(const fdtd_desc* d, const uint8_t* mat_host, const double* freqs,
+              const fdtd_fields* f, void* ws, size_t ws_bytes, void* stream);
+
+/* One field step n -> n+1 without molecules: H^{n+1/2}, then E^{n+1} with the
+ * Drude current and the source sheet J_x = -2 src_value/(eta0 dx) on plane
+ * src_k (src_value = E_inc(t_{n+1/2}) in V/m), then a monitor sample when
+ * (n+1) % mon_every == 0. */
+int fdtd_step(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t n,
+              double src_value, void* stream);
+
+/* Plane-averaged z-flux S(w_f) = <1/2 Re(E_x H_y* - E_y H_x*)> of the monitor
+ * DFTs into flux (device [n_freq] float64). */
+int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Coupling: molecules <-> cells, the self-consistent step.
+ * ---------------------------------------------------------------------- */
+
+/* Host helper: molecule -> flat E_x index and the CSR of occupied cells.
+ * Molecules are placed with SplitMix64(seed), three words per molecule,
+ * i = ((u>>11)*nx)>>53, j likewise, k = slab_k0 + ((u>>11)*slab_nk)>>53.
+ * Outputs (host): cell_of_mol [n_mol], occ_cell [n_mol] (first *n_occ
+ * used, increasing), occ_ptr [n_mol+1] (first *n_occ+1 used), mol_perm
+ * [n_mol] (molecules cell by cell, increasing index inside a cell). */
+int map_build(int32_t n_mol, int32_t nx, int32_t ny, int32_t nz, uint64_t seed,
+              int32_t slab_k0, int32_t slab_nk, int32_t* cell_of_mol, int32_t* occ_cell,
+              int32_t* occ_ptr, int32_t* mol_perm, int32_t* n_occ);
+
+/* The same CSR for a caller-given cell_of_mol (host). */
+int map_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t* occ_cell,
+            int32_t* occ_ptr, int32_t* mol_perm, int32_t* n_occ);
+
+typedef struct {
+  qd_desc qd;
+  fdtd_desc fd;
+  int32_t n_occ;        /* occupied cells                                  */
+  double mol_weight;    /* molecules represented by each simulated one     */
+} cpl_desc;
+
+typedef struct {
+  void* psi;                 /* wavepackets (see qd_step)                  */
+  double* absorbed;          /* [n_mol]                                    */
+  double* d_mol;             /* [n_mol] dipoles after the last step        */
+  double* E_mol;             /* [n_mol] field seen in the last step (au)   */
+  double* P_c;               /* [n_occ] cell polarisation (C/m^2)          */
+  double* J_mol;             /* [n_occ] last polarisation current (A/m^2)  */
+  const int32_t* cell_of_mol;  /* [n_mol] flat E_x index                   */
+  const int32_t* occ_cell;     /* [n_occ]                                  */
+  const int32_t* occ_ptr;      /* [n_occ+1]                                */
+  const int32_t* mol_perm;     /* [n_mol]                                  */
+  fdtd_fields f;
+  const void* qd_ws;
+  const void* fd_ws;
+} cpl_state;
+
+/* n_steps coupled steps from step n0 (section "Efficient numerical
+ * implementation ..."): H^{n+1/2}; E_mol = E_x^n at each molecule's edge;
+ * every molecule one step under E_mol; d_i; P_c^{n+1} = (w/dx^3) sum_{i in c}
+ * d_i (e a0) in CSR order and J_mol = (P_c^{n+1} - P_c^n)/dt; E^{n+1} with
+ * Drude, molecular and source currents; monitor sample.
+ * src_values: host [n_steps], E_inc(t_{n+1/2}) in V/m. */
+int coupled_step(const cpl_desc* d, const cpl_state* s, const double* src_values, int64_t n0,
+                 int32_t n_steps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSQD_H */

@@ -1,0 +1,614 @@
+// C ABI of libmsqd: argument validation, workspace tables, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdtd.h"
+#include "host_tables.h"
+#include "mol.h"
+
+namespace msqd {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int check_hip(hipError_t e, const char* what) {
+  g_err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return MSQD_EDEVICE;
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+QdLayout qd_layout(int n_r, int nj) {
+  QdLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t nr = n_r, J = nj;
+  L.status = take(16);
+  L.psi0 = take(8 * nr);
+  L.kin_d = take(16 * nr);
+  L.tw_d = take(16 * nr);
+  L.vph_d = take(16 * 2 * J * nr);
+  L.tm_d = take(8 * J * J);
+  L.x_d = take(8 * J);
+  L.mudt_d = take(8 * nr);
+  L.mask_d = take(8 * nr);
+  L.mu_d = take(8 * nr);
+  L.cj_d = take(8 * J);
+  L.kin_f = take(8 * nr);
+  L.tw_f = take(8 * nr);
+  L.vph_f = take(8 * 2 * J * nr);
+  L.tm_f = take(4 * J * J);
+  L.x_f = take(4 * J);
+  L.mudt_f = take(4 * nr);
+  L.mask_f = take(4 * nr);
+  L.tmfrag = take(4 * 64 * 8 * 2);  // bf16 fragments: 4 operand blocks x 64 lanes x 8 values x 2 B
+  L.total = o;
+  return L;
+}
+
+FdLayout fd_layout(const fdtd_desc* d) {
+  FdLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t nz = d->nz;
+  L.bE = take(8 * nz);
+  L.aE = take(8 * nz);
+  L.kE = take(8 * nz);
+  L.bH = take(8 * nz);
+  L.aH = take(8 * nz);
+  L.kH = take(8 * nz);
+  L.bEf = take(4 * nz);
+  L.aEf = take(4 * nz);
+  L.kEf = take(4 * nz);
+  L.bHf = take(4 * nz);
+  L.aHf = take(4 * nz);
+  L.kHf = take(4 * nz);
+  L.freqs = take(8 * static_cast<size_t>(d->n_freq > 0 ? d->n_freq : 1));
+  L.total = o;
+  return L;
+}
+
+size_t mol_lds_bytes(int n_r, int nj, int prec) {
+  const int r2 = (n_r == 64 || n_r == 128) ? 8 : 16;
+  const size_t el = prec == MSQD_FP64 ? 16 : 8;
+  return el * static_cast<size_t>(2 * nj) * (n_r + r2) + 16 * 4 * sizeof(double);
+}
+
+size_t mol_lds_limit() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0) {
+      cached = v;
+    } else {
+      cached = 64 * 1024;
+    }
+    (void)hipGetLastError();
+  }
+  return static_cast<size_t>(cached);
+}
+
+// ------------------------------------------------------------ validation
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+static int check_qd(const qd_desc* d) {
+  if (!d) return fail(MSQD_EINVAL, "qd_desc is NULL");
+  if (d->n_mol < 0) return fail(MSQD_EINVAL, "n_mol < 0");
+  if (d->n_r != 64 && d->n_r != 128 && d->n_r != 256 && d->n_r != 512)
+    return fail(MSQD_EUNSUP, "n_r must be 64, 128, 256 or 512");
+  if (d->j_max < 0 || d->j_max + 1 > kMaxNJ) return fail(MSQD_EUNSUP, "j_max must be in [0, 15]");
+  if (d->prec != MSQD_FP64 && d->prec != MSQD_FP32 && d->prec != MSQD_MIXED)
+    return fail(MSQD_EPREC, "unknown precision");
+  if (!(d->r_max > d->r_min) || !(d->r_min > 0.0)) return fail(MSQD_EINVAL, "need 0 < r_min < r_max");
+  if (!(d->mass_au > 0.0) || !(d->dt_au > 0.0)) return fail(MSQD_EINVAL, "mass and dt must be > 0");
+  if (d->absorb_width_au < 0.0 || d->absorb_width_au > d->r_max - d->r_min)
+    return fail(MSQD_EINVAL, "absorber width outside the box");
+  if (!std::isfinite(d->r_diss_au)) return fail(MSQD_EINVAL, "r_diss not finite");
+  return MSQD_OK;
+}
+
+static int check_fd(const fdtd_desc* d) {
+  if (!d) return fail(MSQD_EINVAL, "fdtd_desc is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 4) return fail(MSQD_EINVAL, "grid too small");
+  if (static_cast<double>(d->nx) * d->ny * d->nz > 2.0e9) return fail(MSQD_EUNSUP, "grid too large");
+  if (d->npml < 1 || 2 * d->npml >= d->nz) return fail(MSQD_EINVAL, "npml must satisfy 1 <= npml < nz/2");
+  if (d->prec != MSQD_FP64 && d->prec != MSQD_FP32 && d->prec != MSQD_MIXED)
+    return fail(MSQD_EPREC, "unknown precision");
+  if (!(d->dx > 0.0) || !(d->dt > 0.0)) return fail(MSQD_EINVAL, "dx and dt must be > 0");
+  if (kC0 * d->dt / d->dx > 1.0 / std::sqrt(3.0)) return fail(MSQD_EINVAL, "Courant number above 1/sqrt(3)");
+  for (int m = 0; m < 4; ++m)
+    if (!(d->eps_r[m] > 0.0)) return fail(MSQD_EINVAL, "eps_r must be > 0");
+  if (d->metal_id < 0 || d->metal_id > 3) return fail(MSQD_EINVAL, "metal_id must be in [0, 3]");
+  if (d->kappa_max < 1.0 || d->alpha_max < 0.0 || d->sigma_max_lo < 0.0 || d->sigma_max_hi < 0.0)
+    return fail(MSQD_EINVAL, "bad CPML parameters");
+  if (d->src_k < 1 || d->src_k >= d->nz) return fail(MSQD_EINVAL, "src_k outside the grid");
+  if (d->n_freq < 0) return fail(MSQD_EINVAL, "n_freq < 0");
+  if (d->n_freq > 0) {
+    if (d->mon_k <= d->npml || d->mon_k >= d->nz - d->npml)
+      return fail(MSQD_EINVAL, "mon_k must be inside the interior");
+    if (d->mon_every < 1) return fail(MSQD_EINVAL, "mon_every must be >= 1");
+  }
+  return MSQD_OK;
+}
+
+static int check_fields(const fdtd_desc* d, const fdtd_fields* f) {
+  if (!f) return fail(MSQD_EINVAL, "fdtd_fields is NULL");
+  const void* ptrs[] = {f->Ex, f->Ey, f->Ez, f->Hx, f->Hy, f->Hz, f->JDx, f->JDy, f->JDz, f->psi};
+  for (const void* p : ptrs) {
+    if (!p) return fail(MSQD_EINVAL, "a field pointer is NULL");
+    if (!aligned16(p)) return fail(MSQD_EINVAL, "field pointers must be 16-byte aligned");
+  }
+  if (!f->mat) return fail(MSQD_EINVAL, "material pointer is NULL");
+  if (d->n_freq > 0 && (!f->dft || !aligned16(f->dft)))
+    return fail(MSQD_EINVAL, "monitor buffer missing or misaligned");
+  return MSQD_OK;
+}
+
+static FdArgs make_fd_args(const fdtd_desc* d, const fdtd_fields* f, const void* ws) {
+  FdArgs a{};
+  a.nx = d->nx;
+  a.ny = d->ny;
+  a.nz = d->nz;
+  a.npml = d->npml;
+  a.metal_id = d->metal_id;
+  a.src_k = d->src_k;
+  a.inv_dx = 1.0 / d->dx;
+  a.cH = d->dt / kMu0;
+  for (int m = 0; m < 4; ++m) a.ce[m] = d->dt / (kEps0 * d->eps_r[m]);
+  const double g = d->drude_gamma, wp = d->drude_wp, dt = d->dt;
+  a.alpha_d = (1.0 - g * dt / 2.0) / (1.0 + g * dt / 2.0);
+  a.beta_d = kEps0 * wp * wp * dt / (1.0 + g * dt / 2.0);
+  a.Ex = f->Ex;
+  a.Ey = f->Ey;
+  a.Ez = f->Ez;
+  a.Hx = f->Hx;
+  a.Hy = f->Hy;
+  a.Hz = f->Hz;
+  a.JDx = f->JDx;
+  a.JDy = f->JDy;
+  a.JDz = f->JDz;
+  a.psi = f->psi;
+  a.mat = f->mat;
+  a.ws = static_cast<const char*>(ws);
+  a.lay = fd_layout(d);
+  return a;
+}
+
+static MolArgs make_mol_args(const qd_desc* d, const void* ws) {
+  MolArgs a{};
+  a.n_mol = d->n_mol;
+  a.nj = d->j_max + 1;
+  a.dr = (d->r_max - d->r_min) / d->n_r;
+  a.ws = static_cast<const char*>(ws);
+  a.lay = qd_layout(d->n_r, d->j_max + 1);
+  a.status = reinterpret_cast<int*>(const_cast<char*>(a.ws) + a.lay.status);
+  a.inv_eau = 1.0 / kEau;
+  // first index with r > r_diss
+  int kd = d->n_r;
+  for (int k = 0; k < d->n_r; ++k) {
+    if (d->r_min + k * a.dr > d->r_diss_au) {
+      kd = k;
+      break;
+    }
+  }
+  a.kdiss = kd;
+  return a;
+}
+
+static int launch_mol(const qd_desc* d, const MolArgs& a, hipStream_t s) {
+  int e = 0;
+  if (a.n_mol == 0) return MSQD_OK;
+  const size_t need = mol_lds_bytes(d->n_r, d->j_max + 1, d->prec);
+  if (need > mol_lds_limit())
+    return fail(MSQD_EUNSUP, "n_r x (j_max+1) too large for one workgroup's LDS in this precision (" +
+                                 std::to_string(need) + " > " + std::to_string(mol_lds_limit()) + " bytes)");
+  switch (d->prec) {
+    case MSQD_FP64: e = launch_mol_fp64(a, d->n_r, s); break;
+    case MSQD_FP32: e = launch_mol_fp32(a, d->n_r, s); break;
+    default: e = launch_mol_mixed(a, d->n_r, s); break;
+  }
+  if (e != 0) return check_hip(static_cast<hipError_t>(e), "molecule step launch");
+  return MSQD_OK;
+}
+
+__global__ void init_psi_kernel(void* psi, int n_mol, int lines, int n_r, const double* psi0,
+                                double* absorbed, int is_f32) {
+  const size_t per = static_cast<size_t>(lines) * n_r;
+  const size_t total = per * n_mol;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t in_mol = t % per;
+    const double v = (in_mol < static_cast<size_t>(n_r)) ? psi0[in_mol] : 0.0;
+    if (is_f32) {
+      reinterpret_cast<float2*>(psi)[t] = make_float2(static_cast<float>(v), 0.0f);
+    } else {
+      reinterpret_cast<double2*>(psi)[t] = make_double2(v, 0.0);
+    }
+    if (in_mol == 0) absorbed[t / per] = 0.0;
+  }
+}
+
+}  // namespace msqd
+
+using namespace msqd;
+
+extern "C" {
+
+const char* msqd_last_error(void) { return g_err.c_str(); }
+int msqd_version(void) { return 100; }
+
+size_t qd_workspace_bytes(const qd_desc* d) {
+  if (check_qd(d) != MSQD_OK) return 0;
+  return qd_layout(d->n_r, d->j_max + 1).total;
+}
+
+int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double* mu12,
+            const double* psi0, void* ws, size_t ws_bytes, void* psi, double* absorbed,
+            void* stream) {
+  int rc = check_qd(d);
+  if (rc) return rc;
+  if (!U_g || !U_e || !mu12 || !psi0) return fail(MSQD_EINVAL, "host table pointer is NULL");
+  if (!ws || !aligned16(ws)) return fail(MSQD_EINVAL, "workspace NULL or misaligned");
+  const QdLayout L = qd_layout(d->n_r, d->j_max + 1);
+  if (ws_bytes < L.total) return fail(MSQD_ESHAPE, "workspace too small");
+  if (d->n_mol > 0 && (!psi || !aligned16(psi) || !absorbed))
+    return fail(MSQD_EINVAL, "psi / absorbed NULL or misaligned");
+  for (int k = 0; k < d->n_r; ++k)
+    if (!std::isfinite(U_g[k]) || !std::isfinite(U_e[k]) || !std::isfinite(mu12[k]) || !std::isfinite(psi0[k]))
+      return fail(MSQD_EINVAL, "non-finite value in the model tables");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  const MolTablesHost t = build_mol_tables(*d, U_g, U_e, mu12);
+  std::vector<unsigned char> host(L.total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
+  const int nr = d->n_r, nj = d->j_max + 1;
+  put(L.psi0, psi0, 8 * nr);
+  put(L.kin_d, t.kin.data(), 16 * nr);
+  put(L.tw_d, t.tw.data(), 16 * nr);
+  put(L.vph_d, t.vph.data(), 16 * t.vph.size());
+  put(L.tm_d, t.tm.data(), 8 * t.tm.size());
+  put(L.x_d, t.x.data(), 8 * nj);
+  put(L.mudt_d, t.mudt.data(), 8 * nr);
+  put(L.mask_d, t.mask.data(), 8 * nr);
+  put(L.mu_d, t.mu.data(), 8 * nr);
+  put(L.cj_d, t.cj.data(), 8 * nj);
+  auto putf = [&](size_t off, const std::vector<double>& v) {
+    float* dst = reinterpret_cast<float*>(host.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) dst[i] = static_cast<float>(v[i]);
+  };
+  auto putcf = [&](size_t off, const std::vector<std::complex<double>>& v) {
+    float* dst = reinterpret_cast<float*>(host.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) {
+      dst[2 * i] = static_cast<float>(v[i].real());
+      dst[2 * i + 1] = static_cast<float>(v[i].imag());
+    }
+  };
+  putcf(L.kin_f, t.kin);
+  putcf(L.tw_f, t.tw);
+  putcf(L.vph_f, t.vph);
+  putf(L.tm_f, t.tm);
+  putf(L.x_f, t.x);
+  putf(L.mudt_f, t.mudt);
+  putf(L.mask_f, t.mask);
+  fill_mfma_fragments(host.data() + L.tmfrag, t.tm, nj);
+
+  MSQD_HIP(hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s));
+  if (d->n_mol > 0) {
+    const int lines = 2 * nj;
+    const size_t total = static_cast<size_t>(lines) * nr * d->n_mol;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(init_psi_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, psi,
+                       d->n_mol, lines, nr,
+                       reinterpret_cast<const double*>(static_cast<char*>(ws) + L.psi0), absorbed,
+                       d->prec == MSQD_FP64 ? 0 : 1);
+    MSQD_HIP(hipGetLastError());
+  }
+  MSQD_HIP(hipStreamSynchronize(s));
+  return MSQD_OK;
+}
+
+int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol, double* absorbed,
+            double* d_mol, int32_t n_steps, void* stream) {
+  int rc = check_qd(d);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(MSQD_EINVAL, "n_steps < 0");
+  if (d->n_mol == 0 || n_steps == 0) return MSQD_OK;
+  if (!ws || !psi || !E_mol || !absorbed) return fail(MSQD_EINVAL, "NULL device pointer");
+  if (!aligned16(ws) || !aligned16(psi)) return fail(MSQD_EINVAL, "misaligned device pointer");
+  MolArgs a = make_mol_args(d, ws);
+  a.n_steps = n_steps;
+  a.psi = psi;
+  a.E_mol = E_mol;
+  a.absorbed = absorbed;
+  a.d_mol = d_mol;
+  a.want_d = d_mol != nullptr;
+  return launch_mol(d, a, static_cast<hipStream_t>(stream));
+}
+
+int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
+                   double* d_mol, double* norm_mol, double* yield_mol, void* stream) {
+  int rc = check_qd(d);
+  if (rc) return rc;
+  if (d->n_mol == 0) return MSQD_OK;
+  if (!ws || !psi || !absorbed) return fail(MSQD_EINVAL, "NULL device pointer");
+  if (!aligned16(ws) || !aligned16(psi)) return fail(MSQD_EINVAL, "misaligned device pointer");
+  MolArgs a = make_mol_args(d, ws);
+  a.n_steps = 0;
+  a.psi = const_cast<void*>(psi);
+  a.E_mol = absorbed;  // unused with n_steps = 0 (any valid pointer)
+  a.absorbed = const_cast<double*>(absorbed);
+  a.d_mol = d_mol;
+  a.norm_mol = norm_mol;
+  a.yield_mol = yield_mol;
+  a.want_d = d_mol != nullptr;
+  a.want_norm = norm_mol != nullptr;
+  a.want_yield = yield_mol != nullptr;
+  return launch_mol(d, a, static_cast<hipStream_t>(stream));
+}
+
+int msqd_check_status(const void* ws, void* stream) {
+  if (!ws) return fail(MSQD_EINVAL, "workspace NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int flag = 0;
+  MSQD_HIP(hipMemcpyAsync(&flag, ws, sizeof(int), hipMemcpyDeviceToHost, s));
+  MSQD_HIP(hipStreamSynchronize(s));
+  if (flag != 0) {
+    const int zero = 0;
+    MSQD_HIP(hipMemcpyAsync(const_cast<void*>(ws), &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    MSQD_HIP(hipStreamSynchronize(s));
+    return fail(MSQD_ENONFINITE, "a molecular step produced a non-finite value");
+  }
+  return MSQD_OK;
+}
+
+// ------------------------------------------------------------------ FDTD
+size_t fdtd_workspace_bytes(const fdtd_desc* d) {
+  if (check_fd(d) != MSQD_OK) return 0;
+  return fd_layout(d).total;
+}
+
+size_t fdtd_psi_bytes(const fdtd_desc* d) {
+  if (check_fd(d) != MSQD_OK) return 0;
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  return 4 * 2 * static_cast<size_t>(d->npml) * d->ny * d->nx * el;
+}
+
+size_t fdtd_dft_bytes(const fdtd_desc* d) {
+  if (check_fd(d) != MSQD_OK) return 0;
+  return 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
+}
+
+static void cpml_profile(const fdtd_desc* d, double offset, std::vector<double>& b,
+                         std::vector<double>& a, std::vector<double>& kinv) {
+  const int nz = d->nz, np = d->npml;
+  b.assign(nz, 1.0);
+  a.assign(nz, 0.0);
+  kinv.assign(nz, 1.0);
+  for (int k = 0; k < nz; ++k) {
+    const double z = k + offset;
+    double depth, smax;
+    if (z < np) {
+      depth = (np - z) / np;
+      smax = d->sigma_max_lo;
+    } else if (z > nz - np) {
+      depth = (z - (nz - np)) / np;
+      smax = d->sigma_max_hi;
+    } else {
+      continue;
+    }
+    const double g = std::pow(depth, d->cpml_m);
+    const double sig = smax * g;
+    const double kap = 1.0 + (d->kappa_max - 1.0) * g;
+    const double al = d->alpha_max * (1.0 - depth);
+    const double bb = std::exp(-(sig / kap + al) * d->dt / kEps0);
+    b[k] = bb;
+    kinv[k] = 1.0 / kap;
+    a[k] = sig > 0.0 ? sig * (bb - 1.0) / (sig * kap + kap * kap * al) : 0.0;
+  }
+}
+
+int fdtd_init(const fdtd_desc* d, const uint8_t* mat_host, const double* freqs,
+              const fdtd_fields* f, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_fd(d);
+  if (rc) return rc;
+  rc = check_fields(d, f);
+  if (rc) return rc;
+  if (!mat_host) return fail(MSQD_EINVAL, "material map is NULL");
+  if (d->n_freq > 0 && !freqs) return fail(MSQD_EINVAL, "monitor frequencies missing");
+  const FdLayout L = fd_layout(d);
+  if (!ws || !aligned16(ws)) return fail(MSQD_EINVAL, "workspace NULL or misaligned");
+  if (ws_bytes < L.total) return fail(MSQD_ESHAPE, "workspace too small");
+  const size_t n = static_cast<size_t>(d->nx) * d->ny * d->nz;
+  for (size_t i = 0; i < 3 * n; ++i)
+    if (mat_host[i] > 3) return fail(MSQD_EINVAL, "material id above 3");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<unsigned char> host(L.total, 0);
+  std::vector<double> b, a, k;
+  auto put = [&](size_t off, const std::vector<double>& v) {
+    std::memcpy(host.data() + off, v.data(), 8 * v.size());
+  };
+  auto putf = [&](size_t off, const std::vector<double>& v) {
+    float* dst = reinterpret_cast<float*>(host.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) dst[i] = static_cast<float>(v[i]);
+  };
+  cpml_profile(d, 0.0, b, a, k);
+  put(L.bE, b); put(L.aE, a); put(L.kE, k);
+  putf(L.bEf, b); putf(L.aEf, a); putf(L.kEf, k);
+  cpml_profile(d, 0.5, b, a, k);
+  put(L.bH, b); put(L.aH, a); put(L.kH, k);
+  putf(L.bHf, b); putf(L.aHf, a); putf(L.kHf, k);
+  if (d->n_freq > 0) std::memcpy(host.data() + L.freqs, freqs, 8 * static_cast<size_t>(d->n_freq));
+  MSQD_HIP(hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s));
+  MSQD_HIP(hipMemcpyAsync(f->mat, mat_host, 3 * n, hipMemcpyHostToDevice, s));
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  void* arrs[] = {f->Ex, f->Ey, f->Ez, f->Hx, f->Hy, f->Hz, f->JDx, f->JDy, f->JDz};
+  for (void* p : arrs) {
+    int e = launch_fill_zero(p, n * el, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "field zero fill");
+  }
+  int e = launch_fill_zero(f->psi, fdtd_psi_bytes(d), s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "CPML zero fill");
+  if (d->n_freq > 0) {
+    e = launch_fill_zero(f->dft, fdtd_dft_bytes(d), s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "monitor zero fill");
+  }
+  MSQD_HIP(hipStreamSynchronize(s));
+  return MSQD_OK;
+}
+
+static int fd_monitor(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t n,
+                      hipStream_t s) {
+  if (d->n_freq <= 0 || (n + 1) % d->mon_every != 0) return MSQD_OK;
+  MonArgs m{};
+  m.nx = d->nx;
+  m.ny = d->ny;
+  m.mon_k = d->mon_k;
+  m.n_freq = d->n_freq;
+  m.tE = static_cast<double>(n + 1) * d->dt;
+  m.tH = (static_cast<double>(n) + 0.5) * d->dt;
+  m.wdt = d->mon_every * d->dt;
+  m.Ex = f->Ex;
+  m.Ey = f->Ey;
+  m.Hx = f->Hx;
+  m.Hy = f->Hy;
+  m.dft = f->dft;
+  m.freqs = reinterpret_cast<const double*>(static_cast<const char*>(ws) + fd_layout(d).freqs);
+  const int e = launch_monitor(m, d->prec != MSQD_FP64, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
+  return MSQD_OK;
+}
+
+int fdtd_step(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t n,
+              double src_value, void* stream) {
+  int rc = check_fd(d);
+  if (rc) return rc;
+  rc = check_fields(d, f);
+  if (rc) return rc;
+  if (!ws) return fail(MSQD_EINVAL, "workspace NULL");
+  if (!std::isfinite(src_value)) return fail(MSQD_EINVAL, "source value not finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FdArgs a = make_fd_args(d, f, ws);
+  a.src_term = -2.0 * src_value / (kEta0 * d->dx);
+  const bool f32 = d->prec != MSQD_FP64;
+  int e = launch_yee_h(a, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
+  e = launch_yee_e(a, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
+  return fd_monitor(d, f, ws, n, s);
+}
+
+int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* stream) {
+  int rc = check_fd(d);
+  if (rc) return rc;
+  if (d->n_freq <= 0) return fail(MSQD_EINVAL, "no monitor frequencies");
+  if (!f || !f->dft || !flux) return fail(MSQD_EINVAL, "NULL pointer");
+  const int e = launch_flux(d->nx, d->ny, d->n_freq, f->dft, flux, static_cast<hipStream_t>(stream));
+  if (e) return check_hip(static_cast<hipError_t>(e), "flux launch");
+  return MSQD_OK;
+}
+
+// --------------------------------------------------------------- coupling
+int map_build(int32_t n_mol, int32_t nx, int32_t ny, int32_t nz, uint64_t seed, int32_t slab_k0,
+              int32_t slab_nk, int32_t* cell_of_mol, int32_t* occ_cell, int32_t* occ_ptr,
+              int32_t* mol_perm, int32_t* n_occ) {
+  if (n_mol < 0 || nx < 1 || ny < 1 || nz < 1) return fail(MSQD_EINVAL, "bad sizes");
+  if (slab_nk < 1 || slab_k0 < 1 || slab_k0 + slab_nk > nz) return fail(MSQD_EINVAL, "slab outside the grid");
+  if (static_cast<double>(nx) * ny * nz > 2.0e9) return fail(MSQD_EUNSUP, "grid too large");
+  if (!cell_of_mol || !occ_cell || !occ_ptr || !mol_perm || !n_occ) return fail(MSQD_EINVAL, "NULL output");
+  place_slab(n_mol, nx, ny, seed, slab_k0, slab_nk, cell_of_mol);
+  *n_occ = build_csr(n_mol, nx * ny * nz, cell_of_mol, occ_cell, occ_ptr, mol_perm);
+  return MSQD_OK;
+}
+
+int map_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t* occ_cell,
+            int32_t* occ_ptr, int32_t* mol_perm, int32_t* n_occ) {
+  if (n_mol < 0 || n_cells < 1) return fail(MSQD_EINVAL, "bad sizes");
+  if (!cell_of_mol || !occ_cell || !occ_ptr || !mol_perm || !n_occ) return fail(MSQD_EINVAL, "NULL pointer");
+  for (int32_t m = 0; m < n_mol; ++m)
+    if (cell_of_mol[m] < 0 || cell_of_mol[m] >= n_cells) return fail(MSQD_EINVAL, "cell index out of range");
+  *n_occ = build_csr(n_mol, n_cells, cell_of_mol, occ_cell, occ_ptr, mol_perm);
+  return MSQD_OK;
+}
+
+int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_values, int64_t n0,
+                 int32_t n_steps, void* stream) {
+  if (!d || !st) return fail(MSQD_EINVAL, "NULL descriptor or state");
+  int rc = check_qd(&d->qd);
+  if (rc) return rc;
+  rc = check_fd(&d->fd);
+  if (rc) return rc;
+  rc = check_fields(&d->fd, &st->f);
+  if (rc) return rc;
+  if (n_steps < 0 || (n_steps > 0 && !src_values)) return fail(MSQD_EINVAL, "bad step count or source");
+  const bool f32 = d->fd.prec != MSQD_FP64;
+  if ((d->qd.prec == MSQD_FP64) != (d->fd.prec == MSQD_FP64))
+    return fail(MSQD_EPREC, "molecule and field precision must both be FP64 or both reduced");
+  if (d->n_occ < 0 || d->n_occ > d->qd.n_mol) return fail(MSQD_ESHAPE, "n_occ out of range");
+  if (d->qd.n_mol > 0 && (!st->psi || !st->absorbed || !st->d_mol || !st->P_c || !st->J_mol ||
+                          !st->cell_of_mol || !st->occ_cell || !st->occ_ptr || !st->mol_perm ||
+                          !st->qd_ws))
+    return fail(MSQD_EINVAL, "NULL coupling pointer");
+  if (!st->fd_ws) return fail(MSQD_EINVAL, "NULL field workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FdArgs fa = make_fd_args(&d->fd, &st->f, st->fd_ws);
+  MolArgs ma = make_mol_args(&d->qd, st->qd_ws);
+  ma.n_steps = 1;
+  ma.psi = st->psi;
+  ma.E_mol = nullptr;
+  ma.Ex = st->f.Ex;
+  ma.ex_is_float = f32 ? 1 : 0;
+  ma.cell_of_mol = st->cell_of_mol;
+  ma.E_out = st->E_mol;
+  ma.absorbed = st->absorbed;
+  ma.d_mol = st->d_mol;
+  ma.want_d = 1;
+  DepArgs da{};
+  da.n_occ = d->n_occ;
+  da.pfac = d->mol_weight * kEa0 / (d->fd.dx * d->fd.dx * d->fd.dx);
+  da.inv_dt = 1.0 / d->fd.dt;
+  for (int m = 0; m < 4; ++m) da.ce[m] = d->fd.dt / (kEps0 * d->fd.eps_r[m]);
+  da.d_mol = st->d_mol;
+  da.occ_cell = st->occ_cell;
+  da.occ_ptr = st->occ_ptr;
+  da.mol_perm = st->mol_perm;
+  da.mat = st->f.mat;
+  da.P_c = st->P_c;
+  da.J_mol = st->J_mol;
+  da.Ex = st->f.Ex;
+  for (int32_t t = 0; t < n_steps; ++t) {
+    const int64_t n = n0 + t;
+    if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
+    fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
+    int e = launch_yee_h(fa, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
+    rc = launch_mol(&d->qd, ma, s);
+    if (rc) return rc;
+    e = launch_yee_e(fa, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
+    e = launch_deposit(da, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
+    if (rc) return rc;
+  }
+  return MSQD_OK;
+}
+
+}  // extern "C"

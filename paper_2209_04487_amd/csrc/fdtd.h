@@ -1,0 +1,59 @@
+// Field solver: workspace layout and launchers.
+#pragma once
+
+#include "common.h"
+
+namespace msqd {
+
+struct FdLayout {
+  size_t bE, aE, kE, bH, aH, kH;      // double [nz] CPML profiles (kE, kH hold 1/kappa)
+  size_t bEf, aEf, kEf, bHf, aHf, kHf; // float [nz]
+  size_t freqs;                        // double [n_freq]
+  size_t total;
+};
+FdLayout fd_layout(const fdtd_desc* d);
+
+struct FdArgs {
+  int nx, ny, nz, npml, metal_id, src_k;
+  double inv_dx, cH;                   // 1/dx, dt/mu0
+  double ce[4];                        // dt/(eps0 eps_r[m])
+  double alpha_d, beta_d;              // Drude recurrence
+  double src_term;                     // -2 E_inc / (eta0 dx) on plane src_k (0: none)
+  void *Ex, *Ey, *Ez, *Hx, *Hy, *Hz, *JDx, *JDy, *JDz, *psi;
+  const uint8_t* mat;
+  const char* ws;
+  FdLayout lay;
+};
+
+int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s);
+int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s);
+
+struct MonArgs {
+  int nx, ny, mon_k, n_freq;
+  double tE, tH, wdt;                  // sample times, weight (every * dt)
+  const void *Ex, *Ey, *Hx, *Hy;
+  double* dft;
+  const double* freqs;
+};
+int launch_monitor(const MonArgs& a, bool f32, hipStream_t s);
+int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hipStream_t s);
+
+struct DepArgs {
+  int n_occ;
+  double pfac;                         // w e a0 / dx^3
+  double inv_dt;
+  double ce[4];
+  const double* d_mol;
+  const int* occ_cell;
+  const int* occ_ptr;
+  const int* mol_perm;
+  const uint8_t* mat;                  // E_x material ids
+  double* P_c;
+  double* J_mol;
+  void* Ex;
+};
+int launch_deposit(const DepArgs& a, bool f32, hipStream_t s);
+
+int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace msqd

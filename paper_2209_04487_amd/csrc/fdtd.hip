@@ -1,0 +1,312 @@
+// Yee leap-frog of Eq. (1) with the Drude current of Eq. (2), CPML along z,
+// periodic x/y, soft current-sheet source, detection-plane DFT, and the
+// per-cell polarisation current deposit of the molecules.
+//
+// Each update is a bandwidth-bound stencil: one lane per cell, x fastest so
+// that neighbouring lanes touch neighbouring addresses; the +-1 neighbours in
+// y and z come from cache.
+#include "fdtd.h"
+
+namespace msqd {
+
+template <typename T>
+struct FdPtr {
+  T *Ex, *Ey, *Ez, *Hx, *Hy, *Hz, *JDx, *JDy, *JDz, *psi;
+};
+
+template <typename T>
+__device__ __forceinline__ FdPtr<T> fd_ptrs(const FdArgs& a) {
+  return {static_cast<T*>(a.Ex),  static_cast<T*>(a.Ey),  static_cast<T*>(a.Ez),
+          static_cast<T*>(a.Hx),  static_cast<T*>(a.Hy),  static_cast<T*>(a.Hz),
+          static_cast<T*>(a.JDx), static_cast<T*>(a.JDy), static_cast<T*>(a.JDz),
+          static_cast<T*>(a.psi)};
+}
+
+// plane index of k inside the CPML auxiliary arrays, or -1 outside the layers
+__device__ __forceinline__ int pml_plane(int k, int nz, int npml) {
+  if (k < npml) return k;
+  if (k >= nz - npml) return npml + (k - (nz - npml));
+  return -1;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* prof(const FdArgs& a, size_t off_d, size_t off_f) {
+  if constexpr (sizeof(T) == 8)
+    return reinterpret_cast<const T*>(a.ws + off_d);
+  else
+    return reinterpret_cast<const T*>(a.ws + off_f);
+}
+
+// H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n, with the CPML stretching of the
+// z derivatives: d/dz -> (1/kappa) d/dz + psi, psi <- b psi + a d/dz.
+template <typename T>
+__global__ __launch_bounds__(256) void yee_h_kernel(FdArgs a) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = static_cast<int>(idx % nx);
+  const long jk = idx / nx;
+  const int j = static_cast<int>(jk % ny);
+  const int k = static_cast<int>(jk / ny);
+  const long sx = 1, sy = nx, sz = static_cast<long>(nx) * ny;
+  const long ip = (i + 1 == nx) ? idx - (nx - 1) * sx : idx + sx;
+  const long jp = (j + 1 == ny) ? idx - static_cast<long>(ny - 1) * sy : idx + sy;
+  FdPtr<T> f = fd_ptrs<T>(a);
+  const T inv_dx = static_cast<T>(a.inv_dx);
+  const T cH = static_cast<T>(a.cH);
+
+  const T ex = f.Ex[idx], ey = f.Ey[idx], ez = f.Ez[idx];
+  const T ex_kp = (k + 1 < nz) ? f.Ex[idx + sz] : T(0);
+  const T ey_kp = (k + 1 < nz) ? f.Ey[idx + sz] : T(0);
+  const T dEz_dy = (f.Ez[jp] - ez) * inv_dx;
+  const T dEz_dx = (f.Ez[ip] - ez) * inv_dx;
+  T dEy_dz = (ey_kp - ey) * inv_dx;
+  T dEx_dz = (ex_kp - ex) * inv_dx;
+  const T dEy_dx = (f.Ey[ip] - ey) * inv_dx;
+  const T dEx_dy = (f.Ex[jp] - ex) * inv_dx;
+
+  const int kk = pml_plane(k, nz, a.npml);
+  if (kk >= 0) {
+    const T b = prof<T>(a, a.lay.bH, a.lay.bHf)[k];
+    const T c = prof<T>(a, a.lay.aH, a.lay.aHf)[k];
+    const T ki = prof<T>(a, a.lay.kH, a.lay.kHf)[k];
+    const long plane = static_cast<long>(nx) * ny;
+    const long np = 2L * a.npml * plane;
+    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    T* psiHx = f.psi + 2 * np;
+    T* psiHy = f.psi + 3 * np;
+    const T phx = b * psiHx[o] + c * dEy_dz;
+    const T phy = b * psiHy[o] + c * dEx_dz;
+    psiHx[o] = phx;
+    psiHy[o] = phy;
+    dEy_dz = dEy_dz * ki + phx;
+    dEx_dz = dEx_dz * ki + phy;
+  }
+  f.Hx[idx] -= cH * (dEz_dy - dEy_dz);
+  f.Hy[idx] -= cH * (dEx_dz - dEz_dx);
+  f.Hz[idx] -= cH * (dEy_dx - dEx_dy);
+}
+
+// Drude current (centred form of Eq. (2)) and
+// E^{n+1} = E^n + dt/(eps0 eps_r) [curl H^{n+1/2} - J_D^{n+1/2} - J_src].
+// E_x, E_y at k = 0 stay zero (the grid ends on tangential E = 0).
+template <typename T>
+__global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = static_cast<int>(idx % nx);
+  const long jk = idx / nx;
+  const int j = static_cast<int>(jk % ny);
+  const int k = static_cast<int>(jk / ny);
+  const long sx = 1, sy = nx, sz = static_cast<long>(nx) * ny;
+  const long im = (i == 0) ? idx + (nx - 1) * sx : idx - sx;
+  const long jm = (j == 0) ? idx + static_cast<long>(ny - 1) * sy : idx - sy;
+  FdPtr<T> f = fd_ptrs<T>(a);
+  const T inv_dx = static_cast<T>(a.inv_dx);
+
+  const T hx = f.Hx[idx], hy = f.Hy[idx], hz = f.Hz[idx];
+  const T hx_km = (k > 0) ? f.Hx[idx - sz] : T(0);
+  const T hy_km = (k > 0) ? f.Hy[idx - sz] : T(0);
+  const T dHz_dy = (hz - f.Hz[jm]) * inv_dx;
+  const T dHz_dx = (hz - f.Hz[im]) * inv_dx;
+  T dHy_dz = (hy - hy_km) * inv_dx;
+  T dHx_dz = (hx - hx_km) * inv_dx;
+  const T dHy_dx = (hy - f.Hy[im]) * inv_dx;
+  const T dHx_dy = (hx - f.Hx[jm]) * inv_dx;
+
+  const int kk = pml_plane(k, nz, a.npml);
+  if (kk >= 0) {
+    const T b = prof<T>(a, a.lay.bE, a.lay.bEf)[k];
+    const T c = prof<T>(a, a.lay.aE, a.lay.aEf)[k];
+    const T ki = prof<T>(a, a.lay.kE, a.lay.kEf)[k];
+    const long plane = static_cast<long>(nx) * ny;
+    const long np = 2L * a.npml * plane;
+    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    T* psiEx = f.psi;
+    T* psiEy = f.psi + np;
+    const T pex = b * psiEx[o] + c * dHy_dz;
+    const T pey = b * psiEy[o] + c * dHx_dz;
+    psiEx[o] = pex;
+    psiEy[o] = pey;
+    dHy_dz = dHy_dz * ki + pex;
+    dHx_dz = dHx_dz * ki + pey;
+  }
+  const T curl[3] = {dHz_dy - dHy_dz, dHx_dz - dHz_dx, dHy_dx - dHx_dy};
+  T* E[3] = {f.Ex, f.Ey, f.Ez};
+  T* JD[3] = {f.JDx, f.JDy, f.JDz};
+  const uint8_t* mat = a.mat;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int m = mat[c * n + idx];
+    const T e0 = E[c][idx];
+    T J = T(0);
+    if (m == a.metal_id) {
+      const T jd = static_cast<T>(a.alpha_d) * JD[c][idx] + static_cast<T>(a.beta_d) * e0;
+      JD[c][idx] = jd;
+      J = jd;
+    }
+    if (c == 0 && k == a.src_k) J += static_cast<T>(a.src_term);
+    T e1 = e0 + static_cast<T>(a.ce[m & 3]) * (curl[c] - J);
+    if (c < 2 && k == 0) e1 = T(0);
+    E[c][idx] = e1;
+  }
+}
+
+int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s) {
+  const long n = static_cast<long>(a.nx) * a.ny * a.nz;
+  const int blocks = static_cast<int>((n + 255) / 256);
+  if (f32)
+    hipLaunchKernelGGL(yee_h_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(yee_h_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s) {
+  const long n = static_cast<long>(a.nx) * a.ny * a.nz;
+  const int blocks = static_cast<int>((n + 255) / 256);
+  if (f32)
+    hipLaunchKernelGGL(yee_e_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(yee_e_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+// ------------------------------------------------------------- monitor
+// dft layout [4][n_freq][ny][nx] complex128: E_x, E_y at t_E, and H_x, H_y
+// averaged over the planes mon_k -+ 1/2 at t_H.
+template <typename T>
+__global__ __launch_bounds__(256) void monitor_kernel(MonArgs a) {
+  extern __shared__ double ph[];  // [n_freq][4]: cos tE, sin tE, cos tH, sin tH
+  for (int f = threadIdx.x; f < a.n_freq; f += blockDim.x) {
+    double s, c;
+    sincos(a.freqs[f] * a.tE, &s, &c);
+    ph[4 * f + 0] = c * a.wdt;
+    ph[4 * f + 1] = s * a.wdt;
+    sincos(a.freqs[f] * a.tH, &s, &c);
+    ph[4 * f + 2] = c * a.wdt;
+    ph[4 * f + 3] = s * a.wdt;
+  }
+  __syncthreads();
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const long p = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= plane) return;
+  const long o = static_cast<long>(a.mon_k) * plane + p;
+  const double ex = static_cast<const T*>(a.Ex)[o];
+  const double ey = static_cast<const T*>(a.Ey)[o];
+  const double hx = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hx)[o - plane]) +
+                           static_cast<const T*>(a.Hx)[o]);
+  const double hy = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hy)[o - plane]) +
+                           static_cast<const T*>(a.Hy)[o]);
+  const double val[4] = {ex, ey, hx, hy};
+  double2* acc = reinterpret_cast<double2*>(a.dft);
+  for (int f = 0; f < a.n_freq; ++f) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double cw = ph[4 * f + (c < 2 ? 0 : 2)];
+      const double sw = ph[4 * f + (c < 2 ? 1 : 3)];
+      const long q = (static_cast<long>(c) * a.n_freq + f) * plane + p;
+      double2 z = acc[q];
+      z.x += val[c] * cw;
+      z.y += val[c] * sw;
+      acc[q] = z;
+    }
+  }
+}
+
+int launch_monitor(const MonArgs& a, bool f32, hipStream_t s) {
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const int blocks = static_cast<int>((plane + 255) / 256);
+  const size_t shm = sizeof(double) * 4 * static_cast<size_t>(a.n_freq);
+  if (f32)
+    hipLaunchKernelGGL(monitor_kernel<float>, dim3(blocks), dim3(256), shm, s, a);
+  else
+    hipLaunchKernelGGL(monitor_kernel<double>, dim3(blocks), dim3(256), shm, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+// one workgroup per frequency; fixed-order tree sum over the plane
+__global__ __launch_bounds__(256) void flux_kernel(int plane, int n_freq, const double2* dft,
+                                                   double* flux) {
+  __shared__ double red[256];
+  const int f = blockIdx.x;
+  const double2* Ex = dft + (0L * n_freq + f) * plane;
+  const double2* Ey = dft + (1L * n_freq + f) * plane;
+  const double2* Hx = dft + (2L * n_freq + f) * plane;
+  const double2* Hy = dft + (3L * n_freq + f) * plane;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < plane; p += blockDim.x) {
+    // 1/2 Re(Ex conj(Hy) - Ey conj(Hx))
+    s += 0.5 * ((Ex[p].x * Hy[p].x + Ex[p].y * Hy[p].y) - (Ey[p].x * Hx[p].x + Ey[p].y * Hx[p].y));
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flux[f] = red[0] / plane;
+}
+
+int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hipStream_t s) {
+  hipLaunchKernelGGL(flux_kernel, dim3(n_freq), dim3(256), 0, s, nx * ny, n_freq,
+                     reinterpret_cast<const double2*>(dft), flux);
+  return static_cast<int>(hipGetLastError());
+}
+
+// ------------------------------------------------- polarisation current
+// Per occupied cell: P^{n+1} = (w e a0 / dx^3) sum_{i in cell} d_i in CSR
+// order, J = (P^{n+1} - P^n)/dt, and E_x at the cell loses dt/(eps0 eps_r) J.
+template <typename T>
+__global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_occ) return;
+  double s = 0.0;
+  const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
+  for (int t = b; t < e; ++t) s += a.d_mol[a.mol_perm[t]];
+  const double p_new = s * a.pfac;
+  const double J = (p_new - a.P_c[c]) * a.inv_dt;
+  a.P_c[c] = p_new;
+  a.J_mol[c] = J;
+  const int cell = a.occ_cell[c];
+  const int m = a.mat[cell] & 3;
+  T* Ex = static_cast<T*>(a.Ex);
+  Ex[cell] = Ex[cell] - static_cast<T>(a.ce[m] * J);
+}
+
+int launch_deposit(const DepArgs& a, bool f32, hipStream_t s) {
+  if (a.n_occ <= 0) return 0;
+  const int blocks = (a.n_occ + 255) / 256;
+  if (f32)
+    hipLaunchKernelGGL(deposit_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(deposit_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+// ------------------------------------------------------------- zero fill
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4* p, size_t n16, unsigned char* tail,
+                                                        size_t ntail) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t t = i; t < n16; t += stride) p[t] = make_uint4(0, 0, 0, 0);
+  if (i < ntail) tail[i] = 0;
+}
+
+int launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return 0;
+  const size_t n16 = bytes / 16;
+  unsigned char* tail = static_cast<unsigned char*>(p) + n16 * 16;
+  const size_t ntail = bytes - n16 * 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(p), n16, tail, ntail);
+  return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace msqd

@@ -1,0 +1,156 @@
+// Host-side construction of the molecular tables and of the molecule->cell
+// maps.  Everything here runs once per init call.
+#include "host_tables.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
+namespace msqd {
+
+// Legendre P_0..P_n at x by the three-term recurrence
+// (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}.
+static void legendre_all(int n, double x, double* p) {
+  p[0] = 1.0;
+  if (n >= 1) p[1] = x;
+  for (int k = 1; k < n; ++k) p[k + 1] = ((2.0 * k + 1.0) * x * p[k] - k * p[k - 1]) / (k + 1.0);
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  // Newton iteration on P_n from the Chebyshev-like first guess; nodes are
+  // symmetric, so the negative half is mirrored and x = 0 is exact for odd n.
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  std::vector<double> p(n + 1);
+  const int half = n / 2;
+  for (int i = 0; i < half; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      legendre_all(n, z, p.data());
+      const double dp = n * (z * p[n] - p[n - 1]) / (z * z - 1.0);
+      const double dz = p[n] / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    legendre_all(n, z, p.data());
+    const double dp = n * (z * p[n] - p[n - 1]) / (z * z - 1.0);
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    // ascending order: x[n-1-i] = +z (largest first guess), x[i] = -z
+    x[n - 1 - i] = z;
+    x[i] = -z;
+    w[n - 1 - i] = wi;
+    w[i] = wi;
+  }
+  if (n & 1) {
+    legendre_all(n, 0.0, p.data());
+    const double dp = n * (-p[n - 1]) / (-1.0);  // n (x P_n - P_{n-1})/(x^2 - 1) at x = 0
+    x[half] = 0.0;
+    w[half] = 2.0 / (dp * dp);
+  }
+}
+
+MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
+                               const double* mu12) {
+  MolTablesHost t;
+  const int nr = d.n_r, nj = d.j_max + 1;
+  const double dr = (d.r_max - d.r_min) / nr;
+  const double dt = d.dt_au, mass = d.mass_au;
+  t.dr = dr;
+  t.kin.resize(nr);
+  t.tw.resize(nr);
+  for (int m = 0; m < nr; ++m) {
+    const int ms = (m < nr / 2) ? m : m - nr;
+    const double kap = 2.0 * kPi * ms / (nr * dr);
+    const double ph = -kap * kap * dt / (4.0 * mass);
+    t.kin[m] = std::polar(1.0 / nr, ph);
+    t.tw[m] = std::polar(1.0, -2.0 * kPi * m / nr);
+  }
+  t.vph.resize(static_cast<size_t>(2) * nj * nr);
+  for (int s = 0; s < 2; ++s) {
+    const double* U = (s == 0) ? U_g : U_e;
+    for (int J = 0; J < nj; ++J) {
+      for (int k = 0; k < nr; ++k) {
+        const double r = d.r_min + k * dr;
+        const double V = U[k] + J * (J + 1.0) / (2.0 * mass * r * r);
+        t.vph[(static_cast<size_t>(s) * nj + J) * nr + k] = std::polar(1.0, -V * dt / 2.0);
+      }
+    }
+  }
+  std::vector<double> x, w;
+  gauss_legendre(nj, x, w);
+  t.x = x;
+  t.tm.assign(static_cast<size_t>(nj) * nj, 0.0);
+  std::vector<double> p(nj + 1);
+  for (int k = 0; k < nj; ++k) {
+    legendre_all(nj, x[k], p.data());
+    for (int J = 0; J < nj; ++J)
+      t.tm[static_cast<size_t>(k) * nj + J] = std::sqrt(w[k]) * std::sqrt((2.0 * J + 1.0) / 2.0) * p[J];
+  }
+  t.mudt.resize(nr);
+  t.mu.resize(nr);
+  t.mask.assign(nr, 1.0);
+  const double ra = d.r_max - d.absorb_width_au;
+  t.kdiss = nr;
+  for (int k = 0; k < nr; ++k) {
+    const double r = d.r_min + k * dr;
+    t.mu[k] = mu12[k];
+    t.mudt[k] = mu12[k] * dt;
+    if (d.absorb_width_au > 0.0 && r >= ra)
+      t.mask[k] = std::pow(std::cos(kPi * (r - ra) / (2.0 * d.absorb_width_au)), 0.125);
+    if (r > d.r_diss_au && t.kdiss == nr) t.kdiss = k;
+  }
+  t.cj.assign(nj, 0.0);
+  for (int J = 0; J + 1 < nj; ++J)
+    t.cj[J] = (J + 1.0) / std::sqrt((2.0 * J + 1.0) * (2.0 * J + 3.0));
+  return t;
+}
+
+// ------------------------------------------------------------------ maps
+namespace {
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+inline int32_t scale_index(uint64_t u, int32_t n) {
+  const unsigned __int128 prod = static_cast<unsigned __int128>(u >> 11) * static_cast<uint64_t>(n);
+  return static_cast<int32_t>(prod >> 53);
+}
+}  // namespace
+
+void place_slab(int32_t n_mol, int32_t nx, int32_t ny, uint64_t seed, int32_t k0, int32_t nk,
+                int32_t* cell_of_mol) {
+  SplitMix64 g{seed};
+  for (int32_t m = 0; m < n_mol; ++m) {
+    const uint64_t ux = g.next(), uy = g.next(), uz = g.next();
+    const int64_t i = scale_index(ux, nx), j = scale_index(uy, ny), k = k0 + scale_index(uz, nk);
+    cell_of_mol[m] = static_cast<int32_t>((k * ny + j) * nx + i);
+  }
+}
+
+int32_t build_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t* occ_cell,
+                  int32_t* occ_ptr, int32_t* mol_perm) {
+  // stable counting sort by cell
+  std::vector<int32_t> count(static_cast<size_t>(n_cells) + 1, 0);
+  for (int32_t m = 0; m < n_mol; ++m) count[cell_of_mol[m] + 1]++;
+  for (int32_t c = 0; c < n_cells; ++c) count[c + 1] += count[c];
+  std::vector<int32_t> pos(count.begin(), count.end() - 1);
+  for (int32_t m = 0; m < n_mol; ++m) mol_perm[pos[cell_of_mol[m]]++] = m;
+  int32_t n_occ = 0;
+  for (int32_t c = 0; c < n_cells; ++c) {
+    if (count[c + 1] > count[c]) {
+      occ_cell[n_occ] = c;
+      occ_ptr[n_occ] = count[c];
+      ++n_occ;
+    }
+  }
+  occ_ptr[n_occ] = n_mol;
+  return n_occ;
+}
+
+}  // namespace msqd

@@ -1,0 +1,34 @@
+// Host-side table and map builders.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#include "common.h"
+
+namespace msqd {
+
+struct MolTablesHost {
+  double dr = 0.0;
+  int kdiss = 0;
+  std::vector<std::complex<double>> kin, tw, vph;
+  std::vector<double> tm, x, mudt, mask, mu, cj;
+};
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
+                               const double* mu12);
+
+void place_slab(int32_t n_mol, int32_t nx, int32_t ny, uint64_t seed, int32_t k0, int32_t nk,
+                int32_t* cell_of_mol);
+int32_t build_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t* occ_cell,
+                  int32_t* occ_ptr, int32_t* mol_perm);
+
+}  // namespace msqd
+
+namespace msqd {
+// J<->angle matrix in matrix-core operand order, bf16 hi and lo parts
+// (used by the mixed-precision molecular step).
+void fill_mfma_fragments(unsigned char* dst, const std::vector<double>& tm, int nj);
+}  // namespace msqd

@@ -1,0 +1,637 @@
+// Fused molecular step for one molecule per workgroup.
+//
+// One split-operator step (K/2 V/2 C(E) V/2 K/2, absorber) of the two-state
+// wavepacket of Eqs. (3)-(5), with the angular part of the coupling in Eq. (4)
+// integrated on the Gauss-Legendre angular grid.  The whole molecule stays on
+// chip for the step (and for every step of a multi-step call): psi crosses
+// HBM once in each direction.
+//
+// Work decomposition inside the workgroup
+//   line layout : line (s, J) is owned by R2 consecutive lanes; lane q holds
+//                 r = q + R2 p, p = 0..R1-1 (n_r = R1 R2) in registers.
+//                 K/2 = two in-register DFT passes with an LDS transpose in
+//                 between (four-step FFT), kinetic phase, and the inverse.
+//                 All exchanges of a line stay inside one wavefront.
+//   r layout    : one lane per radial point holds all (s, J) of that point
+//                 (read from the line slots in LDS): J <-> angle transform,
+//                 per-node 2x2 rotation, readouts.
+#pragma once
+
+#include "fft_reg.h"
+#include "mol.h"
+
+namespace msqd {
+
+template <int NR>
+struct FftShape;
+template <>
+struct FftShape<64> { static constexpr int R1 = 8, R2 = 8; };
+template <>
+struct FftShape<128> { static constexpr int R1 = 16, R2 = 8; };
+template <>
+struct FftShape<256> { static constexpr int R1 = 16, R2 = 16; };
+template <>
+struct FftShape<512> { static constexpr int R1 = 32, R2 = 16; };
+
+template <int NR>
+constexpr int line_stride() { return NR + FftShape<NR>::R2; }
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hide a uniform pointer's value from the optimiser so that table loads stay
+// inside the step loop instead of being hoisted into (many) live registers.
+template <typename P>
+__device__ __forceinline__ P* opaque(P* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+template <typename T>
+struct MolTabs {
+  const cx<T>* kin;
+  const cx<T>* tw;
+  const cx<T>* vph;
+  const T* tm;
+  const T* x;
+  const T* mudt;
+  const T* mask;
+  const double* mu;
+  const double* cj;
+};
+
+// ---------------------------------------------------------------- K/2
+// v: this lane's R1 values of its line (r = q + R2 p); slot: the line's LDS
+// region (R2 * (R1 + 1) elements).  kin already carries the 1/NR of the
+// inverse transform.
+template <typename T, int NR>
+__device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* kin,
+                                             const cx<T>* tw) {
+  constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2, U = R1 / R2, RS = R1 + 1;
+  // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
+  dft<R1, false, T>(v);
+#pragma unroll
+  for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw[(q * a) & (NR - 1)]);
+#pragma unroll
+  for (int a = 0; a < R1; ++a) slot[q * RS + a] = v[a];
+  wave_lds_sync();
+  // pass 2 on the transposed data: frequency k = a + R1 b
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int a = q + R2 * u;
+    cx<T>* w = v + u * R2;
+#pragma unroll
+    for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + a];
+    dft<R2, false, T>(w);
+#pragma unroll
+    for (int b = 0; b < R2; ++b) w[b] = cmul(w[b], kin[a + R1 * b]);
+    dft<R2, true, T>(w);
+#pragma unroll
+    for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw[(qq * a) & (NR - 1)]);
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int a = q + R2 * u;
+#pragma unroll
+    for (int qq = 0; qq < R2; ++qq) slot[qq * RS + a] = v[u * R2 + qq];
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int a = 0; a < R1; ++a) v[a] = slot[q * RS + a];
+  dft<R1, true, T>(v);
+  wave_lds_sync();
+}
+
+// -------------------------------------------------------------- C(E)
+// sin(a) and 1 - cos(a).  The coupling angle per step is small in practice:
+// for |a| < 1/32 the Taylor series of sin and of 1 - cos = 2 sin^2(a/2) are
+// summed directly (truncation below 1e-18 relative, and no cancellation in
+// 1 - cos); larger angles take an out-of-line path through the library
+// sine/cosine.
+__device__ __noinline__ void sin_vers_large(double a, double* s, double* v) {
+  double c;
+  sincos(a, s, &c);
+  const double h = sin(0.5 * a);
+  *v = 2.0 * h * h;
+}
+__device__ __noinline__ void sin_vers_large(float a, float* s, float* v) {
+  float c;
+  sincosf(a, s, &c);
+  const float h = sinf(0.5f * a);
+  *v = 2.0f * h * h;
+}
+__device__ __forceinline__ void sin_vers(double a, double* s, double* v) {
+  if (fabs(a) < 0.03125) {
+    const double a2 = a * a;
+    // sin a = a (1 - a^2/3! + a^4/5! - a^6/7! + a^8/9!)
+    double ps = 1.0 / 362880.0;
+    ps = ps * a2 - 1.0 / 5040.0;
+    ps = ps * a2 + 1.0 / 120.0;
+    ps = ps * a2 - 1.0 / 6.0;
+    *s = a + a * a2 * ps;
+    // 1 - cos a = a^2/2! - a^4/4! + a^6/6! - a^8/8! + a^10/10!
+    double pc = 1.0 / 3628800.0;
+    pc = pc * a2 - 1.0 / 40320.0;
+    pc = pc * a2 + 1.0 / 720.0;
+    pc = pc * a2 - 1.0 / 24.0;
+    pc = pc * a2 + 0.5;
+    *v = a2 * pc;
+  } else {
+    sin_vers_large(a, s, v);
+  }
+}
+__device__ __forceinline__ void sin_vers(float a, float* s, float* v) {
+  if (fabsf(a) < 0.125f) {
+    const float a2 = a * a;
+    float ps = 1.0f / 362880.0f;
+    ps = ps * a2 - 1.0f / 5040.0f;
+    ps = ps * a2 + 1.0f / 120.0f;
+    ps = ps * a2 - 1.0f / 6.0f;
+    *s = a + a * a2 * ps;
+    float pc = 1.0f / 3628800.0f;
+    pc = pc * a2 - 1.0f / 40320.0f;
+    pc = pc * a2 + 1.0f / 720.0f;
+    pc = pc * a2 - 1.0f / 24.0f;
+    pc = pc * a2 + 0.5f;
+    *v = a2 * pc;
+  } else {
+    sin_vers_large(a, s, v);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void rotate(cx<T>& g, cx<T>& e, T c, T s) {
+  // [g, e] <- [c g + i s e, i s g + c e]
+  const cx<T> g0 = g, e0 = e;
+  g = {c * g0.x - s * e0.y, c * g0.y + s * e0.x};
+  e = {c * e0.x - s * g0.y, c * e0.y + s * g0.x};
+}
+
+// Exact exp(-i H_int dt) at radial point r on the truncated J basis:
+// Phi = T psi (J -> Gauss-Legendre nodes), per-node rotation by
+// phi_k = mu12(r) x_k E dt, psi = T^T Phi.  The nodes are symmetric
+// (x_{n-1-k} = -x_k, T[n-1-k][J] = (-1)^J T[k][J]), so with
+// u_k = sum_{J even} T[k][J] psi_J and w_k = sum_{J odd} T[k][J] psi_J the
+// node pair (k, n-1-k) holds u + w and u - w, rotated by +phi and -phi.
+// Folding the pair back gives, per state pair (g, e) with sigma_x swapping
+// them:  even J <- 2 sum_k T[k][J] (c u + i s sigma_x w),
+//        odd J  <- 2 sum_k T[k][J] (c w + i s sigma_x u),
+// plus the middle node (x = 0, odd n) which is not rotated.  Even and odd
+// parts are streamed separately to keep few values live.
+template <typename T, int NJ>
+__device__ __forceinline__ void coupling_point(cx<T>* sh, int LS, int r, const T* __restrict__ tm,
+                                               const T* __restrict__ x, T md) {
+  constexpr int KH = NJ / 2;           // mirrored node pairs
+  constexpr bool MID = (NJ & 1) != 0;  // middle node x = 0
+  constexpr int KE = KH + (MID ? 1 : 0);
+  constexpr int NE = (NJ + 1) / 2, NO = NJ / 2;
+  cx<T> ug[KE > 0 ? KE : 1], ue[KE > 0 ? KE : 1];
+  cx<T> wg[KH > 0 ? KH : 1], we[KH > 0 ? KH : 1];
+  {
+    cx<T> g[NE], e[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      g[i] = sh[(2 * i) * LS + r];
+      e[i] = sh[(NJ + 2 * i) * LS + r];
+    }
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      cx<T> ag = {0, 0}, ae = {0, 0};
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const T t = tm[k * NJ + 2 * i];
+        ag = ag + cscale(g[i], t);
+        ae = ae + cscale(e[i], t);
+      }
+      ug[k] = ag;
+      ue[k] = ae;
+    }
+  }
+  if constexpr (NO > 0) {
+    cx<T> g[NO > 0 ? NO : 1], e[NO > 0 ? NO : 1];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      g[i] = sh[(2 * i + 1) * LS + r];
+      e[i] = sh[(NJ + 2 * i + 1) * LS + r];
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      cx<T> ag = {0, 0}, ae = {0, 0};
+#pragma unroll
+      for (int i = 0; i < NO; ++i) {
+        const T t = tm[k * NJ + 2 * i + 1];
+        ag = ag + cscale(g[i], t);
+        ae = ae + cscale(e[i], t);
+      }
+      wg[k] = ag;
+      we[k] = ae;
+    }
+  }
+  // rotate and fold the mirror pairs
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    T sn, vs;
+    sin_vers(md * x[k], &sn, &vs);
+    const T c = T(1) - vs;
+    const cx<T> a_g = {c * ug[k].x - sn * we[k].y, c * ug[k].y + sn * we[k].x};
+    const cx<T> a_e = {c * ue[k].x - sn * wg[k].y, c * ue[k].y + sn * wg[k].x};
+    const cx<T> b_g = {c * wg[k].x - sn * ue[k].y, c * wg[k].y + sn * ue[k].x};
+    const cx<T> b_e = {c * we[k].x - sn * ug[k].y, c * we[k].y + sn * ug[k].x};
+    ug[k] = a_g;
+    ue[k] = a_e;
+    wg[k] = b_g;
+    we[k] = b_e;
+  }
+  // back to J
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int J = 2 * i;
+    cx<T> ag = {0, 0}, ae = {0, 0};
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const T t = T(2) * tm[k * NJ + J];
+      ag = ag + cscale(ug[k], t);
+      ae = ae + cscale(ue[k], t);
+    }
+    if (MID) {
+      const T t = tm[KH * NJ + J];
+      ag = ag + cscale(ug[KE - 1], t);
+      ae = ae + cscale(ue[KE - 1], t);
+    }
+    sh[J * LS + r] = ag;
+    sh[(NJ + J) * LS + r] = ae;
+  }
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int J = 2 * i + 1;
+    cx<T> ag = {0, 0}, ae = {0, 0};
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const T t = T(2) * tm[k * NJ + J];
+      ag = ag + cscale(wg[k], t);
+      ae = ae + cscale(we[k], t);
+    }
+    sh[J * LS + r] = ag;
+    sh[(NJ + J) * LS + r] = ae;
+  }
+}
+
+template <typename T, int NJ>
+__device__ __forceinline__ void coupling_all(cx<T>* sh, int LS, int NR, int tid, int nthr,
+                                          const T* __restrict__ tm, const T* __restrict__ x,
+                                          const T* __restrict__ mudt, T E) {
+#pragma unroll 1
+  for (int r = tid; r < NR; r += nthr)
+    coupling_point<T, NJ>(sh, LS, r, opaque(tm), opaque(x), mudt[r] * E);
+}
+
+template <typename T>
+__device__ __forceinline__ void coupling_dispatch(int nj, cx<T>* sh, int LS, int NR, int tid,
+                                                  int nthr, const T* tm, const T* x,
+                                                  const T* mudt, T E) {
+  switch (nj) {
+#define MSQD_CASE(n) \
+  case n: coupling_all<T, n>(sh, LS, NR, tid, nthr, tm, x, mudt, E); break;
+    MSQD_CASE(1) MSQD_CASE(2) MSQD_CASE(3) MSQD_CASE(4) MSQD_CASE(5) MSQD_CASE(6)
+    MSQD_CASE(7) MSQD_CASE(8) MSQD_CASE(9) MSQD_CASE(10) MSQD_CASE(11) MSQD_CASE(12)
+    MSQD_CASE(13) MSQD_CASE(14) MSQD_CASE(15) MSQD_CASE(16)
+#undef MSQD_CASE
+    default: break;
+  }
+}
+
+
+// ----------------------------------------------- C(E) on the matrix cores
+// Mixed form: psi += T^T (R - I) T psi over the J axis, per radial point, as
+// 16x16x16 BF16 matrix-core products with FP32 accumulation.  Both operands
+// are split into bf16 hi + lo parts and three products are kept
+// (hi*hi + hi*lo + lo*hi).  The increment form keeps the large identity part
+// of the step exact in FP32; only the small rotation increment goes through
+// bf16.  One wavefront handles 16 radial points: lane l works on radial point
+// r0 + l%16 and J (or node) rows 4(l/16) .. 4(l/16)+3, which is the operand
+// layout of the 16x16x16 instruction, so the forward product's output is
+// directly the inverse product's B operand.
+typedef short mf_short4 __attribute__((ext_vector_type(4)));
+typedef float mf_float4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const __bf16 h = static_cast<__bf16>(x);
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __uint_as_float(static_cast<unsigned int>(b) << 16);
+}
+__device__ __forceinline__ void split4(const float* v, mf_short4& hi, mf_short4& lo) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned short h = bf16_rne(v[i]);
+    hi[i] = static_cast<short>(h);
+    lo[i] = static_cast<short>(bf16_rne(v[i] - bf16_val(h)));
+  }
+}
+__device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short4 bhi,
+                                         mf_short4 blo, mf_float4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
+  return c;
+}
+
+// frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16
+__device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int nj,
+                                           const unsigned short* __restrict__ frag,
+                                           const float* __restrict__ x,
+                                           const float* __restrict__ mudt, float E) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+  const int col = lane & 15;
+  const int rb = (lane >> 4) * 4;  // first J (inputs) / node (outputs) row of this lane
+  mf_short4 Ahi, Alo, Bthi, Btlo;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    Ahi[i] = static_cast<short>(frag[(0 * 64 + lane) * 4 + i]);
+    Alo[i] = static_cast<short>(frag[(1 * 64 + lane) * 4 + i]);
+    Bthi[i] = static_cast<short>(frag[(2 * 64 + lane) * 4 + i]);
+    Btlo[i] = static_cast<short>(frag[(3 * 64 + lane) * 4 + i]);
+  }
+  float xk[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xk[i] = (rb + i < nj) ? x[rb + i] : 0.0f;
+  for (int tile = wave; tile * 16 < NR; tile += nwaves) {
+    const int r = tile * 16 + col;
+    // psi rows J = rb..rb+3 of both states at radial point r
+    float gr[4], gi[4], er[4], ei[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = rb + i;
+      cx<float> g = {0.f, 0.f}, e = {0.f, 0.f};
+      if (J < nj) {
+        g = sh[J * LS + r];
+        e = sh[(nj + J) * LS + r];
+      }
+      gr[i] = g.x; gi[i] = g.y; er[i] = e.x; ei[i] = e.y;
+    }
+    mf_short4 h0, l0, h1, l1, h2, l2, h3, l3;
+    split4(gr, h0, l0);
+    split4(gi, h1, l1);
+    split4(er, h2, l2);
+    split4(ei, h3, l3);
+    const mf_float4 z = {0.f, 0.f, 0.f, 0.f};
+    // Phi = T psi for each of (g re, g im, e re, e im); lane holds nodes rb..rb+3
+    mf_float4 Pgr = mma3(Ahi, Alo, h0, l0, z);
+    mf_float4 Pgi = mma3(Ahi, Alo, h1, l1, z);
+    mf_float4 Per = mma3(Ahi, Alo, h2, l2, z);
+    mf_float4 Pei = mma3(Ahi, Alo, h3, l3, z);
+    // (R - I) Phi per node: dg = -v Phi_g + i s Phi_e, de = i s Phi_g - v Phi_e
+    const float md = mudt[r] * E;
+    float dgr[4], dgi[4], der[4], dei[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float sn, vs;
+      sin_vers(md * xk[i], &sn, &vs);
+      dgr[i] = -vs * Pgr[i] - sn * Pei[i];
+      dgi[i] = -vs * Pgi[i] + sn * Per[i];
+      der[i] = -vs * Per[i] - sn * Pgi[i];
+      dei[i] = -vs * Pei[i] + sn * Pgr[i];
+    }
+    split4(dgr, h0, l0);
+    split4(dgi, h1, l1);
+    split4(der, h2, l2);
+    split4(dei, h3, l3);
+    mf_float4 cgr, cgi, cer, cei;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cgr[i] = gr[i]; cgi[i] = gi[i]; cer[i] = er[i]; cei[i] = ei[i];
+    }
+    // psi += T^T dPhi, accumulated in FP32 on top of the exact old psi
+    cgr = mma3(Bthi, Btlo, h0, l0, cgr);
+    cgi = mma3(Bthi, Btlo, h1, l1, cgi);
+    cer = mma3(Bthi, Btlo, h2, l2, cer);
+    cei = mma3(Bthi, Btlo, h3, l3, cei);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = rb + i;
+      if (J < nj) {
+        sh[J * LS + r] = {cgr[i], cgi[i]};
+        sh[(nj + J) * LS + r] = {cer[i], cei[i]};
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of four per-lane partials over the workgroup, in a fixed order.
+__device__ __forceinline__ void block_sum4(double* v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wid * 4 + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w * 4 + i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
+
+// --------------------------------------------------------------- kernel
+template <typename T, int NR, bool MFMA>
+__global__ __launch_bounds__(512) void mol_step_kernel(MolArgs a) {
+  constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2;
+  constexpr int LS = line_stride<NR>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nj = a.nj;
+  const int L = 2 * nj;
+  cx<T>* sh = reinterpret_cast<cx<T>*>(smem);
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * L * LS);
+
+  const int mol = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int line = tid / R2;
+  const int q = tid - line * R2;
+  const bool active = line < L;
+
+  const char* ws = a.ws;
+  MolTabs<T> tb;
+  if constexpr (sizeof(T) == 8) {
+    tb.kin = reinterpret_cast<const cx<T>*>(ws + a.lay.kin_d);
+    tb.tw = reinterpret_cast<const cx<T>*>(ws + a.lay.tw_d);
+    tb.vph = reinterpret_cast<const cx<T>*>(ws + a.lay.vph_d);
+    tb.tm = reinterpret_cast<const T*>(ws + a.lay.tm_d);
+    tb.x = reinterpret_cast<const T*>(ws + a.lay.x_d);
+    tb.mudt = reinterpret_cast<const T*>(ws + a.lay.mudt_d);
+    tb.mask = reinterpret_cast<const T*>(ws + a.lay.mask_d);
+  } else {
+    tb.kin = reinterpret_cast<const cx<T>*>(ws + a.lay.kin_f);
+    tb.tw = reinterpret_cast<const cx<T>*>(ws + a.lay.tw_f);
+    tb.vph = reinterpret_cast<const cx<T>*>(ws + a.lay.vph_f);
+    tb.tm = reinterpret_cast<const T*>(ws + a.lay.tm_f);
+    tb.x = reinterpret_cast<const T*>(ws + a.lay.x_f);
+    tb.mudt = reinterpret_cast<const T*>(ws + a.lay.mudt_f);
+    tb.mask = reinterpret_cast<const T*>(ws + a.lay.mask_f);
+  }
+  tb.mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
+  tb.cj = reinterpret_cast<const double*>(ws + a.lay.cj_d);
+
+  // field seen by this molecule (gathered from E_x at its cell, or given)
+  double Ed;
+  if (a.Ex != nullptr) {
+    const int c = a.cell_of_mol[mol];
+    Ed = (a.ex_is_float ? static_cast<double>(reinterpret_cast<const float*>(a.Ex)[c])
+                        : reinterpret_cast<const double*>(a.Ex)[c]) * a.inv_eau;
+  } else {
+    Ed = a.E_mol[mol];
+  }
+  if (a.E_out != nullptr && tid == 0) a.E_out[mol] = Ed;
+  const T E = static_cast<T>(Ed);
+
+  cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
+  cx<T>* slot = sh + line * LS;
+  cx<T> v[R1];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) v[p] = psi[line * NR + q + R2 * p];
+  }
+
+  double ab = 0.0;
+  for (int step = 0; step < a.n_steps; ++step) {
+    const cx<T>* kin = opaque(tb.kin);
+    const cx<T>* tw = opaque(tb.tw);
+    const cx<T>* vline = opaque(tb.vph) + line * NR;
+    const T* mask = opaque(tb.mask);
+    if (active) {
+      kinetic_half<T, NR>(v, slot, q, kin, tw);
+#pragma unroll
+      for (int p = 0; p < R1; ++p) {
+        v[p] = cmul(v[p], vline[q + R2 * p]);
+        slot[q + R2 * p] = v[p];
+      }
+    }
+    __syncthreads();
+    if constexpr (MFMA) {
+      coupling_mfma(sh, LS, NR, nj, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag), tb.x,
+                    tb.mudt, E);
+    } else {
+      coupling_dispatch<T>(nj, sh, LS, NR, tid, nthr, tb.tm, tb.x, tb.mudt, E);
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < R1; ++p) v[p] = cmul(slot[q + R2 * p], vline[q + R2 * p]);
+      kinetic_half<T, NR>(v, slot, q, opaque(kin), opaque(tw));
+#pragma unroll
+      for (int p = 0; p < R1; ++p) {
+        const T m = mask[q + R2 * p];
+        if (m != T(1)) {
+          ab += static_cast<double>((T(1) - m * m) * norm2(v[p]));
+          v[p] = cscale(v[p], m);
+        }
+      }
+    }
+  }
+
+  // readouts of the final state
+  double nrm = 0.0, yld = 0.0, dd = 0.0;
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) {
+      const int r = q + R2 * p;
+      const double n2 = static_cast<double>(norm2(v[p]));
+      nrm += n2;
+      if (r >= a.kdiss) yld += n2;
+      slot[r] = v[p];
+    }
+  }
+  if (a.want_d) {
+    __syncthreads();
+    for (int r = tid; r < NR; r += nthr) {
+      double acc = 0.0;
+      cx<T> g0 = sh[r], e0 = sh[nj * LS + r];
+      for (int J = 0; J + 1 < nj; ++J) {
+        const cx<T> g1 = sh[(J + 1) * LS + r], e1 = sh[(nj + J + 1) * LS + r];
+        const double t = static_cast<double>(g0.x) * e1.x + static_cast<double>(g0.y) * e1.y +
+                         static_cast<double>(g1.x) * e0.x + static_cast<double>(g1.y) * e0.y;
+        acc += tb.cj[J] * t;
+        g0 = g1;
+        e0 = e1;
+      }
+      dd += tb.mu[r] * acc;
+    }
+  }
+  double sums[4] = {ab, nrm, yld, dd};
+  block_sum4(sums, red);
+  if (tid == 0) {
+    const double dr = a.dr;
+    const double absorbed = a.absorbed[mol] + sums[0] * dr;
+    if (a.n_steps > 0) a.absorbed[mol] = absorbed;
+    const double d = 2.0 * dr * sums[3];
+    if (a.want_d && a.d_mol) a.d_mol[mol] = d;
+    if (a.want_norm && a.norm_mol) a.norm_mol[mol] = sums[1] * dr;
+    if (a.want_yield && a.yield_mol) a.yield_mol[mol] = sums[2] * dr + absorbed;
+    if (!isfinite(d) || !isfinite(sums[1]) || !isfinite(absorbed)) atomicOr(a.status, 1);
+  }
+  if (active && a.n_steps > 0) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) psi[line * NR + q + R2 * p] = v[p];
+  }
+}
+
+template <typename T, int NR, bool MFMA>
+int launch_mol_t(const MolArgs& a, hipStream_t s) {
+  static_assert(NR == FftShape<NR>::R1 * FftShape<NR>::R2, "FFT shape");
+  constexpr int R2 = FftShape<NR>::R2;
+  const int L = 2 * a.nj;
+  int threads = ((L * R2 + 63) / 64) * 64;
+  if (threads < 64) threads = 64;
+  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(L) * line_stride<NR>() + 16 * 4 * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set && shm > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, MFMA>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(mol_lds_limit()));
+    (void)hipGetLastError();
+    if (e != hipSuccess) return static_cast<int>(e);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((mol_step_kernel<T, NR, MFMA>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+template <typename T, bool MFMA>
+int launch_mol_any(const MolArgs& a, int n_r, hipStream_t s) {
+  switch (n_r) {
+    case 64: return launch_mol_t<T, 64, MFMA>(a, s);
+    case 128: return launch_mol_t<T, 128, MFMA>(a, s);
+    case 256: return launch_mol_t<T, 256, MFMA>(a, s);
+    case 512: return launch_mol_t<T, 512, MFMA>(a, s);
+    default: return static_cast<int>(hipErrorInvalidValue);
+  }
+}
+
+}  // namespace msqd

@@ -1,0 +1,389 @@
+"""Python binding of libmsqd (ctypes).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+torch provides device memory and the stream.  The entry points keep the C
+names (qd_init, qd_step, dipole_readout, fdtd_init, fdtd_step, flux_readout,
+map_build, coupled_step); the classes below only allocate the buffers the C
+calls expect and hold the descriptors.
+
+The library is loaded from this package directory; if it is missing the import
+fails loudly (there is no fallback implementation).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsqd.so")
+
+MSQD_OK, MSQD_EINVAL, MSQD_ESHAPE, MSQD_EPREC, MSQD_EUNSUP, MSQD_EDEVICE, MSQD_ENONFINITE = (
+    0, -1, -2, -3, -4, -5, -6)
+FP64, FP32, MIXED = 0, 1, 2
+PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+
+# CODATA 2018 (for converting readouts; the library has its own copy)
+E_AU = 5.14220674763e11
+EA0 = 8.4783536255e-30
+
+EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
+           "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
+           "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
+           "coupled_step"]
+
+
+class MsqdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"msqd error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmsqd.so not found at {LIB_PATH}; build it with "
+                      "python -m paper_2209_04487_amd.build")
+lib = C.CDLL(LIB_PATH)
+
+
+class qd_desc(C.Structure):
+    _fields_ = [("n_mol", C.c_int32), ("n_r", C.c_int32), ("j_max", C.c_int32),
+                ("prec", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
+                ("mass_au", C.c_double), ("dt_au", C.c_double),
+                ("absorb_width_au", C.c_double), ("r_diss_au", C.c_double)]
+
+
+class fdtd_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("npml", C.c_int32),
+                ("prec", C.c_int32), ("metal_id", C.c_int32), ("dx", C.c_double),
+                ("dt", C.c_double), ("eps_r", C.c_double * 4), ("drude_wp", C.c_double),
+                ("drude_gamma", C.c_double), ("cpml_m", C.c_double),
+                ("sigma_max_lo", C.c_double), ("sigma_max_hi", C.c_double),
+                ("kappa_max", C.c_double), ("alpha_max", C.c_double), ("src_k", C.c_int32),
+                ("mon_k", C.c_int32), ("n_freq", C.c_int32), ("mon_every", C.c_int32)]
+
+
+class fdtd_fields(C.Structure):
+    _fields_ = [("Ex", C.c_void_p), ("Ey", C.c_void_p), ("Ez", C.c_void_p),
+                ("Hx", C.c_void_p), ("Hy", C.c_void_p), ("Hz", C.c_void_p),
+                ("JDx", C.c_void_p), ("JDy", C.c_void_p), ("JDz", C.c_void_p),
+                ("psi", C.c_void_p), ("mat", C.c_void_p), ("dft", C.c_void_p)]
+
+
+class cpl_desc(C.Structure):
+    _fields_ = [("qd", qd_desc), ("fd", fdtd_desc), ("n_occ", C.c_int32),
+                ("mol_weight", C.c_double)]
+
+
+class cpl_state(C.Structure):
+    _fields_ = [("psi", C.c_void_p), ("absorbed", C.c_void_p), ("d_mol", C.c_void_p),
+                ("E_mol", C.c_void_p), ("P_c", C.c_void_p), ("J_mol", C.c_void_p),
+                ("cell_of_mol", C.c_void_p), ("occ_cell", C.c_void_p), ("occ_ptr", C.c_void_p),
+                ("mol_perm", C.c_void_p), ("f", fdtd_fields), ("qd_ws", C.c_void_p),
+                ("fd_ws", C.c_void_p)]
+
+
+_vp, _dp, _i32p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+_sigs = {
+    "msqd_last_error": (C.c_char_p, []),
+    "msqd_version": (C.c_int, []),
+    "qd_workspace_bytes": (C.c_size_t, [C.POINTER(qd_desc)]),
+    "qd_init": (C.c_int, [C.POINTER(qd_desc), _dp, _dp, _dp, _dp, _vp, C.c_size_t, _vp, _vp, _vp]),
+    "qd_step": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]),
+    "dipole_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "msqd_check_status": (C.c_int, [_vp, _vp]),
+    "fdtd_workspace_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
+    "fdtd_psi_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
+    "fdtd_dft_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
+    "fdtd_init": (C.c_int, [C.POINTER(fdtd_desc), _vp, _dp, C.POINTER(fdtd_fields), _vp,
+                            C.c_size_t, _vp]),
+    "fdtd_step": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, C.c_int64,
+                            C.c_double, _vp]),
+    "flux_readout": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, _vp]),
+    "map_build": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32,
+                            C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
+    "map_csr": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
+    "coupled_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _dp, C.c_int64,
+                               C.c_int32, _vp]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def last_error() -> str:
+    return lib.msqd_last_error().decode()
+
+
+def _check(rc):
+    if rc != MSQD_OK:
+        raise MsqdError(rc, last_error())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return C.c_void_p(t.data_ptr())
+    return t
+
+
+def _np_dp(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def current_stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# --------------------------------------------------------------- raw calls
+def qd_workspace_bytes(d: qd_desc) -> int:
+    n = lib.qd_workspace_bytes(C.byref(d))
+    if n == 0:
+        raise MsqdError(MSQD_EINVAL, last_error())
+    return n
+
+
+def qd_init(d, U_g, U_e, mu12, psi0, ws, psi, absorbed, stream=None):
+    ug, pug = _np_dp(U_g)
+    ue, pue = _np_dp(U_e)
+    mu, pmu = _np_dp(mu12)
+    p0, pp0 = _np_dp(psi0)
+    return _check(lib.qd_init(C.byref(d), pug, pue, pmu, pp0, _ptr(ws), ws.numel() * ws.element_size(),
+                              _ptr(psi), _ptr(absorbed), stream or current_stream()))
+
+
+def qd_step(d, ws, psi, E_mol, absorbed, d_mol=None, n_steps=1, stream=None):
+    return _check(lib.qd_step(C.byref(d), _ptr(ws), _ptr(psi), _ptr(E_mol), _ptr(absorbed),
+                              _ptr(d_mol), int(n_steps), stream or current_stream()))
+
+
+def dipole_readout(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=None, stream=None):
+    return _check(lib.dipole_readout(C.byref(d), _ptr(ws), _ptr(psi), _ptr(absorbed), _ptr(d_mol),
+                                     _ptr(norm_mol), _ptr(yield_mol), stream or current_stream()))
+
+
+def check_status(ws, stream=None):
+    return _check(lib.msqd_check_status(_ptr(ws), stream or current_stream()))
+
+
+def fdtd_init(d, mat_host, freqs, f, ws, stream=None):
+    mat = np.ascontiguousarray(mat_host, dtype=np.uint8)
+    fr, pfr = _np_dp(freqs if freqs is not None and len(freqs) else np.zeros(1))
+    return _check(lib.fdtd_init(C.byref(d), mat.ctypes.data_as(C.c_void_p), pfr, C.byref(f),
+                                _ptr(ws), ws.numel() * ws.element_size(),
+                                stream or current_stream()))
+
+
+def fdtd_step(d, f, ws, n, src_value, stream=None):
+    return _check(lib.fdtd_step(C.byref(d), C.byref(f), _ptr(ws), int(n), float(src_value),
+                                stream or current_stream()))
+
+
+def flux_readout(d, f, flux, stream=None):
+    return _check(lib.flux_readout(C.byref(d), C.byref(f), _ptr(flux), stream or current_stream()))
+
+
+def map_build(n_mol, nx, ny, nz, seed, slab_k0, slab_nk):
+    """Host call: returns (cell_of_mol, occ_cell, occ_ptr, mol_perm) int32 arrays."""
+    cell = np.zeros(n_mol, np.int32)
+    occ = np.zeros(max(n_mol, 1), np.int32)
+    ptr = np.zeros(n_mol + 1, np.int32)
+    perm = np.zeros(max(n_mol, 1), np.int32)
+    n_occ = C.c_int32(0)
+    _check(lib.map_build(n_mol, nx, ny, nz, C.c_uint64(seed), slab_k0, slab_nk,
+                         cell.ctypes.data_as(_i32p), occ.ctypes.data_as(_i32p),
+                         ptr.ctypes.data_as(_i32p), perm.ctypes.data_as(_i32p), C.byref(n_occ)))
+    k = n_occ.value
+    return cell, occ[:k].copy(), ptr[:k + 1].copy(), perm[:n_mol].copy()
+
+
+def map_csr(cell_of_mol, n_cells):
+    cell = np.ascontiguousarray(cell_of_mol, dtype=np.int32)
+    n_mol = len(cell)
+    occ = np.zeros(max(n_mol, 1), np.int32)
+    ptr = np.zeros(n_mol + 1, np.int32)
+    perm = np.zeros(max(n_mol, 1), np.int32)
+    n_occ = C.c_int32(0)
+    _check(lib.map_csr(n_mol, n_cells, cell.ctypes.data_as(_i32p), occ.ctypes.data_as(_i32p),
+                       ptr.ctypes.data_as(_i32p), perm.ctypes.data_as(_i32p), C.byref(n_occ)))
+    k = n_occ.value
+    return occ[:k].copy(), ptr[:k + 1].copy(), perm[:n_mol].copy()
+
+
+def coupled_step(d, st, src_values, n0, stream=None):
+    src, psrc = _np_dp(src_values)
+    return _check(lib.coupled_step(C.byref(d), C.byref(st), psrc, int(n0), len(src),
+                                   stream or current_stream()))
+
+
+# ------------------------------------------------------------ allocations
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+class Molecules:
+    """Wavepacket batch: descriptor, workspace, psi, absorbed, readout buffers."""
+
+    def __init__(self, n_mol, n_r, j_max, r_min, r_max, mass, dt_au, U_g, U_e, mu12, psi0,
+                 prec="fp64", absorb_width=2.0, r_diss=8.0):
+        self.prec = PREC[prec] if isinstance(prec, str) else prec
+        self.desc = qd_desc(int(n_mol), int(n_r), int(j_max), self.prec, float(r_min), float(r_max),
+                            float(mass), float(dt_au), float(absorb_width), float(r_diss))
+        dev = _dev()
+        nbytes = qd_workspace_bytes(self.desc)
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        cdt = torch.complex128 if self.prec == FP64 else torch.complex64
+        self.psi = torch.empty((int(n_mol), 2, int(j_max) + 1, int(n_r)), dtype=cdt, device=dev)
+        self.absorbed = torch.zeros(int(n_mol), dtype=torch.float64, device=dev)
+        self.d = torch.zeros(int(n_mol), dtype=torch.float64, device=dev)
+        qd_init(self.desc, U_g, U_e, mu12, psi0, self.ws, self.psi, self.absorbed)
+
+    @classmethod
+    def from_config(cls, cfg, n_mol=None, prec=None):
+        from workloads.molecule_inputs import morse_v0, potentials
+        ug, ue, mu = potentials(cfg)
+        return cls(cfg.n_mol if n_mol is None else n_mol, cfg.n_r, cfg.j_max, cfg.r_min, cfg.r_max,
+                   cfg.mass, cfg.dt_au, ug, ue, mu, morse_v0(cfg),
+                   prec or cfg.precision, cfg.absorb_width, cfg.r_diss)
+
+    def step(self, E_mol, n_steps=1, want_d=True):
+        qd_step(self.desc, self.ws, self.psi, E_mol, self.absorbed, self.d if want_d else None,
+                n_steps)
+
+    def readout(self):
+        n = self.desc.n_mol
+        dev = self.psi.device
+        d = torch.empty(n, dtype=torch.float64, device=dev)
+        nrm = torch.empty(n, dtype=torch.float64, device=dev)
+        yld = torch.empty(n, dtype=torch.float64, device=dev)
+        dipole_readout(self.desc, self.ws, self.psi, self.absorbed, d, nrm, yld)
+        return d, nrm, yld
+
+
+def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
+    from workloads.geometry import eps_table
+    p = PREC[prec or cfg.precision]
+    eps = eps_table(cfg)
+    nf = cfg.n_freq if n_freq is None else n_freq
+    return fdtd_desc(cfg.nx, cfg.ny, cfg.nz, cfg.npml, p, 2, cfg.dx, cfg.dt,
+                     (C.c_double * 4)(eps[0], eps[1], eps[2], 1.0), cfg.wp, cfg.gamma, cfg.cpml_m,
+                     cfg.sigma_max_lo, cfg.sigma_max_hi, cfg.cpml_kappa_max, cfg.cpml_alpha_max,
+                     cfg.src_k, cfg.mon_k, nf, cfg.mon_every)
+
+
+class Fields:
+    """Yee field buffers (torch) plus the descriptor and workspace."""
+
+    def __init__(self, desc: fdtd_desc, mat_host, freqs):
+        self.desc = desc
+        dev = _dev()
+        dt = torch.float64 if desc.prec == FP64 else torch.float32
+        shape = (desc.nz, desc.ny, desc.nx)
+        names = ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "JDx", "JDy", "JDz"]
+        self.t = {n: torch.empty(shape, dtype=dt, device=dev) for n in names}
+        psi_bytes = lib.fdtd_psi_bytes(C.byref(desc))
+        self.t["psi"] = torch.empty(max(psi_bytes // (8 if desc.prec == FP64 else 4), 1), dtype=dt,
+                                    device=dev)
+        self.t["mat"] = torch.empty((3,) + shape, dtype=torch.uint8, device=dev)
+        dft_bytes = lib.fdtd_dft_bytes(C.byref(desc))
+        self.t["dft"] = torch.empty(max(dft_bytes // 16, 1), dtype=torch.complex128, device=dev)
+        nbytes = lib.fdtd_workspace_bytes(C.byref(desc))
+        if nbytes == 0:
+            raise MsqdError(MSQD_EINVAL, last_error())
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.f = fdtd_fields(*[C.c_void_p(self.t[n].data_ptr()) for n in names + ["psi", "mat"]],
+                             C.c_void_p(self.t["dft"].data_ptr()) if desc.n_freq > 0 else None)
+        fdtd_init(desc, mat_host, freqs, self.f, self.ws)
+
+    def __getattr__(self, name):
+        t = self.__dict__.get("t")
+        if t is not None and name in t:
+            return t[name]
+        raise AttributeError(name)
+
+    def step(self, n, src_value):
+        fdtd_step(self.desc, self.f, self.ws, n, src_value)
+
+    def flux(self):
+        out = torch.zeros(self.desc.n_freq, dtype=torch.float64, device=self.ws.device)
+        flux_readout(self.desc, self.f, out)
+        return out
+
+    def dft_planes(self):
+        nf, ny, nx = self.desc.n_freq, self.desc.ny, self.desc.nx
+        return self.t["dft"][: 4 * nf * ny * nx].view(4, nf, ny, nx)
+
+
+class Coupled:
+    """The self-consistent system: molecules + fields + maps, driven by
+    coupled_step."""
+
+    def __init__(self, cfg, prec=None, n_mol=None, cells=None, mat=None, n_freq=None):
+        from workloads.geometry import material_map
+        prec = prec or cfg.precision
+        self.cfg = cfg
+        dev = _dev()
+        if mat is None:
+            mat = material_map(cfg)
+        self.fields = Fields(fdtd_desc_from_config(cfg, prec, n_freq), mat, cfg.freqs)
+        if cells is None:
+            if cfg.placement == "block":
+                from workloads.molecule_inputs import block_cell_list
+                cells = block_cell_list(cfg)
+                occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
+            else:
+                cells, occ, ptr, perm = map_build(cfg.n_mol, cfg.nx, cfg.ny, cfg.nz, cfg.seed,
+                                                  cfg.slab_k0, cfg.slab_nk)
+        else:
+            cells = np.asarray(cells, np.int32)
+            occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
+        if n_mol is not None and n_mol != len(cells):
+            cells = cells[:n_mol]
+            occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
+        self.cells_host = cells
+        self.mol = Molecules.from_config(cfg, n_mol=len(cells), prec=prec)
+        it = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=dev)  # noqa: E731
+        self.cell_of_mol = it(cells)
+        self.occ_cell = it(occ)
+        self.occ_ptr = it(ptr)
+        self.mol_perm = it(perm)
+        nm = len(cells)
+        self.E_mol = torch.zeros(max(nm, 1), dtype=torch.float64, device=dev)
+        self.P_c = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
+        self.J_mol = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
+        self.desc = cpl_desc(self.mol.desc, self.fields.desc, len(occ), float(cfg.mol_weight))
+        self.state = cpl_state(C.c_void_p(self.mol.psi.data_ptr()),
+                               C.c_void_p(self.mol.absorbed.data_ptr()),
+                               C.c_void_p(self.mol.d.data_ptr()), C.c_void_p(self.E_mol.data_ptr()),
+                               C.c_void_p(self.P_c.data_ptr()), C.c_void_p(self.J_mol.data_ptr()),
+                               C.c_void_p(self.cell_of_mol.data_ptr()),
+                               C.c_void_p(self.occ_cell.data_ptr()),
+                               C.c_void_p(self.occ_ptr.data_ptr()),
+                               C.c_void_p(self.mol_perm.data_ptr()), self.fields.f,
+                               C.c_void_p(self.mol.ws.data_ptr()),
+                               C.c_void_p(self.fields.ws.data_ptr()))
+        self.n = 0
+
+    def step(self, src_values):
+        src_values = np.atleast_1d(np.asarray(src_values, np.float64))
+        coupled_step(self.desc, self.state, src_values, self.n)
+        self.n += len(src_values)
+
+
+def n_exports_ok():
+    return all(hasattr(lib, n) for n in EXPORTS)
+
+
+def version():
+    return lib.msqd_version()
+
+
+__all__ = ["Molecules", "Fields", "Coupled", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
+           "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status",
+           "MsqdError", "lib", "LIB_PATH", "EXPORTS"]

@@ -1,0 +1,82 @@
+"""GPU parity of the whole coupled step (coupled_step) with the FP64 oracle on
+the tiny workload (24^3 grid, 64 molecules, 500 steps): the ensemble dipole
+trace D(t) = sum_i d_i(t), every molecule's dipole at every step, the final
+fields, wavepackets, absorbed norms, cell polarisation and monitor flux.
+
+FP64 form: 1e-10 relative (the spec parity bar).  FP32 / mixed forms:
+the dipole trace within 1e-4 relative L2 of the FP64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner, rel_err
+from oracle.coupled import CoupledOracle
+from workloads import get_config
+from workloads.pulses import source_values
+
+pytestmark = pytest.mark.gpu
+
+_ORACLE = {}
+
+
+def _oracle(cfg, nsteps):
+    key = (cfg.name, nsteps)
+    if key not in _ORACLE:
+        o = CoupledOracle(cfg)
+        tr = o.run(source_values(cfg, 0, nsteps))
+        _ORACLE[key] = (o, tr)
+    return _ORACLE[key]
+
+
+def _gpu_run(cfg, prec, nsteps):
+    from paper_2209_04487_amd import msqd
+    sysm = msqd.Coupled(cfg, prec=prec)
+    src = source_values(cfg, 0, nsteps)
+    d = np.zeros((nsteps, sysm.mol.desc.n_mol))
+    for n in range(nsteps):
+        sysm.step(src[n:n + 1])
+        d[n] = sysm.mol.d.cpu().numpy()
+    torch.cuda.synchronize()
+    return sysm, d
+
+
+def test_coupled_tiny_fp64_matches_oracle():
+    cfg = get_config("cfg0")
+    nsteps = cfg.n_steps
+    banner(f"coupled cfg0 fp64 {nsteps} steps")
+    sysm, d = _gpu_run(cfg, "fp64", nsteps)
+    o, tr = _oracle(cfg, nsteps)
+    D = d.sum(axis=1)
+    assert np.linalg.norm(D - tr["D"]) / np.linalg.norm(tr["D"]) < 1e-10
+    assert rel_err(d, tr["d"]) < 1e-10
+    # fields: relative to the field scale (the scattered E_y, E_z are small
+    # differences of nearly equal cell currents, so their own scale is not a
+    # meaningful denominator)
+    f = sysm.fields
+    emax = max(np.abs(e).max() for e in o.yee.E)
+    hmax = max(np.abs(h).max() for h in o.yee.H)
+    for c, nm in enumerate(["Ex", "Ey", "Ez"]):
+        assert np.abs(getattr(f, nm).cpu().numpy() - o.yee.E[c]).max() < 1e-10 * emax, nm
+    for c, nm in enumerate(["Hx", "Hy", "Hz"]):
+        assert np.abs(getattr(f, nm).cpu().numpy() - o.yee.H[c]).max() < 1e-10 * hmax, nm
+    assert rel_err(sysm.mol.psi.cpu().numpy(), o.psi) < 1e-10
+    np.testing.assert_allclose(sysm.mol.absorbed.cpu().numpy(), o.absorbed, rtol=1e-10)
+    assert rel_err(sysm.P_c.cpu().numpy(), o.P) < 1e-10
+    assert rel_err(sysm.E_mol.cpu().numpy(), tr["E_mol"][-1]) < 1e-10
+    assert rel_err(f.flux().cpu().numpy(), o.monitor.flux()) < 1e-9
+    dd, nn, yy = sysm.mol.readout()
+    np.testing.assert_allclose(nn.cpu().numpy() + sysm.mol.absorbed.cpu().numpy(), 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_coupled_tiny_reduced_precision_dipole_error(prec):
+    cfg = get_config("cfg0")
+    nsteps = cfg.n_steps
+    banner(f"coupled cfg0 {prec} {nsteps} steps")
+    sysm, d = _gpu_run(cfg, prec, nsteps)
+    o, tr = _oracle(cfg, nsteps)
+    D = d.sum(axis=1)
+    err = np.linalg.norm(D - tr["D"]) / np.linalg.norm(tr["D"])
+    print(f"{prec} relative dipole-trace error {err:.3e}")
+    assert err < 1e-4

@@ -46,3 +46,17 @@ def morse_v0(cfg: Config) -> np.ndarray:
     dr = (cfg.r_max - cfg.r_min) / cfg.n_r
     psi /= math.sqrt(np.sum(psi * psi) * dr)
     return psi
+
+
+def block_cell_list(cfg) -> np.ndarray:
+    """Flat E_x index of each molecule for the block placement: one molecule
+    per cell of the cube [lo, lo+n)^3, i fastest (int32)."""
+    n = cfg.block_n
+    out = np.empty(n ** 3, dtype=np.int32)
+    idx = 0
+    for k in range(cfg.block_lo, cfg.block_lo + n):
+        for j in range(cfg.block_lo, cfg.block_lo + n):
+            for i in range(cfg.block_lo, cfg.block_lo + n):
+                out[idx] = (k * cfg.ny + j) * cfg.nx + i
+                idx += 1
+    return out
