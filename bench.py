@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--n0", type=int, default=0, help="first step of the run (pulse time origin)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64"], default=None,
+                    help="only time the molecular-step kernel of this form (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -210,6 +212,12 @@ def main():
     cfg = get_config("cfg2")
     cfg64 = get_config("cfg1")
     K, W = args.steps, args.warmup
+    if args.kernel:
+        ms = time_mol_kernel(cfg, args.kernel, K)
+        b = mol_bytes_per_step(cfg, args.kernel) * cfg.n_mol
+        print(json.dumps({"kernel": args.kernel, "launches": K, "ms": ms,
+                          "GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}))
+        return
 
     log(f"mixed coupled run: {cfg.n_mol} molecules, {W}+{K} steps")
     mixed = run_coupled(cfg, "mixed", K, W, args.n0, record_d=not args.no_fp64)

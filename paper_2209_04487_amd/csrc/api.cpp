@@ -38,7 +38,7 @@ QdLayout qd_layout(int n_r, int nj) {
   L.status = take(16);
   L.psi0 = take(8 * nr);
   L.kin_d = take(16 * nr);
-  L.tw_d = take(16 * nr);
+  L.tw_d = take(16 * 32 * 32);
   L.vph_d = take(16 * 2 * J * nr);
   L.tm_d = take(8 * J * J);
   L.x_d = take(8 * J);
@@ -47,13 +47,15 @@ QdLayout qd_layout(int n_r, int nj) {
   L.mu_d = take(8 * nr);
   L.cj_d = take(8 * J);
   L.kin_f = take(8 * nr);
-  L.tw_f = take(8 * nr);
+  L.tw_f = take(8 * 32 * 32);
   L.vph_f = take(8 * 2 * J * nr);
   L.tm_f = take(4 * J * J);
   L.x_f = take(4 * J);
   L.mudt_f = take(4 * nr);
   L.mask_f = take(4 * nr);
-  L.tmfrag = take(4 * 64 * 8 * 2);  // bf16 fragments: 4 operand blocks x 64 lanes x 8 values x 2 B
+  L.tmfrag = take(4 * 64 * 4 * 2);  // bf16 fragments: 4 operand blocks x 64 lanes x 4 values
+  L.tmfrag_d = take(2 * 64 * 4 * 8);
+  L.tmfrag_f = take(2 * 64 * 4 * 4);
   L.total = o;
   return L;
 }
@@ -281,7 +283,7 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   const int nr = d->n_r, nj = d->j_max + 1;
   put(L.psi0, psi0, 8 * nr);
   put(L.kin_d, t.kin.data(), 16 * nr);
-  put(L.tw_d, t.tw.data(), 16 * nr);
+  put(L.tw_d, t.tw.data(), 16 * t.tw.size());
   put(L.vph_d, t.vph.data(), 16 * t.vph.size());
   put(L.tm_d, t.tm.data(), 8 * t.tm.size());
   put(L.x_d, t.x.data(), 8 * nj);
@@ -308,6 +310,22 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   putf(L.mudt_f, t.mudt);
   putf(L.mask_f, t.mask);
   fill_mfma_fragments(host.data() + L.tmfrag, t.tm, nj);
+  {
+    double* fd = reinterpret_cast<double*>(host.data() + L.tmfrag_d);
+    float* ff = reinterpret_cast<float*>(host.data() + L.tmfrag_f);
+    // lane l, element i owns row 4 (l/16) + i (FP32 instruction) or
+    // 4 i + l/16 (FP64 instruction) of the 16-row operand blocks
+    auto entry = [&](int row, int k) { return (row < nj && k < nj) ? t.tm[static_cast<size_t>(row) * nj + k] : 0.0; };
+    for (int lane = 0; lane < 64; ++lane)
+      for (int i = 0; i < 4; ++i) {
+        const int c = lane % 16, g = lane / 16;
+        const int kf = 4 * g + i, kd = 4 * i + g;
+        fd[(0 * 64 + lane) * 4 + i] = entry(c, kd);
+        fd[(1 * 64 + lane) * 4 + i] = entry(kd, c);
+        ff[(0 * 64 + lane) * 4 + i] = static_cast<float>(entry(c, kf));
+        ff[(1 * 64 + lane) * 4 + i] = static_cast<float>(entry(kf, c));
+      }
+  }
 
   MSQD_HIP(hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s));
   if (d->n_mol > 0) {

@@ -63,8 +63,15 @@ MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double
     const double kap = 2.0 * kPi * ms / (nr * dr);
     const double ph = -kap * kap * dt / (4.0 * mass);
     t.kin[m] = std::polar(1.0 / nr, ph);
-    t.tw[m] = std::polar(1.0, -2.0 * kPi * m / nr);
   }
+  // four-step FFT twiddles: tw[x * R1 + y] = exp(-2 pi i x y / n_r), x, y < R1
+  const int r1 = fft_r1(nr);
+  t.tw.assign(static_cast<size_t>(r1) * r1, std::complex<double>(0.0, 0.0));
+  for (int x = 0; x < r1; ++x)
+    for (int y = 0; y < r1; ++y) {
+      const long e = (static_cast<long>(x) * y) % nr;
+      t.tw[static_cast<size_t>(x) * r1 + y] = std::polar(1.0, -2.0 * kPi * static_cast<double>(e) / nr);
+    }
   t.vph.resize(static_cast<size_t>(2) * nj * nr);
   for (int s = 0; s < 2; ++s) {
     const double* U = (s == 0) ? U_g : U_e;

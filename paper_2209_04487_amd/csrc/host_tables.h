@@ -17,6 +17,8 @@ struct MolTablesHost {
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// radix of the first in-register FFT pass for a radial grid of n_r points
+inline int fft_r1(int n_r) { return n_r == 64 ? 8 : (n_r == 512 ? 32 : 16); }
 MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
                                const double* mu12);
 

@@ -25,6 +25,8 @@ struct QdLayout {
   size_t cj_d;        // double [nj]      <J|cos|J+1>
   size_t kin_f, tw_f, vph_f, tm_f, x_f, mudt_f, mask_f;   // float versions
   size_t tmfrag;      // bf16 matrix-core fragments of T and T^T (hi, lo)
+  size_t tmfrag_d;    // double [2][64][4] matrix-core fragments of T and T^T
+  size_t tmfrag_f;    // float  [2][64][4]
   size_t total;
 };
 

@@ -71,15 +71,17 @@ struct MolTabs {
 // ---------------------------------------------------------------- K/2
 // v: this lane's R1 values of its line (r = q + R2 p); slot: the line's LDS
 // region (R2 * (R1 + 1) elements).  kin already carries the 1/NR of the
-// inverse transform.
+// inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
+// x, y < R1, so that every table access is a uniform base plus one lane
+// offset plus an immediate.
 template <typename T, int NR>
-__device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* kin,
-                                             const cx<T>* tw) {
+__device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
+                                             const cx<T>* __restrict__ tw2) {
   constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2, U = R1 / R2, RS = R1 + 1;
   // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
   dft<R1, false, T>(v);
 #pragma unroll
-  for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw[(q * a) & (NR - 1)]);
+  for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw2[a * R1 + q]);
 #pragma unroll
   for (int a = 0; a < R1; ++a) slot[q * RS + a] = v[a];
   wave_lds_sync();
@@ -95,7 +97,7 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
     for (int b = 0; b < R2; ++b) w[b] = cmul(w[b], kin[a + R1 * b]);
     dft<R2, true, T>(w);
 #pragma unroll
-    for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw[(qq * a) & (NR - 1)]);
+    for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);
   }
   wave_lds_sync();
 #pragma unroll
@@ -176,140 +178,6 @@ __device__ __forceinline__ void rotate(cx<T>& g, cx<T>& e, T c, T s) {
   e = {c * e0.x - s * g0.y, c * e0.y + s * g0.x};
 }
 
-// Exact exp(-i H_int dt) at radial point r on the truncated J basis:
-// Phi = T psi (J -> Gauss-Legendre nodes), per-node rotation by
-// phi_k = mu12(r) x_k E dt, psi = T^T Phi.  The nodes are symmetric
-// (x_{n-1-k} = -x_k, T[n-1-k][J] = (-1)^J T[k][J]), so with
-// u_k = sum_{J even} T[k][J] psi_J and w_k = sum_{J odd} T[k][J] psi_J the
-// node pair (k, n-1-k) holds u + w and u - w, rotated by +phi and -phi.
-// Folding the pair back gives, per state pair (g, e) with sigma_x swapping
-// them:  even J <- 2 sum_k T[k][J] (c u + i s sigma_x w),
-//        odd J  <- 2 sum_k T[k][J] (c w + i s sigma_x u),
-// plus the middle node (x = 0, odd n) which is not rotated.  Even and odd
-// parts are streamed separately to keep few values live.
-template <typename T, int NJ>
-__device__ __forceinline__ void coupling_point(cx<T>* sh, int LS, int r, const T* __restrict__ tm,
-                                               const T* __restrict__ x, T md) {
-  constexpr int KH = NJ / 2;           // mirrored node pairs
-  constexpr bool MID = (NJ & 1) != 0;  // middle node x = 0
-  constexpr int KE = KH + (MID ? 1 : 0);
-  constexpr int NE = (NJ + 1) / 2, NO = NJ / 2;
-  cx<T> ug[KE > 0 ? KE : 1], ue[KE > 0 ? KE : 1];
-  cx<T> wg[KH > 0 ? KH : 1], we[KH > 0 ? KH : 1];
-  {
-    cx<T> g[NE], e[NE];
-#pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      g[i] = sh[(2 * i) * LS + r];
-      e[i] = sh[(NJ + 2 * i) * LS + r];
-    }
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      cx<T> ag = {0, 0}, ae = {0, 0};
-#pragma unroll
-      for (int i = 0; i < NE; ++i) {
-        const T t = tm[k * NJ + 2 * i];
-        ag = ag + cscale(g[i], t);
-        ae = ae + cscale(e[i], t);
-      }
-      ug[k] = ag;
-      ue[k] = ae;
-    }
-  }
-  if constexpr (NO > 0) {
-    cx<T> g[NO > 0 ? NO : 1], e[NO > 0 ? NO : 1];
-#pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      g[i] = sh[(2 * i + 1) * LS + r];
-      e[i] = sh[(NJ + 2 * i + 1) * LS + r];
-    }
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      cx<T> ag = {0, 0}, ae = {0, 0};
-#pragma unroll
-      for (int i = 0; i < NO; ++i) {
-        const T t = tm[k * NJ + 2 * i + 1];
-        ag = ag + cscale(g[i], t);
-        ae = ae + cscale(e[i], t);
-      }
-      wg[k] = ag;
-      we[k] = ae;
-    }
-  }
-  // rotate and fold the mirror pairs
-#pragma unroll
-  for (int k = 0; k < KH; ++k) {
-    T sn, vs;
-    sin_vers(md * x[k], &sn, &vs);
-    const T c = T(1) - vs;
-    const cx<T> a_g = {c * ug[k].x - sn * we[k].y, c * ug[k].y + sn * we[k].x};
-    const cx<T> a_e = {c * ue[k].x - sn * wg[k].y, c * ue[k].y + sn * wg[k].x};
-    const cx<T> b_g = {c * wg[k].x - sn * ue[k].y, c * wg[k].y + sn * ue[k].x};
-    const cx<T> b_e = {c * we[k].x - sn * ug[k].y, c * we[k].y + sn * ug[k].x};
-    ug[k] = a_g;
-    ue[k] = a_e;
-    wg[k] = b_g;
-    we[k] = b_e;
-  }
-  // back to J
-#pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int J = 2 * i;
-    cx<T> ag = {0, 0}, ae = {0, 0};
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const T t = T(2) * tm[k * NJ + J];
-      ag = ag + cscale(ug[k], t);
-      ae = ae + cscale(ue[k], t);
-    }
-    if (MID) {
-      const T t = tm[KH * NJ + J];
-      ag = ag + cscale(ug[KE - 1], t);
-      ae = ae + cscale(ue[KE - 1], t);
-    }
-    sh[J * LS + r] = ag;
-    sh[(NJ + J) * LS + r] = ae;
-  }
-#pragma unroll
-  for (int i = 0; i < NO; ++i) {
-    const int J = 2 * i + 1;
-    cx<T> ag = {0, 0}, ae = {0, 0};
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const T t = T(2) * tm[k * NJ + J];
-      ag = ag + cscale(wg[k], t);
-      ae = ae + cscale(we[k], t);
-    }
-    sh[J * LS + r] = ag;
-    sh[(NJ + J) * LS + r] = ae;
-  }
-}
-
-template <typename T, int NJ>
-__device__ __forceinline__ void coupling_all(cx<T>* sh, int LS, int NR, int tid, int nthr,
-                                          const T* __restrict__ tm, const T* __restrict__ x,
-                                          const T* __restrict__ mudt, T E) {
-#pragma unroll 1
-  for (int r = tid; r < NR; r += nthr)
-    coupling_point<T, NJ>(sh, LS, r, opaque(tm), opaque(x), mudt[r] * E);
-}
-
-template <typename T>
-__device__ __forceinline__ void coupling_dispatch(int nj, cx<T>* sh, int LS, int NR, int tid,
-                                                  int nthr, const T* tm, const T* x,
-                                                  const T* mudt, T E) {
-  switch (nj) {
-#define MSQD_CASE(n) \
-  case n: coupling_all<T, n>(sh, LS, NR, tid, nthr, tm, x, mudt, E); break;
-    MSQD_CASE(1) MSQD_CASE(2) MSQD_CASE(3) MSQD_CASE(4) MSQD_CASE(5) MSQD_CASE(6)
-    MSQD_CASE(7) MSQD_CASE(8) MSQD_CASE(9) MSQD_CASE(10) MSQD_CASE(11) MSQD_CASE(12)
-    MSQD_CASE(13) MSQD_CASE(14) MSQD_CASE(15) MSQD_CASE(16)
-#undef MSQD_CASE
-    default: break;
-  }
-}
-
-
 // ----------------------------------------------- C(E) on the matrix cores
 // Mixed form: psi += T^T (R - I) T psi over the J axis, per radial point, as
 // 16x16x16 BF16 matrix-core products with FP32 accumulation.  Both operands
@@ -367,6 +235,7 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int
   float xk[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) xk[i] = (rb + i < nj) ? x[rb + i] : 0.0f;
+#pragma unroll 1
   for (int tile = wave; tile * 16 < NR; tile += nwaves) {
     const int r = tile * 16 + col;
     // psi rows J = rb..rb+3 of both states at radial point r
@@ -429,6 +298,120 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int
   }
 }
 
+
+// FP32 / FP64 forms: the same increment-form contraction on the 16x16x4
+// matrix-core instructions of the working precision (no operand splitting).
+// The K = 16 contraction is four instructions; instruction i sums four of
+// the J (or node) rows, lane l feeding the rows it owns, and the forward
+// output rows are again the inverse's operand rows.  Row ownership follows
+// the instruction's output layout: lane l, element i holds row 4 (l/16) + i
+// for the FP32 instruction and row 4 i + l/16 for the FP64 one.
+typedef double mf_double4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaK4;
+template <>
+struct MfmaK4<float> {
+  typedef mf_float4 acc;
+  __device__ static __forceinline__ int row(int g, int i) { return 4 * g + i; }
+  __device__ static __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ void settle(acc&, acc&, acc&, acc&) {}
+};
+template <>
+struct MfmaK4<double> {
+  typedef mf_double4 acc;
+  __device__ static __forceinline__ int row(int g, int i) { return 4 * i + g; }
+  __device__ static __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // The compiler's wait before a vector read of this instruction's result is
+  // too short on gfx950; stall explicitly (about 100 cycles) until the last
+  // product of the chain has landed.
+  __device__ static __forceinline__ void settle(acc& a, acc& b, acc& c, acc& d) {
+    asm volatile(
+        "s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15"
+        : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+  }
+};
+
+// frag: [2][64 lanes][4]: block 0 A_i = T[l%16][row(l/16, i)], block 1 the
+// transpose T[row(l/16, i)][l%16]; zero outside nj.
+template <typename T>
+__device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int LS, int NR, int nj,
+                                                    const T* __restrict__ frag,
+                                                    const T* __restrict__ x,
+                                                    const T* __restrict__ mudt, T E) {
+  typedef typename MfmaK4<T>::acc acc_t;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  T A[4], At[4], xk[4];
+  int rows[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rows[i] = MfmaK4<T>::row(grp, i);
+    A[i] = frag[(0 * 64 + lane) * 4 + i];
+    At[i] = frag[(1 * 64 + lane) * 4 + i];
+    xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
+  }
+#pragma unroll 1
+  for (int tile = wave; tile * 16 < NR; tile += nwaves) {
+    const int r = tile * 16 + col;
+    acc_t cgr, cgi, cer, cei;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = rows[i];
+      cx<T> g = {T(0), T(0)}, e = {T(0), T(0)};
+      if (J < nj) {
+        g = sh[J * LS + r];
+        e = sh[(nj + J) * LS + r];
+      }
+      cgr[i] = g.x; cgi[i] = g.y; cer[i] = e.x; cei[i] = e.y;
+    }
+    const acc_t z = {T(0), T(0), T(0), T(0)};
+    acc_t Pgr = z, Pgi = z, Per = z, Pei = z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Pgr = MfmaK4<T>::mma(A[i], cgr[i], Pgr);
+      Pgi = MfmaK4<T>::mma(A[i], cgi[i], Pgi);
+      Per = MfmaK4<T>::mma(A[i], cer[i], Per);
+      Pei = MfmaK4<T>::mma(A[i], cei[i], Pei);
+    }
+    MfmaK4<T>::settle(Pgr, Pgi, Per, Pei);
+    const T md = mudt[r] * E;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T sn, vs;
+      sin_vers(md * xk[i], &sn, &vs);
+      const T gr = Pgr[i], gi = Pgi[i], er = Per[i], ei = Pei[i];
+      Pgr[i] = -vs * gr - sn * ei;
+      Pgi[i] = -vs * gi + sn * er;
+      Per[i] = -vs * er - sn * gi;
+      Pei[i] = -vs * ei + sn * gr;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cgr = MfmaK4<T>::mma(At[i], Pgr[i], cgr);
+      cgi = MfmaK4<T>::mma(At[i], Pgi[i], cgi);
+      cer = MfmaK4<T>::mma(At[i], Per[i], cer);
+      cei = MfmaK4<T>::mma(At[i], Pei[i], cei);
+    }
+    MfmaK4<T>::settle(cgr, cgi, cer, cei);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = rows[i];
+      if (J < nj) {
+        sh[J * LS + r] = {cgr[i], cgi[i]};
+        sh[(nj + J) * LS + r] = {cer[i], cei[i]};
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -460,8 +443,18 @@ template <typename T>
 __device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
 
 // --------------------------------------------------------------- kernel
-template <typename T, int NR, bool MFMA>
-__global__ __launch_bounds__(512) void mol_step_kernel(MolArgs a) {
+// Occupancy target (waves per SIMD) of the fused step: the FP32 forms are
+// kept within 128 VGPRs so that two workgroups of up to 8 waves share a CU.
+template <typename T>
+struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
+
+// coupling path: BF16 hi/lo split on 16x16x16 (mixed form) or the
+// working precision on 16x16x4 (FP32 and FP64 forms)
+enum { kCpExact = 0, kCpBf16x3 = 1 };
+
+template <typename T, int NR, int CP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T>::waves)))
+void mol_step_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2;
   constexpr int LS = line_stride<NR>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -513,37 +506,39 @@ __global__ __launch_bounds__(512) void mol_step_kernel(MolArgs a) {
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
   cx<T>* slot = sh + line * LS;
+  const int loff = line * NR + q;  // this lane's first element of its line
   cx<T> v[R1];
   if (active) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) v[p] = psi[line * NR + q + R2 * p];
+    for (int p = 0; p < R1; ++p) v[p] = psi[loff + R2 * p];
   }
 
   double ab = 0.0;
   for (int step = 0; step < a.n_steps; ++step) {
     const cx<T>* kin = opaque(tb.kin);
     const cx<T>* tw = opaque(tb.tw);
-    const cx<T>* vline = opaque(tb.vph) + line * NR;
+    const cx<T>* vph = opaque(tb.vph);
     const T* mask = opaque(tb.mask);
     if (active) {
       kinetic_half<T, NR>(v, slot, q, kin, tw);
 #pragma unroll
       for (int p = 0; p < R1; ++p) {
-        v[p] = cmul(v[p], vline[q + R2 * p]);
+        v[p] = cmul(v[p], vph[loff + R2 * p]);
         slot[q + R2 * p] = v[p];
       }
     }
     __syncthreads();
-    if constexpr (MFMA) {
+    if constexpr (CP == kCpBf16x3) {
       coupling_mfma(sh, LS, NR, nj, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag), tb.x,
                     tb.mudt, E);
     } else {
-      coupling_dispatch<T>(nj, sh, LS, NR, tid, nthr, tb.tm, tb.x, tb.mudt, E);
+      const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
+      coupling_mfma_exact<T>(sh, LS, NR, nj, frag, tb.x, tb.mudt, E);
     }
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int p = 0; p < R1; ++p) v[p] = cmul(slot[q + R2 * p], vline[q + R2 * p]);
+      for (int p = 0; p < R1; ++p) v[p] = cmul(slot[q + R2 * p], vph[loff + R2 * p]);
       kinetic_half<T, NR>(v, slot, q, opaque(kin), opaque(tw));
 #pragma unroll
       for (int p = 0; p < R1; ++p) {
@@ -598,11 +593,11 @@ __global__ __launch_bounds__(512) void mol_step_kernel(MolArgs a) {
   }
   if (active && a.n_steps > 0) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) psi[line * NR + q + R2 * p] = v[p];
+    for (int p = 0; p < R1; ++p) psi[loff + R2 * p] = v[p];
   }
 }
 
-template <typename T, int NR, bool MFMA>
+template <typename T, int NR, int CP>
 int launch_mol_t(const MolArgs& a, hipStream_t s) {
   static_assert(NR == FftShape<NR>::R1 * FftShape<NR>::R2, "FFT shape");
   constexpr int R2 = FftShape<NR>::R2;
@@ -612,24 +607,24 @@ int launch_mol_t(const MolArgs& a, hipStream_t s) {
   const size_t shm = sizeof(cx<T>) * static_cast<size_t>(L) * line_stride<NR>() + 16 * 4 * sizeof(double);
   static bool attr_set = false;
   if (!attr_set && shm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, MFMA>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, CP>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(mol_lds_limit()));
     (void)hipGetLastError();
     if (e != hipSuccess) return static_cast<int>(e);
     attr_set = true;
   }
-  hipLaunchKernelGGL((mol_step_kernel<T, NR, MFMA>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  hipLaunchKernelGGL((mol_step_kernel<T, NR, CP>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());
 }
 
-template <typename T, bool MFMA>
+template <typename T, int CP>
 int launch_mol_any(const MolArgs& a, int n_r, hipStream_t s) {
   switch (n_r) {
-    case 64: return launch_mol_t<T, 64, MFMA>(a, s);
-    case 128: return launch_mol_t<T, 128, MFMA>(a, s);
-    case 256: return launch_mol_t<T, 256, MFMA>(a, s);
-    case 512: return launch_mol_t<T, 512, MFMA>(a, s);
+    case 64: return launch_mol_t<T, 64, CP>(a, s);
+    case 128: return launch_mol_t<T, 128, CP>(a, s);
+    case 256: return launch_mol_t<T, 256, CP>(a, s);
+    case 512: return launch_mol_t<T, 512, CP>(a, s);
     default: return static_cast<int>(hipErrorInvalidValue);
   }
 }

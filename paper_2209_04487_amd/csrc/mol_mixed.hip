@@ -10,7 +10,7 @@
 namespace msqd {
 
 int launch_mol_mixed(const MolArgs& a, int n_r, hipStream_t s) {
-  return launch_mol_any<float, true>(a, n_r, s);
+  return launch_mol_any<float, kCpBf16x3>(a, n_r, s);
 }
 
 namespace {
