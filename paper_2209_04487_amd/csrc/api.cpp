@@ -87,8 +87,8 @@ FdLayout fd_layout(const fdtd_desc* d) {
 }
 
 size_t mol_lds_bytes(int n_r, int nj, int prec) {
-  const int r2 = (n_r == 64 || n_r == 128) ? 8 : 16;
   const size_t el = prec == MSQD_FP64 ? 16 : 8;
+  const int r2 = n_r / fft_r1(n_r, static_cast<int>(el / 2));
   return el * static_cast<size_t>(2 * nj) * (n_r + r2) + 16 * 4 * sizeof(double);
 }
 
@@ -303,7 +303,7 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
     }
   };
   putcf(L.kin_f, t.kin);
-  putcf(L.tw_f, t.tw);
+  putcf(L.tw_f, t.tw_f);
   putcf(L.vph_f, t.vph);
   putf(L.tm_f, t.tm);
   putf(L.x_f, t.x);

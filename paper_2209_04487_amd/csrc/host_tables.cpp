@@ -64,14 +64,18 @@ MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double
     const double ph = -kap * kap * dt / (4.0 * mass);
     t.kin[m] = std::polar(1.0 / nr, ph);
   }
-  // four-step FFT twiddles: tw[x * R1 + y] = exp(-2 pi i x y / n_r), x, y < R1
-  const int r1 = fft_r1(nr);
-  t.tw.assign(static_cast<size_t>(r1) * r1, std::complex<double>(0.0, 0.0));
-  for (int x = 0; x < r1; ++x)
-    for (int y = 0; y < r1; ++y) {
-      const long e = (static_cast<long>(x) * y) % nr;
-      t.tw[static_cast<size_t>(x) * r1 + y] = std::polar(1.0, -2.0 * kPi * static_cast<double>(e) / nr);
-    }
+  // four-step FFT twiddles: tw[x * R1 + y] = exp(-2 pi i x y / n_r), x, y < R1,
+  // for the complex128 (tw) and complex64 (tw_f) splits of the grid
+  auto twiddles = [&](int r1, std::vector<std::complex<double>>& out) {
+    out.assign(static_cast<size_t>(r1) * r1, std::complex<double>(0.0, 0.0));
+    for (int x = 0; x < r1; ++x)
+      for (int y = 0; y < r1; ++y) {
+        const long e = (static_cast<long>(x) * y) % nr;
+        out[static_cast<size_t>(x) * r1 + y] = std::polar(1.0, -2.0 * kPi * static_cast<double>(e) / nr);
+      }
+  };
+  twiddles(fft_r1(nr, 8), t.tw);
+  twiddles(fft_r1(nr, 4), t.tw_f);
   t.vph.resize(static_cast<size_t>(2) * nj * nr);
   for (int s = 0; s < 2; ++s) {
     const double* U = (s == 0) ? U_g : U_e;

@@ -12,13 +12,16 @@ namespace msqd {
 struct MolTablesHost {
   double dr = 0.0;
   int kdiss = 0;
-  std::vector<std::complex<double>> kin, tw, vph;
+  std::vector<std::complex<double>> kin, tw, tw_f, vph;
   std::vector<double> tm, x, mudt, mask, mu, cj;
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // radix of the first in-register FFT pass for a radial grid of n_r points
-inline int fft_r1(int n_r) { return n_r == 64 ? 8 : (n_r == 512 ? 32 : 16); }
+// for a radial grid of n_r points and complex elements of el_bytes/2 per part
+constexpr int fft_r1(int n_r, int el_bytes) {
+  return n_r == 64 ? 8 : (n_r == 128 ? 16 : (n_r == 256 ? (el_bytes == 4 ? 32 : 16) : 32));
+}
 MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
                                const double* mu12);
 

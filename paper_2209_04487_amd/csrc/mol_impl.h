@@ -18,23 +18,23 @@
 #pragma once
 
 #include "fft_reg.h"
+#include "host_tables.h"
 #include "mol.h"
 
 namespace msqd {
 
-template <int NR>
-struct FftShape;
-template <>
-struct FftShape<64> { static constexpr int R1 = 8, R2 = 8; };
-template <>
-struct FftShape<128> { static constexpr int R1 = 16, R2 = 8; };
-template <>
-struct FftShape<256> { static constexpr int R1 = 16, R2 = 16; };
-template <>
-struct FftShape<512> { static constexpr int R1 = 32, R2 = 16; };
+// n_r = R1 * R2: each lane holds R1 values of a line, R2 lanes per line.
+// The split is the host's fft_r1(n_r, element bytes): complex64 lines use
+// longer in-register DFTs (fewer lanes and waves per molecule, more
+// molecules per CU); complex128 keeps R1 <= 16 within the register file.
+template <int NR, typename T>
+struct FftShape {
+  static constexpr int R1 = fft_r1(NR, static_cast<int>(sizeof(T)));
+  static constexpr int R2 = NR / R1;
+};
 
-template <int NR>
-constexpr int line_stride() { return NR + FftShape<NR>::R2; }
+template <int NR, typename T>
+constexpr int line_stride() { return NR + FftShape<NR, T>::R2; }
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -77,7 +77,7 @@ struct MolTabs {
 template <typename T, int NR>
 __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
                                              const cx<T>* __restrict__ tw2) {
-  constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2, U = R1 / R2, RS = R1 + 1;
+  constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2, RS = R1 + 1;
   // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
   dft<R1, false, T>(v);
 #pragma unroll
@@ -443,10 +443,12 @@ template <typename T>
 __device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
 
 // --------------------------------------------------------------- kernel
-// Occupancy target (waves per SIMD) of the fused step: the FP32 forms are
-// kept within 128 VGPRs so that two workgroups of up to 8 waves share a CU.
+// Occupancy target (waves per SIMD) of the fused step.  The FP32 forms
+// (three waves per molecule at J_max = 10, n_r = 256) run three molecules per
+// CU, bounded by LDS, within 168 VGPRs; the FP64 form is bounded by LDS (one
+// molecule of complex128 lines per CU) and may use 256 VGPRs.
 template <typename T>
-struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : 4; };
+struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : 3; };
 
 // coupling path: BF16 hi/lo split on 16x16x16 (mixed form) or the
 // working precision on 16x16x4 (FP32 and FP64 forms)
@@ -455,8 +457,8 @@ enum { kCpExact = 0, kCpBf16x3 = 1 };
 template <typename T, int NR, int CP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T>::waves)))
 void mol_step_kernel(MolArgs a) {
-  constexpr int R1 = FftShape<NR>::R1, R2 = FftShape<NR>::R2;
-  constexpr int LS = line_stride<NR>();
+  constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  constexpr int LS = line_stride<NR, T>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int nj = a.nj;
   const int L = 2 * nj;
@@ -599,12 +601,12 @@ void mol_step_kernel(MolArgs a) {
 
 template <typename T, int NR, int CP>
 int launch_mol_t(const MolArgs& a, hipStream_t s) {
-  static_assert(NR == FftShape<NR>::R1 * FftShape<NR>::R2, "FFT shape");
-  constexpr int R2 = FftShape<NR>::R2;
+  static_assert(NR == FftShape<NR, T>::R1 * FftShape<NR, T>::R2, "FFT shape");
+  constexpr int R2 = FftShape<NR, T>::R2;
   const int L = 2 * a.nj;
   int threads = ((L * R2 + 63) / 64) * 64;
   if (threads < 64) threads = 64;
-  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(L) * line_stride<NR>() + 16 * 4 * sizeof(double);
+  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(L) * line_stride<NR, T>() + 16 * 4 * sizeof(double);
   static bool attr_set = false;
   if (!attr_set && shm > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, CP>),
