@@ -212,6 +212,38 @@ typedef struct {
 int coupled_step(const cpl_desc* d, const cpl_state* s, const double* src_values, int64_t n0,
                  int32_t n_steps, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Adjoint of the coupled step (reverse mode), for gradients of the
+ * dissociated population Y = mean_i [sum_{r > r_diss} |psi_i|^2 dr +
+ * absorbed_i] with respect to the incident-field samples.
+ * For complex psi the adjoint is dY/dRe(psi) + i dY/dIm(psi).
+ * Supported in the MSQD_FP64 and MSQD_FP32 forms.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  void* lpsi;        /* adjoint of psi, same layout and type              */
+  double* labs;      /* [n_mol] adjoint of the absorbed norms             */
+  double* lP;        /* [n_occ] adjoint of the cell polarisation          */
+  double* ld;        /* [n_mol] scratch: adjoint of the step's dipoles    */
+  double* lE;        /* [n_mol] scratch: adjoint of the gathered fields   */
+  fdtd_fields lf;    /* adjoint fields (E, H, J_D, CPML psi); mat, dft unused */
+  void* scratch;     /* adjoint_scratch_bytes() of device memory          */
+} cpl_adj;
+
+size_t adjoint_scratch_bytes(const cpl_desc* d);
+
+/* Set the adjoint to dY/d(state) at the end of a run: lpsi = (2 dr/n_mol) psi
+ * for r > r_diss, labs = 1/n_mol, everything else 0.  s->psi is the final
+ * wavepacket. */
+int adjoint_init_yield(const cpl_desc* d, const cpl_state* s, cpl_adj* adj, void* stream);
+
+/* One reverse step n: with adj holding dY/d(state after step n), overwrite
+ * it with dY/d(state before step n) and write g_src[0] = dY/dsrc_value[n]
+ * (device float64).  psi_n and E_mol_n are the wavepackets before step n
+ * and the field it gathered (recorded by a forward recompute); s supplies the
+ * maps, tables and material map of the forward system. */
+int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, const double* E_mol_n,
+                 cpl_adj* adj, int64_t n, double* g_src, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,606 @@
+// Reverse-mode (adjoint) kernels of the coupled step: the exact transpose of
+// every linear factor (Yee curls with their CPML recursions, the Drude
+// recurrence, the source sheet, the per-cell dipole sum and the field
+// gather), and the adjoint of the molecular split-operator step, including
+// the derivative of the dipole-coupling rotation with respect to the field.
+//
+// Conventions: for a complex state psi the adjoint is
+// lambda = dY/dRe(psi) + i dY/dIm(psi), so a complex-linear factor U maps
+// lambda' to U^H lambda'.
+#include "adjoint.h"
+#include "mol_impl.h"
+
+namespace msqd {
+
+// ------------------------------------------------------------ molecules
+// Adjoint of the coupling at one radial point.  A holds chi (the coupling's
+// input), B holds the adjoint at its output and receives the adjoint at its
+// input.  Phi = T chi, Phi' = R(phi) Phi; Lambda = T lambda_out;
+// dY/dE += sum_k mu12 x_k dt * (-Im[conj(L_g) Phi'_e + conj(L_e) Phi'_g]);
+// lambda_in = T^T R(-phi) Lambda.
+template <typename T>
+__device__ __forceinline__ double coupling_point_adj(const cx<T>* A, cx<T>* B, int LS, int r, int nj,
+                                                     const T* __restrict__ tm, const T* __restrict__ x,
+                                                     T md) {
+  cx<T> ag[kMaxNJ], ae[kMaxNJ];
+#pragma unroll
+  for (int J = 0; J < kMaxNJ; ++J) {
+    ag[J] = {T(0), T(0)};
+    ae[J] = {T(0), T(0)};
+  }
+  double grad = 0.0;
+  for (int k = 0; k < nj; ++k) {
+    cx<T> Lg = {T(0), T(0)}, Le = {T(0), T(0)}, Pg = {T(0), T(0)}, Pe = {T(0), T(0)};
+    for (int J = 0; J < nj; ++J) {
+      const T t = tm[k * nj + J];
+      Lg = Lg + cscale(B[J * LS + r], t);
+      Le = Le + cscale(B[(nj + J) * LS + r], t);
+      Pg = Pg + cscale(A[J * LS + r], t);
+      Pe = Pe + cscale(A[(nj + J) * LS + r], t);
+    }
+    T sn, vs;
+    sin_vers(md * x[k], &sn, &vs);
+    const T c = T(1) - vs;
+    // Phi' = R(phi) Phi
+    const cx<T> Qg = {c * Pg.x - sn * Pe.y, c * Pg.y + sn * Pe.x};
+    const cx<T> Qe = {c * Pe.x - sn * Pg.y, c * Pe.y + sn * Pg.x};
+    // -Im[conj(L_g) Q_e + conj(L_e) Q_g]
+    const double im = static_cast<double>(Lg.x * Qe.y - Lg.y * Qe.x) +
+                      static_cast<double>(Le.x * Qg.y - Le.y * Qg.x);
+    grad -= static_cast<double>(x[k]) * im;
+    // R(-phi) Lambda: [c L_g - i s L_e, -i s L_g + c L_e]
+    const cx<T> Rg = {c * Lg.x + sn * Le.y, c * Lg.y - sn * Le.x};
+    const cx<T> Re = {c * Le.x + sn * Lg.y, c * Le.y - sn * Lg.x};
+#pragma unroll
+    for (int J = 0; J < kMaxNJ; ++J) {
+      if (J < nj) {
+        const T t = tm[k * nj + J];
+        ag[J] = ag[J] + cscale(Rg, t);
+        ae[J] = ae[J] + cscale(Re, t);
+      }
+    }
+  }
+#pragma unroll
+  for (int J = 0; J < kMaxNJ; ++J) {
+    if (J < nj) {
+      B[J * LS + r] = ag[J];
+      B[(nj + J) * LS + r] = ae[J];
+    }
+  }
+  return grad;
+}
+
+// forward coupling (full form, VALU) from A into B, used by the recompute
+template <typename T>
+__device__ __forceinline__ void coupling_point_fwd(const cx<T>* A, cx<T>* B, int LS, int r, int nj,
+                                                   const T* __restrict__ tm, const T* __restrict__ x,
+                                                   T md) {
+  cx<T> ag[kMaxNJ], ae[kMaxNJ];
+#pragma unroll
+  for (int J = 0; J < kMaxNJ; ++J) {
+    ag[J] = {T(0), T(0)};
+    ae[J] = {T(0), T(0)};
+  }
+  for (int k = 0; k < nj; ++k) {
+    cx<T> Pg = {T(0), T(0)}, Pe = {T(0), T(0)};
+    for (int J = 0; J < nj; ++J) {
+      const T t = tm[k * nj + J];
+      Pg = Pg + cscale(A[J * LS + r], t);
+      Pe = Pe + cscale(A[(nj + J) * LS + r], t);
+    }
+    T sn, vs;
+    sin_vers(md * x[k], &sn, &vs);
+    const T c = T(1) - vs;
+    const cx<T> Qg = {c * Pg.x - sn * Pe.y, c * Pg.y + sn * Pe.x};
+    const cx<T> Qe = {c * Pe.x - sn * Pg.y, c * Pe.y + sn * Pg.x};
+#pragma unroll
+    for (int J = 0; J < kMaxNJ; ++J) {
+      if (J < nj) {
+        const T t = tm[k * nj + J];
+        ag[J] = ag[J] + cscale(Qg, t);
+        ae[J] = ae[J] + cscale(Qe, t);
+      }
+    }
+  }
+#pragma unroll
+  for (int J = 0; J < kMaxNJ; ++J) {
+    if (J < nj) {
+      B[J * LS + r] = ag[J];
+      B[(nj + J) * LS + r] = ae[J];
+    }
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
+  constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  constexpr int LS = line_stride<NR, T>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nj = a.nj;
+  const int L = 2 * nj;
+  cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* B = A + L * LS;
+  double* red = reinterpret_cast<double*>(smem + 2 * sizeof(cx<T>) * L * LS);
+  const int mol = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int line = tid / R2;
+  const int q = tid - line * R2;
+  const bool active = line < L;
+  const int s_of_line = line / (nj > 0 ? nj : 1);
+  const int J_of_line = line - s_of_line * nj;
+
+  const char* ws = a.ws;
+  const bool dbl = sizeof(T) == 8;
+  const cx<T>* kin = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.kin_d : a.lay.kin_f));
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.tw_d : a.lay.tw_f));
+  const cx<T>* vph = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.vph_d : a.lay.vph_f));
+  const T* tm = reinterpret_cast<const T*>(ws + (dbl ? a.lay.tm_d : a.lay.tm_f));
+  const T* xk = reinterpret_cast<const T*>(ws + (dbl ? a.lay.x_d : a.lay.x_f));
+  const T* mudt = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mudt_d : a.lay.mudt_f));
+  const T* mask = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mask_d : a.lay.mask_f));
+  const double* mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
+  const double* cj = reinterpret_cast<const double*>(ws + a.lay.cj_d);
+
+  const T E = static_cast<T>(a.E_mol[mol]);
+  const size_t base = static_cast<size_t>(mol) * L * NR;
+  const cx<T>* psi = reinterpret_cast<const cx<T>*>(a.psi_n) + base;
+  cx<T>* lpsi = reinterpret_cast<cx<T>*>(a.lpsi) + base;
+  cx<T>* slot = B + line * LS;
+  const int loff = line * NR + q;
+
+  // ---- forward recompute: chi = V K psi -> A; psi_pre = K V C(chi)
+  cx<T> v[R1];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) v[p] = psi[loff + R2 * p];
+    kinetic_half<T, NR>(v, slot, q, kin, tw);
+#pragma unroll
+    for (int p = 0; p < R1; ++p) A[line * LS + q + R2 * p] = cmul(v[p], vph[loff + R2 * p]);
+  }
+  __syncthreads();
+  for (int r = tid; r < NR; r += nthr) coupling_point_fwd<T>(A, B, LS, r, nj, tm, xk, mudt[r] * E);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) v[p] = cmul(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
+    kinetic_half<T, NR>(v, slot, q, kin, tw);       // v = psi_pre (before the absorber)
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = cscale(v[p], mask[q + R2 * p]);
+  }
+  __syncthreads();
+
+  // ---- reverse: dipole and absorber terms, then K^H V^H
+  const double ld = a.ld ? a.ld[mol] : 0.0;
+  const double lab = a.labs[mol];
+  cx<T> lam[R1];
+  if (active) {
+    const int sb = 1 - s_of_line;
+    const T cjm = (J_of_line > 0) ? static_cast<T>(cj[J_of_line - 1]) : T(0);
+    const T cjp = (J_of_line + 1 < nj) ? static_cast<T>(cj[J_of_line]) : T(0);
+    const T fd = static_cast<T>(2.0 * a.dr * ld);
+    const T fa = static_cast<T>(2.0 * a.dr * lab);
+#pragma unroll
+    for (int p = 0; p < R1; ++p) {
+      const int r = q + R2 * p;
+      cx<T> l = lpsi[loff + R2 * p];
+      // D psi' with D = mu12(r) <J|cos|J'> sigma_x
+      cx<T> dpsi = {T(0), T(0)};
+      if (J_of_line > 0) dpsi = dpsi + cscale(B[(sb * nj + J_of_line - 1) * LS + r], cjm);
+      if (J_of_line + 1 < nj) dpsi = dpsi + cscale(B[(sb * nj + J_of_line + 1) * LS + r], cjp);
+      l = l + cscale(dpsi, fd * static_cast<T>(mu[r]));
+      const T m = mask[r];
+      l = cscale(l, m) + cscale(v[p], fa * (T(1) - m * m));
+      lam[p] = l;
+    }
+  }
+  __syncthreads();
+  if (active) {
+    kinetic_half<T, NR, true>(lam, slot, q, kin, tw);
+#pragma unroll
+    for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = cmul_conj(lam[p], vph[loff + R2 * p]);
+  }
+  __syncthreads();
+  double grad = 0.0;
+  for (int r = tid; r < NR; r += nthr)
+    grad += static_cast<double>(mudt[r]) * coupling_point_adj<T>(A, B, LS, r, nj, tm, xk, mudt[r] * E);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) lam[p] = cmul_conj(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
+  }
+  __syncthreads();
+  if (active) {
+    kinetic_half<T, NR, true>(lam, slot, q, kin, tw);
+#pragma unroll
+    for (int p = 0; p < R1; ++p) lpsi[loff + R2 * p] = lam[p];
+  }
+  double sums[4] = {grad, 0.0, 0.0, 0.0};
+  block_sum4(sums, red);
+  if (tid == 0) a.lE[mol] = sums[0];
+}
+
+size_t mol_adj_lds_bytes(int n_r, int nj, bool f32) {
+  const size_t el = f32 ? 8 : 16;
+  const int r2 = n_r / fft_r1(n_r, static_cast<int>(el / 2));
+  return 2 * el * static_cast<size_t>(2 * nj) * (n_r + r2) + 16 * 4 * sizeof(double);
+}
+
+template <typename T, int NR>
+static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
+  constexpr int R2 = FftShape<NR, T>::R2;
+  const int L = 2 * a.nj;
+  int threads = ((L * R2 + 63) / 64) * 64;
+  if (threads < 64) threads = 64;
+  const size_t shm = mol_adj_lds_bytes(NR, a.nj, sizeof(T) == 4);
+  static bool attr_set = false;
+  if (!attr_set && shm > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(mol_lds_limit()));
+    (void)hipGetLastError();
+    if (e != hipSuccess) return static_cast<int>(e);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((mol_adj_kernel<T, NR>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_mol_adj(const MolAdjArgs& a, int n_r, bool f32, hipStream_t s) {
+  if (f32) {
+    switch (n_r) {
+      case 64: return launch_mol_adj_t<float, 64>(a, s);
+      case 128: return launch_mol_adj_t<float, 128>(a, s);
+      case 256: return launch_mol_adj_t<float, 256>(a, s);
+      case 512: return launch_mol_adj_t<float, 512>(a, s);
+      default: break;
+    }
+  } else {
+    switch (n_r) {
+      case 64: return launch_mol_adj_t<double, 64>(a, s);
+      case 128: return launch_mol_adj_t<double, 128>(a, s);
+      case 256: return launch_mol_adj_t<double, 256>(a, s);
+      case 512: return launch_mol_adj_t<double, 512>(a, s);
+      default: break;
+    }
+  }
+  return static_cast<int>(hipErrorInvalidValue);
+}
+
+// ----------------------------------------------------------------- fields
+template <typename T>
+struct AdjPtr {
+  T *Ex, *Ey, *Ez, *Hx, *Hy, *Hz, *JDx, *JDy, *JDz, *psi;
+};
+template <typename T>
+__device__ __forceinline__ AdjPtr<T> adj_ptrs(const FdArgs& a) {
+  return {static_cast<T*>(a.Ex),  static_cast<T*>(a.Ey),  static_cast<T*>(a.Ez),
+          static_cast<T*>(a.Hx),  static_cast<T*>(a.Hy),  static_cast<T*>(a.Hz),
+          static_cast<T*>(a.JDx), static_cast<T*>(a.JDy), static_cast<T*>(a.JDz),
+          static_cast<T*>(a.psi)};
+}
+
+__device__ __forceinline__ int pml_plane_a(int k, int nz, int npml) {
+  if (k < npml) return k;
+  if (k >= nz - npml) return npml + (k - (nz - npml));
+  return -1;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* prof_a(const FdArgs& a, size_t off_d, size_t off_f) {
+  if constexpr (sizeof(T) == 8)
+    return reinterpret_cast<const T*>(a.ws + off_d);
+  else
+    return reinterpret_cast<const T*>(a.ws + off_f);
+}
+
+// E update, first half: with lambda' after the update, form lambda before it
+// for E, J_D and the CPML auxiliaries, and the adjoints of the six H
+// differences (scratch b_zy, b_zx, b_yz, b_xz, b_yx, b_xy).
+template <typename T>
+__global__ __launch_bounds__(256) void yee_e_adj_k1(FdAdjArgs aa) {
+  const FdArgs& a = aa.f;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int k = static_cast<int>(idx / (static_cast<long>(nx) * ny));
+  AdjPtr<T> f = adj_ptrs<T>(a);
+  T* sc = static_cast<T*>(aa.scratch);
+  T* E[3] = {f.Ex, f.Ey, f.Ez};
+  T* JD[3] = {f.JDx, f.JDy, f.JDz};
+  T lcurl[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int m = a.mat[c * n + idx];
+    T le = E[c][idx];
+    if (c < 2 && k == 0) le = T(0);  // those components are held at zero
+    const T ce = static_cast<T>(a.ce[m & 3]);
+    lcurl[c] = ce * le;
+    T lE = le;
+    if (m == a.metal_id) {
+      const T ljd = JD[c][idx] - ce * le;
+      JD[c][idx] = static_cast<T>(a.alpha_d) * ljd;
+      lE += static_cast<T>(a.beta_d) * ljd;
+    }
+    E[c][idx] = lE;
+  }
+  // curl_x = dHz_dy - dHy_dz~, curl_y = dHx_dz~ - dHz_dx, curl_z = dHy_dx - dHx_dy
+  T b_zy = lcurl[0], b_yz = -lcurl[0], b_xz = lcurl[1], b_zx = -lcurl[1];
+  const T b_yx = lcurl[2], b_xy = -lcurl[2];
+  const int kk = pml_plane_a(k, nz, a.npml);
+  if (kk >= 0) {
+    const T b = prof_a<T>(a, a.lay.bE, a.lay.bEf)[k];
+    const T c = prof_a<T>(a, a.lay.aE, a.lay.aEf)[k];
+    const T ki = prof_a<T>(a, a.lay.kE, a.lay.kEf)[k];
+    const long plane = static_cast<long>(nx) * ny;
+    const long np = 2L * a.npml * plane;
+    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    T* psiEx = f.psi;
+    T* psiEy = f.psi + np;
+    const T tx = psiEx[o] + b_yz;   // adjoint of psi_Ex' (total)
+    const T ty = psiEy[o] + b_xz;
+    psiEx[o] = b * tx;
+    psiEy[o] = b * ty;
+    b_yz = ki * b_yz + c * tx;
+    b_xz = ki * b_xz + c * ty;
+  }
+  sc[0 * n + idx] = b_zy;
+  sc[1 * n + idx] = b_zx;
+  sc[2 * n + idx] = b_yz;
+  sc[3 * n + idx] = b_xz;
+  sc[4 * n + idx] = b_yx;
+  sc[5 * n + idx] = b_xy;
+}
+
+// E update, second half: lambda_H += curl^T of the difference adjoints.
+template <typename T>
+__global__ __launch_bounds__(256) void yee_e_adj_k2(FdAdjArgs aa) {
+  const FdArgs& a = aa.f;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = static_cast<int>(idx % nx);
+  const long jk = idx / nx;
+  const int j = static_cast<int>(jk % ny);
+  const int k = static_cast<int>(jk / ny);
+  const long sy = nx, sz = static_cast<long>(nx) * ny;
+  const long ip = (i + 1 == nx) ? idx - (nx - 1) : idx + 1;
+  const long jp = (j + 1 == ny) ? idx - static_cast<long>(ny - 1) * sy : idx + sy;
+  AdjPtr<T> f = adj_ptrs<T>(a);
+  const T* sc = static_cast<const T*>(aa.scratch);
+  const T inv_dx = static_cast<T>(a.inv_dx);
+  const T* b_zy = sc;
+  const T* b_zx = sc + n;
+  const T* b_yz = sc + 2 * n;
+  const T* b_xz = sc + 3 * n;
+  const T* b_yx = sc + 4 * n;
+  const T* b_xy = sc + 5 * n;
+  // dHz_dy(c) = Hz[c] - Hz[c - y]; dHz_dx(c) = Hz[c] - Hz[c - x]
+  f.Hz[idx] += (b_zy[idx] - b_zy[jp] + b_zx[idx] - b_zx[ip]) * inv_dx;
+  // dHy_dz(c) = Hy[c] - Hy[c - z] (Hy below k = 0 is zero); dHy_dx(c) = Hy[c] - Hy[c - x]
+  const T yz_up = (k + 1 < nz) ? b_yz[idx + sz] : T(0);
+  f.Hy[idx] += (b_yz[idx] - yz_up + b_yx[idx] - b_yx[ip]) * inv_dx;
+  const T xz_up = (k + 1 < nz) ? b_xz[idx + sz] : T(0);
+  f.Hx[idx] += (b_xz[idx] - xz_up + b_xy[idx] - b_xy[jp]) * inv_dx;
+}
+
+// H update, first half: difference adjoints a_* and the CPML auxiliaries.
+template <typename T>
+__global__ __launch_bounds__(256) void yee_h_adj_k1(FdAdjArgs aa) {
+  const FdArgs& a = aa.f;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int k = static_cast<int>(idx / (static_cast<long>(nx) * ny));
+  AdjPtr<T> f = adj_ptrs<T>(a);
+  T* sc = static_cast<T*>(aa.scratch);
+  const T cH = static_cast<T>(a.cH);
+  const T lhx = f.Hx[idx], lhy = f.Hy[idx], lhz = f.Hz[idx];
+  // Hx' = Hx - cH (dEz_dy - dEy_dz~); Hy' = Hy - cH (dEx_dz~ - dEz_dx);
+  // Hz' = Hz - cH (dEy_dx - dEx_dy)
+  const T a_zy = -cH * lhx;
+  T a_yz = cH * lhx;
+  T a_xz = -cH * lhy;
+  const T a_zx = cH * lhy;
+  const T a_yx = -cH * lhz;
+  const T a_xy = cH * lhz;
+  const int kk = pml_plane_a(k, nz, a.npml);
+  if (kk >= 0) {
+    const T b = prof_a<T>(a, a.lay.bH, a.lay.bHf)[k];
+    const T c = prof_a<T>(a, a.lay.aH, a.lay.aHf)[k];
+    const T ki = prof_a<T>(a, a.lay.kH, a.lay.kHf)[k];
+    const long plane = static_cast<long>(nx) * ny;
+    const long np = 2L * a.npml * plane;
+    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    T* psiHx = f.psi + 2 * np;
+    T* psiHy = f.psi + 3 * np;
+    const T tx = psiHx[o] + a_yz;
+    const T ty = psiHy[o] + a_xz;
+    psiHx[o] = b * tx;
+    psiHy[o] = b * ty;
+    a_yz = ki * a_yz + c * tx;
+    a_xz = ki * a_xz + c * ty;
+  }
+  sc[0 * n + idx] = a_zy;
+  sc[1 * n + idx] = a_zx;
+  sc[2 * n + idx] = a_yz;
+  sc[3 * n + idx] = a_xz;
+  sc[4 * n + idx] = a_yx;
+  sc[5 * n + idx] = a_xy;
+}
+
+// H update, second half: lambda_E += curl^T of the difference adjoints.
+template <typename T>
+__global__ __launch_bounds__(256) void yee_h_adj_k2(FdAdjArgs aa) {
+  const FdArgs& a = aa.f;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long n = static_cast<long>(nx) * ny * nz;
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = static_cast<int>(idx % nx);
+  const long jk = idx / nx;
+  const int j = static_cast<int>(jk % ny);
+  const int k = static_cast<int>(jk / ny);
+  const long sy = nx, sz = static_cast<long>(nx) * ny;
+  const long im = (i == 0) ? idx + (nx - 1) : idx - 1;
+  const long jm = (j == 0) ? idx + static_cast<long>(ny - 1) * sy : idx - sy;
+  AdjPtr<T> f = adj_ptrs<T>(a);
+  const T* sc = static_cast<const T*>(aa.scratch);
+  const T inv_dx = static_cast<T>(a.inv_dx);
+  const T* a_zy = sc;
+  const T* a_zx = sc + n;
+  const T* a_yz = sc + 2 * n;
+  const T* a_xz = sc + 3 * n;
+  const T* a_yx = sc + 4 * n;
+  const T* a_xy = sc + 5 * n;
+  // dEz_dy(c) = Ez[c + y] - Ez[c]; dEz_dx(c) = Ez[c + x] - Ez[c]
+  f.Ez[idx] += (a_zy[jm] - a_zy[idx] + a_zx[im] - a_zx[idx]) * inv_dx;
+  // dEy_dz(c) = Ey[c + z] - Ey[c] (Ey above the top is zero); dEy_dx(c) = Ey[c + x] - Ey[c]
+  const T yz_dn = (k > 0) ? a_yz[idx - sz] : T(0);
+  f.Ey[idx] += (yz_dn - a_yz[idx] + a_yx[im] - a_yx[idx]) * inv_dx;
+  const T xz_dn = (k > 0) ? a_xz[idx - sz] : T(0);
+  f.Ex[idx] += (xz_dn - a_xz[idx] + a_xy[jm] - a_xy[idx]) * inv_dx;
+}
+
+int launch_yee_e_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
+  const long n = static_cast<long>(a.f.nx) * a.f.ny * a.f.nz;
+  const int blocks = static_cast<int>((n + 255) / 256);
+  if (f32) {
+    hipLaunchKernelGGL(yee_e_adj_k1<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_e_adj_k2<float>, dim3(blocks), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(yee_e_adj_k1<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_e_adj_k2<double>, dim3(blocks), dim3(256), 0, s, a);
+  }
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_yee_h_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
+  const long n = static_cast<long>(a.f.nx) * a.f.ny * a.f.nz;
+  const int blocks = static_cast<int>((n + 255) / 256);
+  if (f32) {
+    hipLaunchKernelGGL(yee_h_adj_k1<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_adj_k2<float>, dim3(blocks), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(yee_h_adj_k1<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_adj_k2<double>, dim3(blocks), dim3(256), 0, s, a);
+  }
+  return static_cast<int>(hipGetLastError());
+}
+
+// g = coef * sum over the source plane of ce[mat] lambda_Ex, fixed-order tree
+template <typename T>
+__global__ __launch_bounds__(256) void src_grad_kernel(FdArgs a, double coef, double* g_out) {
+  __shared__ double red[256];
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const long n = plane * a.nz;
+  const long o = static_cast<long>(a.src_k) * plane;
+  const T* lEx = static_cast<const T*>(a.Ex);
+  double s = 0.0;
+  for (long p = threadIdx.x; p < plane; p += blockDim.x)
+    s += a.ce[a.mat[o + p] & 3] * static_cast<double>(lEx[o + p]);
+  (void)n;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g_out[0] = coef * red[0];
+}
+
+int launch_src_grad(const FdArgs& lam, double coef, double* g_out, bool f32, hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL(src_grad_kernel<float>, dim3(1), dim3(256), 0, s, lam, coef, g_out);
+  else
+    hipLaunchKernelGGL(src_grad_kernel<double>, dim3(1), dim3(256), 0, s, lam, coef, g_out);
+  return static_cast<int>(hipGetLastError());
+}
+
+// -------------------------------------------------------------- coupling
+// Forward: E_x[cell] -= ce (P' - P)/dt with P' = pfac sum_i d_i.
+template <typename T>
+__global__ __launch_bounds__(256) void deposit_adj_kernel(CplAdjArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_occ) return;
+  const int cell = a.occ_cell[c];
+  const double ce = a.ce[a.mat[cell] & 3];
+  const double lex = static_cast<double>(static_cast<const T*>(a.lEx)[cell]);
+  const double lp_new = a.lP[c] - ce * a.inv_dt * lex;
+  a.lP[c] = ce * a.inv_dt * lex;
+  const double ldv = a.pfac * lp_new;
+  for (int t = a.occ_ptr[c]; t < a.occ_ptr[c + 1]; ++t) a.ld[a.mol_perm[t]] = ldv;
+}
+
+// Forward: E_mol,i = E_x[cell(i)] / E_au.
+template <typename T>
+__global__ __launch_bounds__(256) void gather_adj_kernel(CplAdjArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_occ) return;
+  double s = 0.0;
+  for (int t = a.occ_ptr[c]; t < a.occ_ptr[c + 1]; ++t) s += a.lE[a.mol_perm[t]];
+  T* lEx = static_cast<T*>(a.lEx);
+  const int cell = a.occ_cell[c];
+  lEx[cell] = lEx[cell] + static_cast<T>(s * a.inv_eau);
+}
+
+int launch_deposit_adj(const CplAdjArgs& a, bool f32, hipStream_t s) {
+  if (a.n_occ <= 0) return 0;
+  const int blocks = (a.n_occ + 255) / 256;
+  if (f32)
+    hipLaunchKernelGGL(deposit_adj_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(deposit_adj_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_gather_adj(const CplAdjArgs& a, bool f32, hipStream_t s) {
+  if (a.n_occ <= 0) return 0;
+  const int blocks = (a.n_occ + 255) / 256;
+  if (f32)
+    hipLaunchKernelGGL(gather_adj_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(gather_adj_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+// ------------------------------------------------------------- objective
+template <typename T>
+__global__ __launch_bounds__(256) void yield_adj_init_kernel(cx<T>* lpsi, double* labs, const cx<T>* psi,
+                                                             int n_mol, int lines, int n_r, int kdiss,
+                                                             double dr, double scale) {
+  const size_t per = static_cast<size_t>(lines) * n_r;
+  const size_t total = per * n_mol;
+  const T f = static_cast<T>(2.0 * dr * scale);
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int r = static_cast<int>(t % n_r);
+    lpsi[t] = (r >= kdiss) ? cscale(psi[t], f) : cx<T>{T(0), T(0)};
+    if (t % per == 0) labs[t / per] = scale;
+  }
+}
+
+int launch_yield_adj_init(void* lpsi, double* labs, const void* psi, int n_mol, int lines, int n_r,
+                          int kdiss, double dr, double scale, bool f32, hipStream_t s) {
+  const size_t total = static_cast<size_t>(lines) * n_r * n_mol;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return 0;
+  if (f32)
+    hipLaunchKernelGGL(yield_adj_init_kernel<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<cx<float>*>(lpsi), labs, static_cast<const cx<float>*>(psi), n_mol,
+                       lines, n_r, kdiss, dr, scale);
+  else
+    hipLaunchKernelGGL(yield_adj_init_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<cx<double>*>(lpsi), labs, static_cast<const cx<double>*>(psi), n_mol,
+                       lines, n_r, kdiss, dr, scale);
+  return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace msqd

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "fdtd.h"
 #include "host_tables.h"
 #include "mol.h"
@@ -626,6 +627,128 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
     if (rc) return rc;
   }
+  return MSQD_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+size_t adjoint_scratch_bytes(const cpl_desc* d) {
+  if (!d || check_fd(&d->fd) != MSQD_OK) return 0;
+  const size_t el = d->fd.prec == MSQD_FP64 ? 8 : 4;
+  return 6 * static_cast<size_t>(d->fd.nx) * d->fd.ny * d->fd.nz * el;
+}
+
+static int check_adj(const cpl_desc* d, const cpl_state* st, const cpl_adj* adj) {
+  if (!d || !st || !adj) return fail(MSQD_EINVAL, "NULL descriptor, state or adjoint");
+  int rc = check_qd(&d->qd);
+  if (rc) return rc;
+  rc = check_fd(&d->fd);
+  if (rc) return rc;
+  if (d->qd.prec == MSQD_MIXED || d->fd.prec == MSQD_MIXED)
+    return fail(MSQD_EUNSUP, "the adjoint is provided for the FP64 and FP32 forms");
+  if (d->qd.prec != d->fd.prec) return fail(MSQD_EPREC, "molecule and field precision differ");
+  const fdtd_fields& f = adj->lf;
+  const void* ptrs[] = {f.Ex, f.Ey, f.Ez, f.Hx, f.Hy, f.Hz, f.JDx, f.JDy, f.JDz, f.psi, adj->scratch};
+  for (const void* p : ptrs)
+    if (!p || !aligned16(p)) return fail(MSQD_EINVAL, "adjoint field pointer NULL or misaligned");
+  if (d->qd.n_mol > 0 && (!adj->lpsi || !adj->labs || !adj->ld || !adj->lE))
+    return fail(MSQD_EINVAL, "adjoint molecule pointer NULL");
+  if (d->n_occ > 0 && !adj->lP) return fail(MSQD_EINVAL, "adjoint polarisation pointer NULL");
+  if (!st->f.mat || !st->fd_ws) return fail(MSQD_EINVAL, "forward material map or workspace NULL");
+  const size_t need = mol_adj_lds_bytes(d->qd.n_r, d->qd.j_max + 1, d->qd.prec != MSQD_FP64);
+  if (need > mol_lds_limit())
+    return fail(MSQD_EUNSUP, "n_r x (j_max+1) too large for the adjoint molecular kernel's LDS");
+  return MSQD_OK;
+}
+
+int adjoint_init_yield(const cpl_desc* d, const cpl_state* st, cpl_adj* adj, void* stream) {
+  int rc = check_adj(d, st, adj);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const fdtd_desc* fd = &d->fd;
+  const size_t n = static_cast<size_t>(fd->nx) * fd->ny * fd->nz;
+  const size_t el = fd->prec == MSQD_FP64 ? 8 : 4;
+  void* arrs[] = {adj->lf.Ex, adj->lf.Ey, adj->lf.Ez, adj->lf.Hx, adj->lf.Hy, adj->lf.Hz,
+                  adj->lf.JDx, adj->lf.JDy, adj->lf.JDz};
+  for (void* p : arrs) {
+    const int e = launch_fill_zero(p, n * el, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "adjoint zero fill");
+  }
+  int e = launch_fill_zero(adj->lf.psi, fdtd_psi_bytes(fd), s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "adjoint CPML zero fill");
+  if (d->n_occ > 0) {
+    e = launch_fill_zero(adj->lP, sizeof(double) * d->n_occ, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "adjoint polarisation zero fill");
+  }
+  if (d->qd.n_mol > 0) {
+    const MolArgs ma = make_mol_args(&d->qd, st->qd_ws);
+    e = launch_yield_adj_init(adj->lpsi, adj->labs, st->psi, d->qd.n_mol, 2 * (d->qd.j_max + 1), d->qd.n_r,
+                              ma.kdiss, ma.dr, 1.0 / d->qd.n_mol, d->qd.prec != MSQD_FP64, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "adjoint objective init");
+  }
+  return MSQD_OK;
+}
+
+int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, const double* E_mol_n,
+                 cpl_adj* adj, int64_t n, double* g_src, void* stream) {
+  int rc = check_adj(d, st, adj);
+  if (rc) return rc;
+  if (!g_src) return fail(MSQD_EINVAL, "g_src NULL");
+  if (d->qd.n_mol > 0 && (!psi_n || !E_mol_n)) return fail(MSQD_EINVAL, "recorded state NULL");
+  (void)n;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f32 = d->fd.prec != MSQD_FP64;
+  FdArgs lam = make_fd_args(&d->fd, &adj->lf, st->fd_ws);
+  lam.mat = st->f.mat;
+  FdAdjArgs fa{lam, adj->scratch};
+  CplAdjArgs ca{};
+  ca.n_occ = d->n_occ;
+  ca.pfac = d->mol_weight * kEa0 / (d->fd.dx * d->fd.dx * d->fd.dx);
+  ca.inv_dt = 1.0 / d->fd.dt;
+  ca.inv_eau = 1.0 / kEau;
+  for (int m = 0; m < 4; ++m) ca.ce[m] = d->fd.dt / (kEps0 * d->fd.eps_r[m]);
+  ca.occ_cell = st->occ_cell;
+  ca.occ_ptr = st->occ_ptr;
+  ca.mol_perm = st->mol_perm;
+  ca.mat = st->f.mat;
+  ca.lP = adj->lP;
+  ca.ld = adj->ld;
+  ca.lE = adj->lE;
+  ca.lEx = adj->lf.Ex;
+  // reverse order of the forward step: deposit, E update, molecules, gather, H update
+  int e = launch_src_grad(lam, 2.0 / (kEta0 * d->fd.dx), g_src, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "source gradient launch");
+  if (d->qd.n_mol > 0 && d->n_occ > 0) {
+    e = launch_deposit_adj(ca, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "deposit adjoint launch");
+  }
+  e = launch_yee_e_adj(fa, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "E adjoint launch");
+  if (d->qd.n_mol > 0) {
+    if (d->n_occ == 0) {
+      e = launch_fill_zero(adj->ld, sizeof(double) * d->qd.n_mol, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "dipole adjoint zero fill");
+    }
+    const MolArgs m = make_mol_args(&d->qd, st->qd_ws);
+    MolAdjArgs ma{};
+    ma.n_mol = d->qd.n_mol;
+    ma.nj = m.nj;
+    ma.kdiss = m.kdiss;
+    ma.dr = m.dr;
+    ma.psi_n = psi_n;
+    ma.E_mol = E_mol_n;
+    ma.lpsi = adj->lpsi;
+    ma.labs = adj->labs;
+    ma.ld = adj->ld;
+    ma.lE = adj->lE;
+    ma.ws = m.ws;
+    ma.lay = m.lay;
+    e = launch_mol_adj(ma, d->qd.n_r, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "molecular adjoint launch");
+    e = launch_gather_adj(ca, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "gather adjoint launch");
+  }
+  e = launch_yee_h_adj(fa, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "H adjoint launch");
   return MSQD_OK;
 }
 

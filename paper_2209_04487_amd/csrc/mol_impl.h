@@ -74,7 +74,7 @@ struct MolTabs {
 // inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
 // x, y < R1, so that every table access is a uniform base plus one lane
 // offset plus an immediate.
-template <typename T, int NR>
+template <typename T, int NR, bool CONJ = false>
 __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
                                              const cx<T>* __restrict__ tw2) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2, RS = R1 + 1;
@@ -94,7 +94,7 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
     for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + a];
     dft<R2, false, T>(w);
 #pragma unroll
-    for (int b = 0; b < R2; ++b) w[b] = cmul(w[b], kin[a + R1 * b]);
+    for (int b = 0; b < R2; ++b) w[b] = CONJ ? cmul_conj(w[b], kin[a + R1 * b]) : cmul(w[b], kin[a + R1 * b]);
     dft<R2, true, T>(w);
 #pragma unroll
     for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);

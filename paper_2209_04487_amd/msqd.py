@@ -33,7 +33,7 @@ EA0 = 8.4783536255e-30
 EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
-           "coupled_step"]
+           "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step"]
 
 
 class MsqdError(RuntimeError):
@@ -85,6 +85,11 @@ class cpl_state(C.Structure):
                 ("fd_ws", C.c_void_p)]
 
 
+class cpl_adj(C.Structure):
+    _fields_ = [("lpsi", C.c_void_p), ("labs", C.c_void_p), ("lP", C.c_void_p), ("ld", C.c_void_p),
+                ("lE", C.c_void_p), ("lf", fdtd_fields), ("scratch", C.c_void_p)]
+
+
 _vp, _dp, _i32p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
 _sigs = {
     "msqd_last_error": (C.c_char_p, []),
@@ -107,6 +112,11 @@ _sigs = {
     "map_csr": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
     "coupled_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _dp, C.c_int64,
                                C.c_int32, _vp]),
+    "adjoint_scratch_bytes": (C.c_size_t, [C.POINTER(cpl_desc)]),
+    "adjoint_init_yield": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), C.POINTER(cpl_adj),
+                                     _vp]),
+    "adjoint_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _vp, _vp,
+                               C.POINTER(cpl_adj), C.c_int64, _vp, _vp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(lib, _name)
@@ -220,6 +230,16 @@ def coupled_step(d, st, src_values, n0, stream=None):
     src, psrc = _np_dp(src_values)
     return _check(lib.coupled_step(C.byref(d), C.byref(st), psrc, int(n0), len(src),
                                    stream or current_stream()))
+
+
+def adjoint_init_yield(d, st, adj, stream=None):
+    return _check(lib.adjoint_init_yield(C.byref(d), C.byref(st), C.byref(adj),
+                                         stream or current_stream()))
+
+
+def adjoint_step(d, st, psi_n, E_mol_n, adj, n, g_src, stream=None):
+    return _check(lib.adjoint_step(C.byref(d), C.byref(st), _ptr(psi_n), _ptr(E_mol_n),
+                                   C.byref(adj), int(n), _ptr(g_src), stream or current_stream()))
 
 
 # ------------------------------------------------------------ allocations
@@ -374,6 +394,55 @@ class Coupled:
         src_values = np.atleast_1d(np.asarray(src_values, np.float64))
         coupled_step(self.desc, self.state, src_values, self.n)
         self.n += len(src_values)
+
+    # -------------------------------------------------- checkpoint / restore
+    _STATE = ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "JDx", "JDy", "JDz", "psi", "dft"]
+
+    def snapshot(self):
+        """Device copy of everything a later step reads (checkpoint)."""
+        snap = {k: self.fields.t[k].clone() for k in self._STATE}
+        snap["mol_psi"] = self.mol.psi.clone()
+        snap["absorbed"] = self.mol.absorbed.clone()
+        snap["P_c"] = self.P_c.clone()
+        snap["J_mol"] = self.J_mol.clone()
+        snap["n"] = self.n
+        return snap
+
+    def restore(self, snap):
+        for k in self._STATE:
+            self.fields.t[k].copy_(snap[k])
+        self.mol.psi.copy_(snap["mol_psi"])
+        self.mol.absorbed.copy_(snap["absorbed"])
+        self.P_c.copy_(snap["P_c"])
+        self.J_mol.copy_(snap["J_mol"])
+        self.n = snap["n"]
+
+    def yield_mean(self):
+        """Mean dissociated population (norm beyond r_diss plus absorbed)."""
+        _, _, y = self.mol.readout()
+        return y.mean()
+
+    def adjoint_buffers(self):
+        """Allocate the adjoint state (same shapes as the forward state)."""
+        dev = self.mol.psi.device
+        fd = self.fields
+        t = {n: torch.zeros_like(fd.t[n]) for n in ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz",
+                                                      "JDx", "JDy", "JDz", "psi"]}
+        t["lpsi"] = torch.zeros_like(self.mol.psi)
+        nm = max(self.mol.desc.n_mol, 1)
+        t["labs"] = torch.zeros(nm, dtype=torch.float64, device=dev)
+        t["ld"] = torch.zeros(nm, dtype=torch.float64, device=dev)
+        t["lE"] = torch.zeros(nm, dtype=torch.float64, device=dev)
+        t["lP"] = torch.zeros(max(self.desc.n_occ, 1), dtype=torch.float64, device=dev)
+        nbytes = lib.adjoint_scratch_bytes(C.byref(self.desc))
+        t["scratch"] = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
+        lf = fdtd_fields(*[C.c_void_p(t[n].data_ptr()) for n in ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz",
+                                                                  "JDx", "JDy", "JDz", "psi"]],
+                         None, None)
+        adj = cpl_adj(C.c_void_p(t["lpsi"].data_ptr()), C.c_void_p(t["labs"].data_ptr()),
+                      C.c_void_p(t["lP"].data_ptr()), C.c_void_p(t["ld"].data_ptr()),
+                      C.c_void_p(t["lE"].data_ptr()), lf, C.c_void_p(t["scratch"].data_ptr()))
+        return adj, t
 
 
 def n_exports_ok():

@@ -1,0 +1,182 @@
+"""GPU checks of the hand-written adjoint of the coupled step.
+
+1. One reverse step against the forward: <lambda', J delta> (central
+   differences of the forward step) equals <J^T lambda', delta> (adjoint_step)
+   for random state perturbations and adjoints, all state components at once
+   (wavepackets, absorbed norms, cell polarisation, E, H, Drude currents, CPML
+   auxiliaries) plus the source sample; FP64, tolerance 1e-7 relative.
+2. The gradient of the dissociated population of a whole checkpointed run
+   along a random direction of (64 knots, carrier) against the FP64 oracle's
+   tangent-linear derivative (1e-8 relative in the FP64 form, 1e-3 in FP32).
+3. The same gradient against central finite differences of the FP64 GPU
+   form with a relative step of 1e-4 (tolerance 1e-3).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner
+from oracle.tangent import CoupledTangent, source_derivatives
+from workloads import get_config
+from workloads.geometry import material_map
+from workloads.pulses import knot_values, source_values
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(n_steps=120):
+    return get_config("cfg0", n_r=128, j_max=6, pulse="knots", n_knots=64, knot_seed=4,
+                      n_steps=n_steps, omega_h=0.10, ckpt_every=40)
+
+
+def _cfg_dissociating(n_steps=250, ckpt=80):
+    """A regime where the yield is a real signal: carrier near the vertical
+    gap (one-photon excitation), lighter nuclei and r_diss = 4 a0, so the
+    excited packet crosses r_diss within the run and Y is far above the FP32
+    round-off floor (with the 0.10 Eh carrier and 120 steps of the tiny case
+    Y ~ 1e-12, which FP32 cannot resolve and finite differences cannot
+    difference)."""
+    return get_config("cfg0", n_r=128, j_max=6, mass=500.0, r_diss=4.0, pulse="knots", n_knots=64,
+                      knot_seed=4, n_steps=n_steps, omega_h=0.45, ckpt_every=ckpt)
+
+
+def _mat_with_metal(cfg):
+    mat = material_map(cfg)
+    mat[:, 15:17] = 2      # a Drude layer above the molecules
+    mat[:, 19:] = 1        # glass into the top CPML
+    return mat
+
+
+STATE = ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "JDx", "JDy", "JDz", "psi"]
+
+
+def _dot_state(sysm, vec):
+    """<vec, state> over the differentiable state (real inner product)."""
+    s = 0.0
+    for k in STATE:
+        s += float((vec[k] * sysm.fields.t[k]).sum())
+    s += float((torch.conj(vec["mol_psi"]) * sysm.mol.psi).real.sum())
+    s += float((vec["absorbed"] * sysm.mol.absorbed).sum())
+    s += float((vec["P_c"] * sysm.P_c).sum())
+    return s
+
+
+def test_adjoint_step_dot_product_fp64():
+    from paper_2209_04487_amd import msqd
+    cfg = _cfg()
+    banner("adjoint step dot product fp64")
+    mat = _mat_with_metal(cfg)
+    kn = knot_values(cfg) * 30.0
+    src = source_values(cfg, 0, 60, knots=kn)
+    sysm = msqd.Coupled(cfg, prec="fp64", mat=mat)
+    sysm.step(src[:40])
+    x = sysm.snapshot()
+    gen = torch.Generator(device="cpu").manual_seed(0)
+
+    def rnd_like(t, scale):
+        if t.is_complex():
+            r = torch.randn(t.shape, generator=gen, dtype=torch.float64) + 1j * torch.randn(
+                t.shape, generator=gen, dtype=torch.float64)
+            return (r * scale).to(t.dtype).to(t.device)
+        return (torch.randn(t.shape, generator=gen, dtype=torch.float64) * scale).to(t.dtype).to(t.device)
+
+    def scale_of(t):
+        v = float(t.abs().max()) if t.numel() else 0.0
+        return v if v > 0 else 1.0
+
+    delta, lam = {}, {}
+    for k in STATE:
+        sc = scale_of(x[k]) if k != "psi" else scale_of(x["Ex"]) * 1e-3
+        delta[k] = rnd_like(x[k], sc)
+        lam[k] = rnd_like(x[k], 1.0 / sc)
+    for k, t in [("mol_psi", x["mol_psi"]), ("absorbed", x["absorbed"]), ("P_c", x["P_c"])]:
+        sc = scale_of(t)
+        delta[k] = rnd_like(t, sc)
+        lam[k] = rnd_like(t, 1.0 / sc)
+    ds = float(abs(src[40]))
+
+    def step_from(eps):
+        sysm.restore(x)
+        for k in STATE:
+            sysm.fields.t[k].add_(eps * delta[k])
+        sysm.mol.psi.add_(eps * delta["mol_psi"])
+        sysm.mol.absorbed.add_(eps * delta["absorbed"])
+        sysm.P_c.add_(eps * delta["P_c"])
+        sysm.step(np.array([src[40] + eps * ds]))
+        return _dot_state(sysm, lam)
+
+    eps = 1e-6
+    jv = (step_from(eps) - step_from(-eps)) / (2 * eps)
+
+    # adjoint: restore x, recompute the step's gathered field, then reverse
+    sysm.restore(x)
+    psi_n = sysm.mol.psi.clone()
+    sysm.step(src[40:41])
+    e_n = sysm.E_mol.clone()
+    adj, buf = sysm.adjoint_buffers()
+    for k in STATE:
+        buf[k].copy_(lam[k])
+    buf["lpsi"].copy_(lam["mol_psi"])
+    buf["labs"].copy_(lam["absorbed"])
+    buf["lP"][: lam["P_c"].numel()].copy_(lam["P_c"])
+    g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    msqd.adjoint_step(sysm.desc, sysm.state, psi_n, e_n, adj, 40, g)
+    torch.cuda.synchronize()
+    jtl = 0.0
+    for k in STATE:
+        jtl += float((buf[k] * delta[k]).sum())
+    jtl += float((torch.conj(buf["lpsi"]) * delta["mol_psi"]).real.sum())
+    jtl += float((buf["labs"] * delta["absorbed"]).sum())
+    jtl += float((buf["lP"][: lam["P_c"].numel()] * delta["P_c"]).sum())
+    jtl += float(g[0]) * ds
+    assert abs(jv - jtl) <= 1e-7 * max(abs(jv), abs(jtl)), (jv, jtl)
+
+
+def _direction(cfg, seed=7):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(cfg.n_knots + 1)
+    v[-1] *= cfg.omega * 1e-2
+    return v
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+def test_gradient_matches_oracle_tangent(prec, tol):
+    from paper_2209_04487_amd.grad import yield_and_gradient
+    cfg = _cfg_dissociating()
+    banner(f"adjoint gradient vs oracle tangent {prec}")
+    kn = knot_values(cfg) * 10.0
+    Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec=prec)
+    v = _direction(cfg)
+    dY_gpu = float(dk @ v[:-1] + dw * v[-1])
+    tl = CoupledTangent(cfg)
+    dsrc = v @ source_derivatives(cfg, cfg.n_steps, knots=kn)
+    Y_o, dY_o = tl.run(source_values(cfg, 0, cfg.n_steps, knots=kn), dsrc)
+    print(f"{prec}: Y gpu {Y:.12e} oracle {Y_o:.12e}; dY gpu {dY_gpu:.12e} oracle {dY_o:.12e}")
+    assert Y_o > 5e-5          # a real dissociation signal
+    assert abs(Y - Y_o) <= (1e-10 if prec == "fp64" else 1e-4) * abs(Y_o)
+    assert abs(dY_gpu - dY_o) <= tol * abs(dY_o)
+
+
+def test_gradient_matches_central_differences():
+    from paper_2209_04487_amd.grad import CoupledYield, yield_and_gradient
+    cfg = _cfg_dissociating(n_steps=200, ckpt=70)
+    banner("adjoint gradient vs GPU central differences fp64")
+    kn = knot_values(cfg) * 10.0
+    Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp64")
+
+    def Yof(knots, omega):
+        k = torch.as_tensor(knots)
+        w = torch.as_tensor(float(omega), dtype=torch.float64)
+        return float(CoupledYield.apply(k, w, cfg, "fp64", None))
+
+    for j in [int(np.argmax(np.abs(dk))), 20, 35]:
+        h = 1e-4 * kn[j]
+        kp, km = kn.copy(), kn.copy()
+        kp[j] += h
+        km[j] -= h
+        fd = (Yof(kp, cfg.omega) - Yof(km, cfg.omega)) / (2 * h)
+        assert abs(fd - dk[j]) <= 1e-3 * abs(dk[j]), (j, fd, dk[j])
+    h = 1e-4 * cfg.omega
+    fd = (Yof(kn, cfg.omega + h) - Yof(kn, cfg.omega - h)) / (2 * h)
+    assert abs(fd - dw) <= 1e-3 * abs(dw), (fd, dw)

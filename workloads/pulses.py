@@ -70,3 +70,17 @@ def source_values(cfg: Config, n0: int = 0, n_steps: int | None = None,
         env = np.interp(t, knot_times(cfg), a) * U.E_AU
         return env * np.cos(w * t)
     raise ValueError(cfg.pulse)
+
+
+def source_jacobian(cfg, n0: int, n_steps: int, knots=None, omega=None) -> np.ndarray:
+    """d E_inc(t_{n+1/2}) / d p for the knot envelope E_inc = A(t) cos(omega t):
+    rows p = knot_0 .. knot_{K-1} (per au of field) then omega (per rad/s);
+    shape [n_knots + 1, n_steps], V/m per parameter unit."""
+    t = source_times(cfg, n0, n_steps)
+    a = knot_values(cfg) if knots is None else np.asarray(knots, dtype=np.float64)
+    w = cfg.omega if omega is None else omega
+    h = envelope_basis(cfg, t)
+    jac = np.zeros((cfg.n_knots + 1, n_steps))
+    jac[:cfg.n_knots] = (h * np.cos(w * t)[:, None]).T * U.E_AU
+    jac[cfg.n_knots] = -(h @ a) * t * np.sin(w * t) * U.E_AU
+    return jac
