@@ -156,14 +156,14 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
     for (int p = 0; p < R1; ++p) v[p] = psi[loff + R2 * p];
     kinetic_half<T, NR>(v, slot, q, kin, tw);
 #pragma unroll
-    for (int p = 0; p < R1; ++p) A[line * LS + q + R2 * p] = cmul(v[p], vph[loff + R2 * p]);
+    for (int p = 0; p < R1; ++p) A[line * LS + q + R2 * p] = phase_mul(v[p], vph[loff + R2 * p]);
   }
   __syncthreads();
   for (int r = tid; r < NR; r += nthr) coupling_point_fwd<T>(A, B, LS, r, nj, tm, xk, mudt[r] * E);
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) v[p] = cmul(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
+    for (int p = 0; p < R1; ++p) v[p] = phase_mul(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
     kinetic_half<T, NR>(v, slot, q, kin, tw);       // v = psi_pre (before the absorber)
   }
   __syncthreads();
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   if (active) {
     kinetic_half<T, NR, true>(lam, slot, q, kin, tw);
 #pragma unroll
-    for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = cmul_conj(lam[p], vph[loff + R2 * p]);
+    for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = phase_mul_conj(lam[p], vph[loff + R2 * p]);
   }
   __syncthreads();
   double grad = 0.0;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) lam[p] = cmul_conj(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
+    for (int p = 0; p < R1; ++p) lam[p] = phase_mul_conj(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
   }
   __syncthreads();
   if (active) {

@@ -296,16 +296,21 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
     float* dst = reinterpret_cast<float*>(host.data() + off);
     for (size_t i = 0; i < v.size(); ++i) dst[i] = static_cast<float>(v[i]);
   };
-  auto putcf = [&](size_t off, const std::vector<std::complex<double>>& v) {
+  // FP32 phase tables: the kinetic and potential phases as lifting
+  // parameters (the kinetic one without its 1/n_r), the transform twiddles
+  // as float pairs of modulus closest to one
+  auto put_lift = [&](size_t off, const std::vector<std::complex<double>>& v, double scale) {
     float* dst = reinterpret_cast<float*>(host.data() + off);
-    for (size_t i = 0; i < v.size(); ++i) {
-      dst[2 * i] = static_cast<float>(v[i].real());
-      dst[2 * i + 1] = static_cast<float>(v[i].imag());
-    }
+    for (size_t i = 0; i < v.size(); ++i)
+      lift_params(v[i].real() * scale, v[i].imag() * scale, &dst[2 * i], &dst[2 * i + 1]);
   };
-  putcf(L.kin_f, t.kin);
-  putcf(L.tw_f, t.tw_f);
-  putcf(L.vph_f, t.vph);
+  auto put_unit = [&](size_t off, const std::vector<std::complex<double>>& v) {
+    float* dst = reinterpret_cast<float*>(host.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) unit_pair_f32(v[i].real(), v[i].imag(), &dst[2 * i], &dst[2 * i + 1]);
+  };
+  put_lift(L.kin_f, t.kin, static_cast<double>(nr));
+  put_unit(L.tw_f, t.tw_f);
+  put_lift(L.vph_f, t.vph, 1.0);
   putf(L.tm_f, t.tm);
   putf(L.x_f, t.x);
   putf(L.mudt_f, t.mudt);

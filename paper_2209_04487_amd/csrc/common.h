@@ -56,6 +56,27 @@ __host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; 
 template <typename T>
 __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * a.y; }
 
+// Rotation v * exp(i phi) as three shears (lifting): x += p y; y += u x;
+// x += p y, with p = -tan(phi / 2) and u = sin(phi).  The shears have
+// determinant one whatever p and u are rounded to, so the rounded product
+// changes |v|^2 only at second order in the rounding of the parameters when
+// averaged over the phase of v.  A rounded (cos, sin) pair instead scales
+// every |v|^2 by the same factor |c + i s|^2 = 1 + O(eps), which, applied to
+// every element in every step, turns into a systematic drift of the norm.
+template <typename T>
+__host__ __device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> lift_rot(cx<T> v, T p, T u) {
+  const T x1 = fma_t(p, v.y, v.x);
+  const T y1 = fma_t(u, x1, v.y);
+  return {fma_t(p, y1, x1), y1};
+}
+
 // ------------------------------------------------ compile-time cos / sin
 // cos(2 pi j / n) and sin(2 pi j / n) evaluated in constant expressions:
 // reduce to the first octant by symmetry, then Taylor series to convergence.
@@ -100,6 +121,29 @@ constexpr void ct_sincos_frac(long j, long n, double* s, double* c) {
     default: *s = -ca; *c = sa; break;
   }
 }
+
+// exp(+-2 pi i j / N) split into k quarter turns and a remainder |phi| <=
+// pi/4, the remainder as lifting parameters (p, u) in float
+template <int N, bool INV>
+struct LiftTwiddles {
+  int k[N];
+  bool rest[N];
+  float p[N];
+  float u[N];
+  constexpr LiftTwiddles() : k(), rest(), p(), u() {
+    for (int j = 0; j < N; ++j) {
+      const long num = INV ? 4L * j : -4L * j;          // angle in quarter turns, times N
+      long kq = (num >= 0) ? (num + N / 2) / N : -((-num + N / 2) / N);
+      const long m = num - kq * N;                        // remainder angle = 2 pi m / (4N)
+      k[j] = static_cast<int>(((kq % 4) + 4) % 4);
+      rest[j] = (m != 0);
+      double s = 0.0, c = 1.0;
+      ct_sincos_frac(m, 4L * N, &s, &c);
+      p[j] = static_cast<float>(-s / (1.0 + c));
+      u[j] = static_cast<float>(s);
+    }
+  }
+};
 
 template <int N>
 struct Twiddles {

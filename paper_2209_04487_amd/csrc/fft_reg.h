@@ -1,6 +1,7 @@
 // In-register DFTs of small power-of-two sizes, fully unrolled (radix-4
 // decimation in time, one radix-2 stage when log2 N is odd), with the
-// twiddle factors folded to constants at compile time.
+// twiddle factors folded to constants at compile time: (cos, sin) products in
+// double, lifting rotations in float.
 #pragma once
 
 #include "common.h"
@@ -30,9 +31,23 @@ __host__ __device__ __forceinline__ cx<T> mul_tw(cx<T> v, int j) {
     const bool times_minus_i = (q == 1) != INV;
     return times_minus_i ? mul_mi(v) : mul_i(v);
   }
-  const T c = static_cast<T>(tw_cos<N>(j));
-  const T s = INV ? static_cast<T>(tw_sin<N>(j)) : static_cast<T>(-tw_sin<N>(j));
-  return {v.x * c - v.y * s, v.x * s + v.y * c};
+  if constexpr (sizeof(T) == 4) {
+    // float: exact quarter turns, then the remainder by lifting (no
+    // systematic modulus error; see lift_rot)
+    constexpr LiftTwiddles<N, INV> L{};
+    cx<T> w = v;
+    switch (L.k[j]) {
+      case 1: w = mul_i(w); break;
+      case 2: w = cx<T>{-w.x, -w.y}; break;
+      case 3: w = mul_mi(w); break;
+      default: break;
+    }
+    return L.rest[j] ? lift_rot(w, L.p[j], L.u[j]) : w;
+  } else {
+    const T c = static_cast<T>(tw_cos<N>(j));
+    const T s = INV ? static_cast<T>(tw_sin<N>(j)) : static_cast<T>(-tw_sin<N>(j));
+    return {v.x * c - v.y * s, v.x * s + v.y * c};
+  }
 }
 
 // In-place DFT of x[0..N-1]: X[k] = sum_n x[n] exp(-+2 pi i n k / N), no scaling.

@@ -49,6 +49,35 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+void lift_params(double c, double s, float* p, float* u) {
+  // -tan(phi/2) = -s / (1 + c); near phi = pi use (c - 1) / s instead
+  const double pd = (c > -0.5) ? -s / (1.0 + c) : (c - 1.0) / s;
+  *p = static_cast<float>(pd);
+  *u = static_cast<float>(s);
+}
+
+void unit_pair_f32(double c, double s, float* cf, float* sf) {
+  const bool c_big = std::fabs(c) >= std::fabs(s);
+  const double big = c_big ? c : s, small = c_big ? s : c;
+  const float bf = static_cast<float>(big);
+  const double bb = static_cast<double>(bf);
+  const double rest = std::sqrt(std::max(0.0, 1.0 - bb * bb));
+  float best = static_cast<float>(std::copysign(rest, small));
+  double err = std::fabs(bb * bb + static_cast<double>(best) * best - 1.0);
+  // the nearest float of the square root and its two neighbours
+  for (int d = -1; d <= 1; d += 2) {
+    const float cand = std::nextafter(best, d < 0 ? -2.0f : 2.0f);
+    const double e = std::fabs(bb * bb + static_cast<double>(cand) * cand - 1.0);
+    if (e < err) {
+      err = e;
+      best = cand;
+    }
+  }
+  if (small == 0.0) best = 0.0f;
+  *cf = c_big ? bf : best;
+  *sf = c_big ? best : bf;
+}
+
 MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
                                const double* mu12) {
   MolTablesHost t;

@@ -18,12 +18,21 @@ struct MolTablesHost {
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // radix of the first in-register FFT pass for a radial grid of n_r points
-// for a radial grid of n_r points and complex elements of el_bytes/2 per part
+// and complex elements of el_bytes/2 per part
 constexpr int fft_r1(int n_r, int el_bytes) {
   return n_r == 64 ? 8 : (n_r == 128 ? 16 : (n_r == 256 ? (el_bytes == 4 ? 32 : 16) : 32));
 }
 MolTablesHost build_mol_tables(const qd_desc& d, const double* U_g, const double* U_e,
                                const double* mu12);
+
+// Lifting parameters (p, u) = (-tan(phi/2), sin phi) of the unit phase
+// c + i s = exp(i phi), phi in (-pi, pi].
+void lift_params(double c, double s, float* p, float* u);
+// Float pair (cf, sf) for the unit number c + i s whose modulus is as close
+// to one as the float grid allows: the larger component rounded to nearest,
+// the smaller one the float nearest sqrt(1 - larger^2) (the phase moves by at
+// most about 1e-6 rad for the angles of the transform tables).
+void unit_pair_f32(double c, double s, float* cf, float* sf);
 
 void place_slab(int32_t n_mol, int32_t nx, int32_t ny, uint64_t seed, int32_t k0, int32_t nk,
                 int32_t* cell_of_mol);

@@ -55,6 +55,35 @@ __device__ __forceinline__ cx<T> cmul_conj(cx<T> a, cx<T> b) {  // a * conj(b)
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
+// Unit phase factors from the kinetic and potential tables: the FP64 tables
+// hold (cos, sin), the FP32 tables the lifting parameters (-tan(phi/2),
+// sin phi) of the same angle (see lift_rot).
+template <typename T>
+__device__ __forceinline__ cx<T> phase_mul(cx<T> v, cx<T> t) {
+  if constexpr (sizeof(T) == 8)
+    return cmul(v, t);
+  else
+    return lift_rot(v, t.x, t.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> phase_mul_conj(cx<T> v, cx<T> t) {
+  if constexpr (sizeof(T) == 8)
+    return cmul_conj(v, t);
+  else
+    return lift_rot(v, -t.x, -t.y);
+}
+// kinetic factor: the FP64 table carries the 1/NR of the inverse transform,
+// the FP32 form applies it as an exact power-of-two scale after the rotation
+template <typename T, int NR, bool CONJ>
+__device__ __forceinline__ cx<T> kin_mul(cx<T> v, cx<T> t) {
+  if constexpr (sizeof(T) == 8) {
+    return CONJ ? cmul_conj(v, t) : cmul(v, t);
+  } else {
+    const cx<T> w = CONJ ? phase_mul_conj(v, t) : phase_mul(v, t);
+    return cscale(w, T(1) / T(NR));
+  }
+}
+
 template <typename T>
 struct MolTabs {
   const cx<T>* kin;
@@ -70,8 +99,8 @@ struct MolTabs {
 
 // ---------------------------------------------------------------- K/2
 // v: this lane's R1 values of its line (r = q + R2 p); slot: the line's LDS
-// region (R2 * (R1 + 1) elements).  kin already carries the 1/NR of the
-// inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
+// region (R2 * (R1 + 1) elements).  kin is applied by kin_mul, which
+// includes the 1/NR of the inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
 // x, y < R1, so that every table access is a uniform base plus one lane
 // offset plus an immediate.
 template <typename T, int NR, bool CONJ = false>
@@ -94,7 +123,7 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
     for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + a];
     dft<R2, false, T>(w);
 #pragma unroll
-    for (int b = 0; b < R2; ++b) w[b] = CONJ ? cmul_conj(w[b], kin[a + R1 * b]) : cmul(w[b], kin[a + R1 * b]);
+    for (int b = 0; b < R2; ++b) w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
     dft<R2, true, T>(w);
 #pragma unroll
     for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);
@@ -525,7 +554,7 @@ void mol_step_kernel(MolArgs a) {
       kinetic_half<T, NR>(v, slot, q, kin, tw);
 #pragma unroll
       for (int p = 0; p < R1; ++p) {
-        v[p] = cmul(v[p], vph[loff + R2 * p]);
+        v[p] = phase_mul(v[p], vph[loff + R2 * p]);
         slot[q + R2 * p] = v[p];
       }
     }
@@ -540,7 +569,7 @@ void mol_step_kernel(MolArgs a) {
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int p = 0; p < R1; ++p) v[p] = cmul(slot[q + R2 * p], vph[loff + R2 * p]);
+      for (int p = 0; p < R1; ++p) v[p] = phase_mul(slot[q + R2 * p], vph[loff + R2 * p]);
       kinetic_half<T, NR>(v, slot, q, opaque(kin), opaque(tw));
 #pragma unroll
       for (int p = 0; p < R1; ++p) {
