@@ -9,8 +9,13 @@ cores with a hi/lo split, FP32 fields, FP64 reductions) in molecule-steps/s
 of the whole coupled step (H update, field gather, molecular step, per-cell
 dipole reduction and polarisation current, E update with Drude and source,
 flux monitor).  The plain FP64 form is timed on the same workload for the
-comparison, and the relative L2 error of the ensemble dipole trace of the
-precision form against the FP64 form is measured over the same steps.
+comparison.
+
+Accuracy: both forms are run from the same first step for --acc-steps steps
+(default 1,000, covering the arrival of the pulse peak at the molecules),
+recording the ensemble dipole after every step; the line reports the
+relative L2 error of the precision form's dipole trace, of its transmitted
+flux spectrum and of its mean dissociated population against the FP64 form.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -18,8 +23,10 @@ Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (not used by this
+# library): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = 78.6
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "mol_step_mixed_srr100k_counters.md")
 METRIC = "molecule-steps/s, coupled step, FP32/BF16 vs FP64 at ≤1e-4 rel dipole err"
 
 
@@ -47,6 +58,67 @@ def mol_bytes_per_step(cfg, prec):
     return 2 * psi + field + 4 + 16 + 8 + 8
 
 
+def mol_flops_per_step(cfg):
+    """Algorithmic vector flops of one molecule-step: four N_r-point complex
+    FFTs per (state, J) line (two kinetic half-steps, each a forward and an
+    inverse transform; 5 N log2 N flops each), the kinetic and the two
+    potential phase multiplies (6 flops per point each), the 2x2 coupling
+    rotation at every (angle node, r) point (12 flops plus 2 for the angle),
+    and the norm and dipole readouts.  The J<->angle contractions run on the
+    matrix cores and are not counted here."""
+    n, nj = cfg.n_r, cfg.n_j
+    lines = 2 * nj
+    fft = 5 * n * int(np.log2(n))
+    per_line = 4 * fft + 2 * 6 * n + 2 * 6 * n
+    rot = nj * n * 14
+    readout = 2 * nj * n * 3 + (nj - 1) * n * 8
+    return lines * per_line + rot + readout
+
+
+def mol_mfma_flops_per_step(cfg):
+    """Algorithmic flops of the J->angle and angle->J contractions (a real
+    n_j x n_j matrix applied to the complex wavepacket of both states)."""
+    return 2 * 2 * 4 * cfg.n_j * cfg.n_j * cfg.n_r
+
+
+def sources_sha256():
+    """Hash of the kernel sources, to tie stored counter figures to the code
+    they were taken from."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2209_04487_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch of the mixed molecular kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
+    known size), or None when the kernel sources changed since."""
+    try:
+        with open(COUNTER_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None, None
+    m_sha = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
+    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_t):
+        return None, None
+    if m_sha.group(1) != sources_sha256():
+        return None, "kernel sources changed since the counters were taken"
+    return float(m_t.group(1)), os.path.relpath(COUNTER_PROFILE, ROOT)
+
+
+def default_first_step(cfg):
+    """First step of the measured window: 600 steps before the pulse peak
+    leaves the source plane (the peak reaches the molecule slab about 90
+    steps later), so the window covers the strong-field interaction."""
+    return max(0, int(round(cfg.t0 / cfg.dt)) - 600)
+
+
 def stencil_bytes_per_cell(prec):
     """Algorithmic bytes per cell-update of the two stencil kernels as
     launched: H update reads E (3) and H (3), writes H (3); E update reads H
@@ -55,7 +127,9 @@ def stencil_bytes_per_cell(prec):
     return 18 * w + 3
 
 
-def run_coupled(cfg, prec, steps, warmup, n0, record_d):
+def run_coupled(cfg, prec, steps, warmup, n0):
+    """Time `steps` coupled steps (after `warmup` untimed ones) with HIP
+    events on the stream the steps are launched on."""
     import torch
 
     from paper_2209_04487_amd import msqd
@@ -63,7 +137,6 @@ def run_coupled(cfg, prec, steps, warmup, n0, record_d):
     sysm = msqd.Coupled(cfg, prec=prec)
     src = source_values(cfg, n0, warmup + steps)
     stream = torch.cuda.current_stream()
-    # warm-up steps (part of the same run)
     if warmup:
         msqd.coupled_step(sysm.desc, sysm.state, src[:warmup], n0)
     torch.cuda.synchronize()
@@ -75,23 +148,50 @@ def run_coupled(cfg, prec, steps, warmup, n0, record_d):
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end)
     msqd.check_status(sysm.mol.ws)
-    D = None
-    if record_d:
-        # untimed replay of the same steps from a fresh state, recording the
-        # ensemble dipole after every step
-        del sysm
-        torch.cuda.empty_cache()
-        sysm = msqd.Coupled(cfg, prec=prec)
-        D = np.zeros(warmup + steps)
-        acc = torch.zeros(warmup + steps, dtype=torch.float64, device="cuda")
-        for s in range(warmup + steps):
-            msqd.coupled_step(sysm.desc, sysm.state, src[s:s + 1], n0 + s)
-            acc[s] = sysm.mol.d.sum()
-        D = acc.cpu().numpy()
-    out = {"ms": ms, "D": D, "n_mol": sysm.mol.desc.n_mol}
+    out = {"ms": ms, "n_mol": sysm.mol.desc.n_mol}
     del sysm
     torch.cuda.empty_cache()
     return out
+
+
+def run_accuracy(cfg, prec, steps, n0):
+    """Untimed run of `steps` coupled steps from a fresh state, recording the
+    ensemble dipole after every step; returns the trace, the transmitted
+    flux spectrum and the mean dissociated population at the end."""
+    import torch
+
+    from paper_2209_04487_amd import msqd
+    from workloads.pulses import source_values
+    sysm = msqd.Coupled(cfg, prec=prec)
+    src = source_values(cfg, n0, steps)
+    acc = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    for s in range(steps):
+        msqd.coupled_step(sysm.desc, sysm.state, src[s:s + 1], n0 + s)
+        acc[s] = sysm.mol.d.sum()
+    flux = sysm.fields.flux().cpu().numpy()
+    y = float(sysm.yield_mean())
+    msqd.check_status(sysm.mol.ws)
+    out = {"D": acc.cpu().numpy(), "flux": flux, "yield": y}
+    del sysm
+    torch.cuda.empty_cache()
+    return out
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def calibration_copy(nbytes=1 << 30, reps=3):
+    """Device-to-device copies of a known size, for scaling the HBM byte
+    counters of a counter run (FETCH_SIZE / WRITE_SIZE) to bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def time_mol_kernel(cfg, prec, launches):
@@ -193,11 +293,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n0", type=int, default=0, help="first step of the run (pulse time origin)")
+    ap.add_argument("--n0", type=int, default=None,
+                    help="first step of the run (default: 600 steps before the pulse peak)")
+    ap.add_argument("--acc-steps", type=int, default=1000,
+                    help="length of the accuracy comparison against the FP64 form (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 timing and comparison")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64"], default=None,
-                    help="only time the molecular-step kernel of this form (for counter runs)")
+                    help="only time the molecular-step kernel of this form (for counter runs), "
+                         "followed by a 1 GiB calibration copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -212,29 +316,45 @@ def main():
     cfg = get_config("cfg2")
     cfg64 = get_config("cfg1")
     K, W = args.steps, args.warmup
+    n0 = default_first_step(cfg) if args.n0 is None else args.n0
     if args.kernel:
-        ms = time_mol_kernel(cfg, args.kernel, K)
-        b = mol_bytes_per_step(cfg, args.kernel) * cfg.n_mol
+        c = cfg if args.kernel != "fp64" else cfg64
+        ms = time_mol_kernel(c, args.kernel, K)
+        b = mol_bytes_per_step(c, args.kernel) * c.n_mol
+        calibration_copy()
         print(json.dumps({"kernel": args.kernel, "launches": K, "ms": ms,
-                          "GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}))
+                          "GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "TFLOPs": mol_flops_per_step(c) * c.n_mol / (ms / 1e3) / 1e12,
+                          "calibration_copy_bytes": 1 << 30, "sources_sha256": sources_sha256()}))
         return
 
-    log(f"mixed coupled run: {cfg.n_mol} molecules, {W}+{K} steps")
-    mixed = run_coupled(cfg, "mixed", K, W, args.n0, record_d=not args.no_fp64)
+    log(f"mixed coupled run: {cfg.n_mol} molecules, {W}+{K} steps from step {n0}")
+    mixed = run_coupled(cfg, "mixed", K, W, n0)
     value = mixed["n_mol"] * K / (mixed["ms"] / 1e3)
     fp64 = None
-    err = None
     if not args.no_fp64:
         log("fp64 coupled run")
-        fp64 = run_coupled(cfg64, "fp64", K, W, args.n0, record_d=True)
-        D64, Dm = fp64["D"], mixed["D"]
-        err = float(np.linalg.norm(Dm - D64) / max(np.linalg.norm(D64), 1e-300))
+        fp64 = run_coupled(cfg64, "fp64", K, W, n0)
+    acc = None
+    if args.acc_steps > 0 and not args.no_fp64:
+        log(f"accuracy: {args.acc_steps} steps of both forms from step {n0}")
+        am = run_accuracy(cfg, "mixed", args.acc_steps, n0)
+        a64 = run_accuracy(cfg64, "fp64", args.acc_steps, n0)
+        acc = {"steps": f"{n0}..{n0 + args.acc_steps}",
+               "dipole_trace_rel_l2": rel_l2(am["D"], a64["D"]),
+               "flux_spectrum_rel_l2": rel_l2(am["flux"], a64["flux"]),
+               "yield_rel": abs(am["yield"] - a64["yield"]) / max(abs(a64["yield"]), 1e-300),
+               "yield_fp64": a64["yield"],
+               "dipole_peak_fp64": float(np.abs(a64["D"]).max())}
 
     log("kernel timing")
     launches = max(10, min(K, 100))
     mol_ms = time_mol_kernel(cfg, "mixed", launches)
     unit_bytes = mol_bytes_per_step(cfg, "mixed")
-    achieved = unit_bytes * cfg.n_mol / (mol_ms / 1e3) / 1e9
+    unit_flops = mol_flops_per_step(cfg)
+    achieved_gbs = unit_bytes * cfg.n_mol / (mol_ms / 1e3) / 1e9
+    achieved_tf = unit_flops * cfg.n_mol / (mol_ms / 1e3) / 1e12
+    traffic, traffic_src = counter_traffic()
     sten_ms = time_stencil(cfg, "mixed", launches)
     cells = cfg.nx * cfg.ny * cfg.nz
     sten_gbs = stencil_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
@@ -256,19 +376,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+bf16 (f64 reductions)",
+        "dtype": "f32+bf16x3 (f64 reductions)",
         "data": "synthetic",
         "config": {
             "workload": (f"SRR array {cfg.nx}x{cfg.ny}x{cfg.nz} cells dx=2nm, {cfg.n_mol} molecules, "
                          f"N_r={cfg.n_r}, J<={cfg.j_max}, precision form"),
             "n_mol": cfg.n_mol, "n_r": cfg.n_r, "j_max": cfg.j_max, "cells": cells,
-            "first_step": args.n0,
+            "first_step": n0,
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "mol_step_kernel<float,256,mfma>", "kernel_ms": mol_ms,
-            "bytes_per_molecule_step": unit_bytes,
+            "bound": "alu", "achieved": achieved_tf, "peak": VALU_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tf / VALU_F32_PEAK_TFLOPS,
+            "traffic": None if traffic is None else traffic,
+            "traffic_source": traffic_src,
+            "kernel": "mol_step_kernel<float,256,bf16x3>", "kernel_ms": mol_ms,
+            "flops_per_molecule_step": unit_flops,
+            "mfma_flops_per_molecule_step": mol_mfma_flops_per_step(cfg),
+            "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved_gbs / HBM_PEAK_GBS, "bytes_per_molecule_step": unit_bytes,
+                    "algorithmic_bytes_per_launch": unit_bytes * cfg.n_mol},
         },
         "stencil": {"ms_per_step": sten_ms, "cell_updates_per_s": cells / (sten_ms / 1e3),
                     "achieved_GBs": sten_gbs, "frac": sten_gbs / HBM_PEAK_GBS},
@@ -276,7 +402,7 @@ def main():
             "value": fp64["n_mol"] * K / (fp64["ms"] / 1e3), "ms_per_step": fp64["ms"] / K,
             "mol_kernel_ms": mol64_ms},
         "speedup_vs_fp64": None if fp64 is None else fp64["ms"] / mixed["ms"],
-        "dipole_rel_err_vs_fp64": err,
+        "accuracy_vs_fp64": acc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

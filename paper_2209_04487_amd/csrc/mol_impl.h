@@ -44,10 +44,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Hide a uniform pointer's value from the optimiser so that table loads stay
 // inside the step loop instead of being hoisted into (many) live registers.
+// The barrier acts on a global-address-space copy of the pointer, so that
+// loads through the result stay global loads (a generic pointer would turn
+// them into flat loads, which also count against the LDS wait counter and
+// make every LDS wait also wait for the table loads in flight).
 template <typename P>
 __device__ __forceinline__ P* opaque(P* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+  using GP = __attribute__((address_space(1))) P*;
+  GP g = (GP)p;
+  asm volatile("" : "+s"(g));
+  return (P*)g;
 }
 
 template <typename T>
