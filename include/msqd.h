@@ -185,6 +185,9 @@ typedef struct {
   fdtd_desc fd;
   int32_t n_occ;        /* occupied cells                                  */
   double mol_weight;    /* molecules represented by each simulated one     */
+  int32_t mol_every;    /* M: molecules step every M field steps (0 or 1:
+                           every step); qd.dt_au must equal M fd.dt in
+                           atomic units (relative 1e-9)                     */
 } cpl_desc;
 
 typedef struct {
@@ -203,21 +206,87 @@ typedef struct {
   const void* fd_ws;
 } cpl_state;
 
-/* n_steps coupled steps from step n0 (section "Efficient numerical
- * implementation ..."): H^{n+1/2}; E_mol = E_x^n at each molecule's edge;
+/* n_steps coupled steps from step n0 (section on molecular mapping, with
+ * Eqs. (1), (2), (4), (5)): H^{n+1/2}; E_mol = E_x^n at each molecule's edge;
  * every molecule one step under E_mol; d_i; P_c^{n+1} = (w/dx^3) sum_{i in c}
  * d_i (e a0) in CSR order and J_mol = (P_c^{n+1} - P_c^n)/dt; E^{n+1} with
  * Drude, molecular and source currents; monitor sample.
- * src_values: host [n_steps], E_inc(t_{n+1/2}) in V/m. */
+ * Multi-rate (d->mol_every = M > 1, the paper's molecules-every-40th-step
+ * scheme): the molecular part runs only at steps with n % M == 0, each
+ * molecule taking one step of M dt under E_x^n; J_mol = (P_new - P_old)/(M dt)
+ * is then applied unchanged at every field step until the next update.
+ * src_values: host [n_steps], E_inc(t_{n+1/2}) in V/m.
+ * Errors: MSQD_EINVAL for a step/precision mismatch (qd.dt_au != M fd.dt). */
 int coupled_step(const cpl_desc* d, const cpl_state* s, const double* src_values, int64_t n0,
                  int32_t n_steps, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Frozen two-level (Bloch) emitters: the paper's comparison workload in the
+ * section on molecular mapping, where the ro-vibrational degrees of freedom
+ * are frozen and each molecule obeys the Bloch equations, integrated by the
+ * classical fourth-order Runge-Kutta scheme.  Atomic units; interaction
+ * -mu E sigma_x with the field along the dipole, V = -mu E:
+ *   d rho_ee/dt = 2 V Im(rho_ge) - gamma1 rho_ee
+ *   d rho_ge/dt = (i omega0 - gamma2) rho_ge - i V (2 rho_ee - 1)
+ * The field is held over each step.  The emitter's dipole is
+ * d = 2 mu Re(rho_ge).
+ * State: caller-owned device planes [3][n] = (rho_ee, Re rho_ge, Im rho_ge),
+ * double for MSQD_FP64, float for MSQD_FP32 and MSQD_MIXED, 16-byte aligned.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n;            /* emitters (>= 0)                                  */
+  int32_t prec;         /* MSQD_FP64 | MSQD_FP32 | MSQD_MIXED (= FP32 here)  */
+  double omega0_au;     /* transition frequency                             */
+  double mu_au;         /* transition dipole along the field                */
+  double gamma1_au;     /* population decay rate (>= 0)                     */
+  double gamma2_au;     /* coherence decay rate (>= 0)                      */
+  double dt_au;         /* step (> 0)                                       */
+} bloch_desc;
+
+/* state := the ground state (rho_ee = rho_ge = 0).  Errors: MSQD_EINVAL. */
+int bloch_init(const bloch_desc* d, void* state, void* stream);
+
+/* n_steps RK4 steps under E (device double [n], au) held over the steps;
+ * d_out: device double [n] dipoles after the steps (au), or NULL.
+ * n_steps = 0 only writes d_out.  Errors: MSQD_EINVAL, MSQD_EPREC. */
+int bloch_step(const bloch_desc* d, void* state, const double* E, double* d_out, int32_t n_steps,
+               void* stream);
+
+/* The coupled step with Bloch emitters in place of the wavepackets: the same
+ * H update, gather of E_x^n at each emitter's edge, per-cell polarisation in
+ * CSR order, polarisation current and E update as coupled_step (M = 1).
+ * bl.dt_au must equal fd.dt in atomic units (relative 1e-9); bl.prec and
+ * fd.prec are both FP64 or both reduced. */
+typedef struct {
+  bloch_desc bl;
+  fdtd_desc fd;
+  int32_t n_occ;
+  double weight;        /* emitters represented by each simulated one       */
+} cpl_bloch_desc;
+
+typedef struct {
+  void* state;                 /* [3][n] (see bloch_step)                   */
+  double* d_mol;               /* [n] dipoles after the last step           */
+  double* E_mol;               /* [n] field seen in the last step (au)      */
+  double* P_c;                 /* [n_occ]                                   */
+  double* J_mol;               /* [n_occ]                                   */
+  const int32_t* cell_of_mol;  /* [n]                                       */
+  const int32_t* occ_cell;     /* [n_occ]                                   */
+  const int32_t* occ_ptr;      /* [n_occ+1]                                 */
+  const int32_t* mol_perm;     /* [n]                                       */
+  fdtd_fields f;
+  const void* fd_ws;
+} cpl_bloch_state;
+
+int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* s, const double* src_values,
+                       int64_t n0, int32_t n_steps, void* stream);
 
 /* ------------------------------------------------------------------------
  * Adjoint of the coupled step (reverse mode), for gradients of the
  * dissociated population Y = mean_i [sum_{r > r_diss} |psi_i|^2 dr +
  * absorbed_i] with respect to the incident-field samples.
  * For complex psi the adjoint is dY/dRe(psi) + i dY/dIm(psi).
- * Supported in the MSQD_FP64 and MSQD_FP32 forms.
+ * Supported in the MSQD_FP64 and MSQD_FP32 forms with mol_every <= 1.
  * ---------------------------------------------------------------------- */
 typedef struct {
   void* lpsi;        /* adjoint of psi, same layout and type              */

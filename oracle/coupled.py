@@ -15,6 +15,14 @@ One coupled step n -> n+1, in this order:
      cell in molecule-index order; J_mol,c = (P_c^{n+1} - P_c^n) / dt
   5. E^{n+1} with the Drude, molecular and source currents    (Eqs. (1), (2))
   6. flux-monitor sample
+
+Multi-rate coupling (the paper advances its molecules only every 40th field
+step, section on molecular mapping): with mol_every = M the molecules take
+one step of M dt at every field step n with n % M == 0, driven by E_x^n held
+over the M field steps; P jumps to its new value there and the current
+J_mol = (P_new - P_old) / (M dt) is applied, unchanged, at each of the M field
+steps that follow (P linear in time between molecular updates).  M = 1 is the
+scheme above.
 """
 
 from __future__ import annotations
@@ -33,14 +41,15 @@ EA0 = 8.4783536255e-30       # C m
 
 
 class CoupledOracle:
-    def __init__(self, cfg, n_mol=None, cells=None, mat=None, yee=None):
+    def __init__(self, cfg, n_mol=None, cells=None, mat=None, yee=None, mol_every=1):
         self.cfg = cfg
+        self.mol_every = int(mol_every)
         if mat is None:
             mat = material_map(cfg)
         self.mat = mat
         self.yee = yee if yee is not None else yee_from_config(cfg, mat, eps_table(cfg))
         ug, ue, mu = potentials(cfg)
-        self.mol = model_from_config(cfg, ug, ue, mu)
+        self.mol = model_from_config(cfg, ug, ue, mu, dt_au=cfg.dt_au * self.mol_every)
         if cells is None:
             cells = cells_from_config(cfg)
         if n_mol is not None:
@@ -54,6 +63,7 @@ class CoupledOracle:
         self.Jmol = np.zeros(len(self.occ))
         self.monitor = FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k, cfg.freqs, cfg.dt, cfg.mon_every)
         self.d = np.zeros(self.n_mol)
+        self.e_mol = np.zeros(self.n_mol)
 
     def cell_sums(self, d):
         """Per occupied cell, the sum of its molecules' dipoles in CSR order."""
@@ -66,18 +76,22 @@ class CoupledOracle:
         return out
 
     def step(self, n, src_value):
+        """Field step n -> n+1; the molecules advance when n % mol_every == 0.
+        Returns the field the molecules saw at their last update."""
         cfg = self.cfg
         yee = self.yee
         yee.update_H()
-        e_mol = yee.E[0].reshape(-1)[self.cells] / E_AU
-        self.psi, self.absorbed = self.mol.step(self.psi, e_mol, self.absorbed)
-        self.d = self.mol.dipole(self.psi)
-        P_new = cfg.mol_weight * self.cell_sums(self.d) * EA0 / cfg.dx ** 3
-        self.Jmol = (P_new - self.P) / cfg.dt
-        self.P = P_new
+        if n % self.mol_every == 0:
+            e_mol = yee.E[0].reshape(-1)[self.cells] / E_AU
+            self.psi, self.absorbed = self.mol.step(self.psi, e_mol, self.absorbed)
+            self.d = self.mol.dipole(self.psi)
+            P_new = cfg.mol_weight * self.cell_sums(self.d) * EA0 / cfg.dx ** 3
+            self.Jmol = (P_new - self.P) / (cfg.dt * self.mol_every)
+            self.P = P_new
+            self.e_mol = e_mol
         yee.update_E(src_value, cfg.src_k, self.occ, self.Jmol)
         self.monitor.sample(yee, n)
-        return e_mol
+        return self.e_mol
 
     def run(self, src_values, n0=0, record_fields=False):
         """Run len(src_values) steps from step n0; returns per-step traces."""

@@ -173,6 +173,9 @@ class MoleculeModel:
         return psi
 
 
-def model_from_config(cfg, U_g, U_e, mu12):
-    return MoleculeModel(cfg.n_r, cfg.r_min, cfg.r_max, cfg.j_max, cfg.mass, cfg.dt_au,
+def model_from_config(cfg, U_g, U_e, mu12, dt_au=None):
+    """The molecular model of a workload; dt_au overrides the step (the
+    multi-rate scheme steps molecules by a multiple of the field step)."""
+    return MoleculeModel(cfg.n_r, cfg.r_min, cfg.r_max, cfg.j_max, cfg.mass,
+                         cfg.dt_au if dt_au is None else dt_au,
                          U_g, U_e, mu12, cfg.absorb_width, cfg.r_diss)

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "adjoint.h"
+#include "bloch.h"
 #include "fdtd.h"
 #include "host_tables.h"
 #include "mol.h"
@@ -90,7 +91,7 @@ FdLayout fd_layout(const fdtd_desc* d) {
 size_t mol_lds_bytes(int n_r, int nj, int prec) {
   const size_t el = prec == MSQD_FP64 ? 16 : 8;
   const int r2 = n_r / fft_r1(n_r, static_cast<int>(el / 2));
-  return el * static_cast<size_t>(2 * nj) * (n_r + r2) + 16 * 4 * sizeof(double);
+  return el * static_cast<size_t>(lds_line_start(2 * nj, n_r + r2, static_cast<int>(el))) + 16 * 4 * sizeof(double);
 }
 
 size_t mol_lds_limit() {
@@ -212,6 +213,18 @@ static MolArgs make_mol_args(const qd_desc* d, const void* ws) {
     }
   }
   a.kdiss = kd;
+  // first index inside the absorber (the same test as the mask table's)
+  int km = d->n_r;
+  if (d->absorb_width_au > 0.0) {
+    const double ra = d->r_max - d->absorb_width_au;
+    for (int k = 0; k < d->n_r; ++k) {
+      if (d->r_min + k * a.dr >= ra) {
+        km = k;
+        break;
+      }
+    }
+  }
+  a.kmask = km;
   return a;
 }
 
@@ -591,6 +604,14 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
                           !st->qd_ws))
     return fail(MSQD_EINVAL, "NULL coupling pointer");
   if (!st->fd_ws) return fail(MSQD_EINVAL, "NULL field workspace");
+  if (d->mol_every < 0) return fail(MSQD_EINVAL, "mol_every < 0");
+  const int M = d->mol_every > 1 ? d->mol_every : 1;
+  {
+    // the molecular step must be M field steps (atomic unit of time, CODATA 2018)
+    const double dt_mol_s = d->qd.dt_au * kTau;
+    if (!(std::fabs(dt_mol_s - M * d->fd.dt) <= 1e-9 * M * d->fd.dt))
+      return fail(MSQD_EINVAL, "qd.dt_au must equal mol_every * fd.dt (in atomic units)");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   FdArgs fa = make_fd_args(&d->fd, &st->f, st->fd_ws);
   MolArgs ma = make_mol_args(&d->qd, st->qd_ws);
@@ -607,6 +628,123 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
   DepArgs da{};
   da.n_occ = d->n_occ;
   da.pfac = d->mol_weight * kEa0 / (d->fd.dx * d->fd.dx * d->fd.dx);
+  da.inv_dt = 1.0 / (M * d->fd.dt);
+  for (int m = 0; m < 4; ++m) da.ce[m] = d->fd.dt / (kEps0 * d->fd.eps_r[m]);
+  da.d_mol = st->d_mol;
+  da.occ_cell = st->occ_cell;
+  da.occ_ptr = st->occ_ptr;
+  da.mol_perm = st->mol_perm;
+  da.mat = st->f.mat;
+  da.P_c = st->P_c;
+  da.J_mol = st->J_mol;
+  da.Ex = st->f.Ex;
+  for (int32_t t = 0; t < n_steps; ++t) {
+    const int64_t n = n0 + t;
+    if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
+    fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
+    int e = launch_yee_h(fa, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
+    const bool mol_now = (n % M) == 0;
+    if (mol_now) {
+      rc = launch_mol(&d->qd, ma, s);
+      if (rc) return rc;
+    }
+    e = launch_yee_e(fa, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
+    da.update = mol_now ? 1 : 0;
+    e = launch_deposit(da, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
+    if (rc) return rc;
+  }
+  return MSQD_OK;
+}
+
+// ------------------------------------------------------------ Bloch emitters
+static int check_bloch(const bloch_desc* d) {
+  if (!d) return fail(MSQD_EINVAL, "NULL Bloch descriptor");
+  if (d->n < 0) return fail(MSQD_EINVAL, "n < 0");
+  if (d->prec != MSQD_FP64 && d->prec != MSQD_FP32 && d->prec != MSQD_MIXED)
+    return fail(MSQD_EPREC, "unknown precision");
+  const double v[] = {d->omega0_au, d->mu_au, d->gamma1_au, d->gamma2_au, d->dt_au};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(MSQD_EINVAL, "non-finite Bloch parameter");
+  if (!(d->dt_au > 0.0)) return fail(MSQD_EINVAL, "dt_au must be positive");
+  if (d->gamma1_au < 0.0 || d->gamma2_au < 0.0) return fail(MSQD_EINVAL, "negative decay rate");
+  return MSQD_OK;
+}
+
+static BlochArgs make_bloch_args(const bloch_desc* d, void* state) {
+  BlochArgs a{};
+  a.n = d->n;
+  a.w0 = d->omega0_au;
+  a.mu = d->mu_au;
+  a.g1 = d->gamma1_au;
+  a.g2 = d->gamma2_au;
+  a.dt = d->dt_au;
+  a.state = state;
+  a.inv_eau = 1.0 / kEau;
+  return a;
+}
+
+int bloch_init(const bloch_desc* d, void* state, void* stream) {
+  int rc = check_bloch(d);
+  if (rc) return rc;
+  if (d->n == 0) return MSQD_OK;
+  if (!state || !aligned16(state)) return fail(MSQD_EINVAL, "state NULL or misaligned");
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  const int e = launch_fill_zero(state, 3 * static_cast<size_t>(d->n) * el, static_cast<hipStream_t>(stream));
+  return e ? check_hip(static_cast<hipError_t>(e), "Bloch state fill") : MSQD_OK;
+}
+
+int bloch_step(const bloch_desc* d, void* state, const double* E, double* d_out, int32_t n_steps,
+               void* stream) {
+  int rc = check_bloch(d);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(MSQD_EINVAL, "n_steps < 0");
+  if (d->n == 0) return MSQD_OK;
+  if (!state || !aligned16(state) || !E) return fail(MSQD_EINVAL, "state or field NULL or misaligned");
+  BlochArgs a = make_bloch_args(d, state);
+  a.n_steps = n_steps;
+  a.E = E;
+  a.d = d_out;
+  const int e = launch_bloch(a, d->prec != MSQD_FP64, static_cast<hipStream_t>(stream));
+  return e ? check_hip(static_cast<hipError_t>(e), "Bloch step launch") : MSQD_OK;
+}
+
+int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* st, const double* src_values,
+                       int64_t n0, int32_t n_steps, void* stream) {
+  if (!d || !st) return fail(MSQD_EINVAL, "NULL descriptor or state");
+  int rc = check_bloch(&d->bl);
+  if (rc) return rc;
+  rc = check_fd(&d->fd);
+  if (rc) return rc;
+  rc = check_fields(&d->fd, &st->f);
+  if (rc) return rc;
+  if (n_steps < 0 || (n_steps > 0 && !src_values)) return fail(MSQD_EINVAL, "bad step count or source");
+  if ((d->bl.prec == MSQD_FP64) != (d->fd.prec == MSQD_FP64))
+    return fail(MSQD_EPREC, "emitter and field precision must both be FP64 or both reduced");
+  if (d->n_occ < 0 || d->n_occ > d->bl.n) return fail(MSQD_ESHAPE, "n_occ out of range");
+  if (d->bl.n > 0 && (!st->state || !aligned16(st->state) || !st->d_mol || !st->P_c || !st->J_mol ||
+                      !st->cell_of_mol || !st->occ_cell || !st->occ_ptr || !st->mol_perm))
+    return fail(MSQD_EINVAL, "NULL or misaligned coupling pointer");
+  if (!st->fd_ws) return fail(MSQD_EINVAL, "NULL field workspace");
+  if (!(std::fabs(d->bl.dt_au * kTau - d->fd.dt) <= 1e-9 * d->fd.dt))
+    return fail(MSQD_EINVAL, "bl.dt_au must equal fd.dt (in atomic units)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f32 = d->fd.prec != MSQD_FP64;
+  FdArgs fa = make_fd_args(&d->fd, &st->f, st->fd_ws);
+  BlochArgs ba = make_bloch_args(&d->bl, st->state);
+  ba.n_steps = 1;
+  ba.Ex = st->f.Ex;
+  ba.ex_is_float = f32 ? 1 : 0;
+  ba.cell_of_mol = st->cell_of_mol;
+  ba.E_out = st->E_mol;
+  ba.d = st->d_mol;
+  DepArgs da{};
+  da.n_occ = d->n_occ;
+  da.update = 1;
+  da.pfac = d->weight * kEa0 / (d->fd.dx * d->fd.dx * d->fd.dx);
   da.inv_dt = 1.0 / d->fd.dt;
   for (int m = 0; m < 4; ++m) da.ce[m] = d->fd.dt / (kEps0 * d->fd.eps_r[m]);
   da.d_mol = st->d_mol;
@@ -623,8 +761,8 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
     int e = launch_yee_h(fa, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
-    rc = launch_mol(&d->qd, ma, s);
-    if (rc) return rc;
+    e = launch_bloch(ba, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "Bloch step launch");
     e = launch_yee_e(fa, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
     e = launch_deposit(da, f32, s);
@@ -650,6 +788,7 @@ static int check_adj(const cpl_desc* d, const cpl_state* st, const cpl_adj* adj)
   if (rc) return rc;
   if (d->qd.prec == MSQD_MIXED || d->fd.prec == MSQD_MIXED)
     return fail(MSQD_EUNSUP, "the adjoint is provided for the FP64 and FP32 forms");
+  if (d->mol_every > 1) return fail(MSQD_EUNSUP, "the adjoint is provided for mol_every <= 1");
   if (d->qd.prec != d->fd.prec) return fail(MSQD_EPREC, "molecule and field precision differ");
   const fdtd_fields& f = adj->lf;
   const void* ptrs[] = {f.Ex, f.Ey, f.Ez, f.Hx, f.Hy, f.Hz, f.JDx, f.JDy, f.JDz, f.psi, adj->scratch};

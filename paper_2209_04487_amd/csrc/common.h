@@ -30,6 +30,7 @@ constexpr double kMu0 = 1.25663706212e-6;
 constexpr double kEta0 = 376.730313668;
 constexpr double kEau = 5.14220674763e11;      // V/m per atomic unit of field
 constexpr double kEa0 = 8.4783536255e-30;      // C m per e a0
+constexpr double kTau = 2.4188843265857e-17;    // s per atomic unit of time
 constexpr double kPi = 3.14159265358979323846;
 
 // ------------------------------------------------------------ complex type
@@ -55,6 +56,16 @@ template <typename T>
 __host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
 template <typename T>
 __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * a.y; }
+
+// Start (in elements) of line `line` of a molecule's LDS line array, line
+// stride ls elements of el_bytes each.  complex64 rows are staggered by 16
+// elements on every other group of four lines (plus 32 every eight lines) so
+// that the four J rows one matrix-core operand load reads (J = 4g + i,
+// g = 0..3) fall on both halves of the 64 LDS banks instead of one; the
+// in-line transposes keep their two-pass access.
+constexpr int lds_line_start(int line, int ls, int el_bytes) {
+  return el_bytes == 8 ? line * ls + 16 * ((line >> 2) & 1) + 32 * (line >> 3) : line * ls;
+}
 
 // Rotation v * exp(i phi) as three shears (lifting): x += p y; y += u x;
 // x += p y, with p = -tan(phi / 2) and u = sin(phi).  The shears have

@@ -40,6 +40,7 @@ int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hip
 
 struct DepArgs {
   int n_occ;
+  int update;                          // 1: new P from the dipoles; 0: apply the held J_mol
   double pfac;                         // w e a0 / dx^3
   double inv_dt;
   double ce[4];

@@ -259,18 +259,25 @@ int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hip
 
 // ------------------------------------------------- polarisation current
 // Per occupied cell: P^{n+1} = (w e a0 / dx^3) sum_{i in cell} d_i in CSR
-// order, J = (P^{n+1} - P^n)/dt, and E_x at the cell loses dt/(eps0 eps_r) J.
+// order, J = (P^{n+1} - P^n)/dt_mol, and E_x at the cell loses
+// dt/(eps0 eps_r) J.  Between molecular updates (multi-rate coupling) only
+// the held J is applied.
 template <typename T>
 __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_occ) return;
-  double s = 0.0;
-  const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
-  for (int t = b; t < e; ++t) s += a.d_mol[a.mol_perm[t]];
-  const double p_new = s * a.pfac;
-  const double J = (p_new - a.P_c[c]) * a.inv_dt;
-  a.P_c[c] = p_new;
-  a.J_mol[c] = J;
+  double J;
+  if (a.update) {
+    double s = 0.0;
+    const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
+    for (int t = b; t < e; ++t) s += a.d_mol[a.mol_perm[t]];
+    const double p_new = s * a.pfac;
+    J = (p_new - a.P_c[c]) * a.inv_dt;
+    a.P_c[c] = p_new;
+    a.J_mol[c] = J;
+  } else {
+    J = a.J_mol[c];
+  }
   const int cell = a.occ_cell[c];
   const int m = a.mat[cell] & 3;
   T* Ex = static_cast<T*>(a.Ex);

@@ -37,6 +37,7 @@ struct MolArgs {
   int nj;
   int n_steps;          // 0: readouts only, state untouched
   int kdiss;            // first radial index with r > r_diss
+  int kmask;            // first radial index where the absorber mask is below one
   int want_d, want_norm, want_yield;
   double dr;
   void* psi;            // cx<T> [n_mol][2][nj][n_r]

@@ -35,6 +35,10 @@ struct FftShape {
 
 template <int NR, typename T>
 constexpr int line_stride() { return NR + FftShape<NR, T>::R2; }
+template <int NR, typename T>
+__device__ __forceinline__ int lds_row(int line) {
+  return lds_line_start(line, line_stride<NR, T>(), static_cast<int>(sizeof(cx<T>)));
+}
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -250,10 +254,12 @@ __device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short
 }
 
 // frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16
-__device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int nj,
+template <int NR>
+__device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj,
                                            const unsigned short* __restrict__ frag,
                                            const float* __restrict__ x,
                                            const float* __restrict__ mudt, float E) {
+  using T = float;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
@@ -280,8 +286,8 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int
       const int J = rb + i;
       cx<float> g = {0.f, 0.f}, e = {0.f, 0.f};
       if (J < nj) {
-        g = sh[J * LS + r];
-        e = sh[(nj + J) * LS + r];
+        g = sh[lds_row<NR, T>(J) + r];
+        e = sh[lds_row<NR, T>(nj + J) + r];
       }
       gr[i] = g.x; gi[i] = g.y; er[i] = e.x; ei[i] = e.y;
     }
@@ -326,8 +332,8 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int LS, int NR, int
     for (int i = 0; i < 4; ++i) {
       const int J = rb + i;
       if (J < nj) {
-        sh[J * LS + r] = {cgr[i], cgi[i]};
-        sh[(nj + J) * LS + r] = {cer[i], cei[i]};
+        sh[lds_row<NR, T>(J) + r] = {cgr[i], cgi[i]};
+        sh[lds_row<NR, T>(nj + J) + r] = {cer[i], cei[i]};
       }
     }
   }
@@ -373,8 +379,8 @@ struct MfmaK4<double> {
 
 // frag: [2][64 lanes][4]: block 0 A_i = T[l%16][row(l/16, i)], block 1 the
 // transpose T[row(l/16, i)][l%16]; zero outside nj.
-template <typename T>
-__device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int LS, int NR, int nj,
+template <typename T, int NR>
+__device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj,
                                                     const T* __restrict__ frag,
                                                     const T* __restrict__ x,
                                                     const T* __restrict__ mudt, T E) {
@@ -402,8 +408,8 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int LS, int NR, i
       const int J = rows[i];
       cx<T> g = {T(0), T(0)}, e = {T(0), T(0)};
       if (J < nj) {
-        g = sh[J * LS + r];
-        e = sh[(nj + J) * LS + r];
+        g = sh[lds_row<NR, T>(J) + r];
+        e = sh[lds_row<NR, T>(nj + J) + r];
       }
       cgr[i] = g.x; cgi[i] = g.y; cer[i] = e.x; cei[i] = e.y;
     }
@@ -440,8 +446,8 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int LS, int NR, i
     for (int i = 0; i < 4; ++i) {
       const int J = rows[i];
       if (J < nj) {
-        sh[J * LS + r] = {cgr[i], cgi[i]};
-        sh[(nj + J) * LS + r] = {cer[i], cei[i]};
+        sh[lds_row<NR, T>(J) + r] = {cgr[i], cgi[i]};
+        sh[lds_row<NR, T>(nj + J) + r] = {cer[i], cei[i]};
       }
     }
   }
@@ -477,6 +483,15 @@ __device__ __forceinline__ void block_sum4(double* v, double* red) {
 template <typename T>
 __device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
 
+// absorber mask at one point: the removed probability is accumulated in FP64
+template <typename T>
+__device__ __forceinline__ void absorb_point(cx<T>& v, T m, double& ab) {
+  if (m != T(1)) {
+    ab += static_cast<double>((T(1) - m * m) * norm2(v));
+    v = cscale(v, m);
+  }
+}
+
 // --------------------------------------------------------------- kernel
 // Occupancy target (waves per SIMD) of the fused step.  The FP32 forms
 // (three waves per molecule at J_max = 10, n_r = 256) run three molecules per
@@ -493,12 +508,11 @@ template <typename T, int NR, int CP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T>::waves)))
 void mol_step_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
-  constexpr int LS = line_stride<NR, T>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int nj = a.nj;
   const int L = 2 * nj;
   cx<T>* sh = reinterpret_cast<cx<T>*>(smem);
-  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * L * LS);
+  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * lds_row<NR, T>(L));
 
   const int mol = blockIdx.x;
   const int tid = threadIdx.x;
@@ -542,7 +556,7 @@ void mol_step_kernel(MolArgs a) {
   const T E = static_cast<T>(Ed);
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
-  cx<T>* slot = sh + line * LS;
+  cx<T>* slot = sh + lds_row<NR, T>(line);
   const int loff = line * NR + q;  // this lane's first element of its line
   cx<T> v[R1];
   if (active) {
@@ -566,47 +580,54 @@ void mol_step_kernel(MolArgs a) {
     }
     __syncthreads();
     if constexpr (CP == kCpBf16x3) {
-      coupling_mfma(sh, LS, NR, nj, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag), tb.x,
+      coupling_mfma<NR>(sh, nj, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag), tb.x,
                     tb.mudt, E);
     } else {
       const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
-      coupling_mfma_exact<T>(sh, LS, NR, nj, frag, tb.x, tb.mudt, E);
+      coupling_mfma_exact<T, NR>(sh, nj, frag, tb.x, tb.mudt, E);
     }
     __syncthreads();
     if (active) {
 #pragma unroll
       for (int p = 0; p < R1; ++p) v[p] = phase_mul(slot[q + R2 * p], vph[loff + R2 * p]);
       kinetic_half<T, NR>(v, slot, q, opaque(kin), opaque(tw));
+      // absorber: when it lies within the last quarter of the grid only
+      // those registers are tested (one uniform branch), otherwise all
+      constexpr int P0 = (3 * R1) / 4;
+      if (a.kmask >= R2 * P0) {
 #pragma unroll
-      for (int p = 0; p < R1; ++p) {
-        const T m = mask[q + R2 * p];
-        if (m != T(1)) {
-          ab += static_cast<double>((T(1) - m * m) * norm2(v[p]));
-          v[p] = cscale(v[p], m);
-        }
+        for (int p = P0; p < R1; ++p) absorb_point(v[p], mask[q + R2 * p], ab);
+      } else {
+#pragma unroll
+        for (int p = 0; p < R1; ++p) absorb_point(v[p], mask[q + R2 * p], ab);
       }
     }
   }
 
-  // readouts of the final state
+  // readouts of the final state (the norm also when no dipole is asked
+  // for, as the finiteness check)
   double nrm = 0.0, yld = 0.0, dd = 0.0;
+  const bool want_n = a.want_norm || !a.want_d;
   if (active) {
+    if (want_n || a.want_yield) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) {
-      const int r = q + R2 * p;
-      const double n2 = static_cast<double>(norm2(v[p]));
-      nrm += n2;
-      if (r >= a.kdiss) yld += n2;
-      slot[r] = v[p];
+      for (int p = 0; p < R1; ++p) {
+        const int r = q + R2 * p;
+        const double n2 = static_cast<double>(norm2(v[p]));
+        nrm += n2;
+        if (r >= a.kdiss) yld += n2;
+      }
     }
+#pragma unroll
+    for (int p = 0; p < R1; ++p) slot[q + R2 * p] = v[p];
   }
   if (a.want_d) {
     __syncthreads();
     for (int r = tid; r < NR; r += nthr) {
       double acc = 0.0;
-      cx<T> g0 = sh[r], e0 = sh[nj * LS + r];
+      cx<T> g0 = sh[r], e0 = sh[lds_row<NR, T>(nj) + r];
       for (int J = 0; J + 1 < nj; ++J) {
-        const cx<T> g1 = sh[(J + 1) * LS + r], e1 = sh[(nj + J + 1) * LS + r];
+        const cx<T> g1 = sh[lds_row<NR, T>(J + 1) + r], e1 = sh[lds_row<NR, T>(nj + J + 1) + r];
         const double t = static_cast<double>(g0.x) * e1.x + static_cast<double>(g0.y) * e1.y +
                          static_cast<double>(g1.x) * e0.x + static_cast<double>(g1.y) * e0.y;
         acc += tb.cj[J] * t;
@@ -641,7 +662,8 @@ int launch_mol_t(const MolArgs& a, hipStream_t s) {
   const int L = 2 * a.nj;
   int threads = ((L * R2 + 63) / 64) * 64;
   if (threads < 64) threads = 64;
-  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(L) * line_stride<NR, T>() + 16 * 4 * sizeof(double);
+  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, line_stride<NR, T>(), sizeof(cx<T>))) +
+                     16 * 4 * sizeof(double);
   static bool attr_set = false;
   if (!attr_set && shm > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, CP>),

@@ -33,7 +33,8 @@ EA0 = 8.4783536255e-30
 EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
-           "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step"]
+           "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
+           "bloch_init", "bloch_step", "coupled_bloch_step"]
 
 
 class MsqdError(RuntimeError):
@@ -74,7 +75,7 @@ class fdtd_fields(C.Structure):
 
 class cpl_desc(C.Structure):
     _fields_ = [("qd", qd_desc), ("fd", fdtd_desc), ("n_occ", C.c_int32),
-                ("mol_weight", C.c_double)]
+                ("mol_weight", C.c_double), ("mol_every", C.c_int32)]
 
 
 class cpl_state(C.Structure):
@@ -83,6 +84,23 @@ class cpl_state(C.Structure):
                 ("cell_of_mol", C.c_void_p), ("occ_cell", C.c_void_p), ("occ_ptr", C.c_void_p),
                 ("mol_perm", C.c_void_p), ("f", fdtd_fields), ("qd_ws", C.c_void_p),
                 ("fd_ws", C.c_void_p)]
+
+
+class bloch_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("prec", C.c_int32), ("omega0_au", C.c_double),
+                ("mu_au", C.c_double), ("gamma1_au", C.c_double), ("gamma2_au", C.c_double),
+                ("dt_au", C.c_double)]
+
+
+class cpl_bloch_desc(C.Structure):
+    _fields_ = [("bl", bloch_desc), ("fd", fdtd_desc), ("n_occ", C.c_int32), ("weight", C.c_double)]
+
+
+class cpl_bloch_state(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("d_mol", C.c_void_p), ("E_mol", C.c_void_p),
+                ("P_c", C.c_void_p), ("J_mol", C.c_void_p), ("cell_of_mol", C.c_void_p),
+                ("occ_cell", C.c_void_p), ("occ_ptr", C.c_void_p), ("mol_perm", C.c_void_p),
+                ("f", fdtd_fields), ("fd_ws", C.c_void_p)]
 
 
 class cpl_adj(C.Structure):
@@ -117,6 +135,10 @@ _sigs = {
                                      _vp]),
     "adjoint_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _vp, _vp,
                                C.POINTER(cpl_adj), C.c_int64, _vp, _vp]),
+    "bloch_init": (C.c_int, [C.POINTER(bloch_desc), _vp, _vp]),
+    "bloch_step": (C.c_int, [C.POINTER(bloch_desc), _vp, _vp, _vp, C.c_int32, _vp]),
+    "coupled_bloch_step": (C.c_int, [C.POINTER(cpl_bloch_desc), C.POINTER(cpl_bloch_state), _dp,
+                                     C.c_int64, C.c_int32, _vp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(lib, _name)
@@ -265,11 +287,11 @@ class Molecules:
         qd_init(self.desc, U_g, U_e, mu12, psi0, self.ws, self.psi, self.absorbed)
 
     @classmethod
-    def from_config(cls, cfg, n_mol=None, prec=None):
+    def from_config(cls, cfg, n_mol=None, prec=None, dt_au=None):
         from workloads.molecule_inputs import morse_v0, potentials
         ug, ue, mu = potentials(cfg)
         return cls(cfg.n_mol if n_mol is None else n_mol, cfg.n_r, cfg.j_max, cfg.r_min, cfg.r_max,
-                   cfg.mass, cfg.dt_au, ug, ue, mu, morse_v0(cfg),
+                   cfg.mass, cfg.dt_au if dt_au is None else dt_au, ug, ue, mu, morse_v0(cfg),
                    prec or cfg.precision, cfg.absorb_width, cfg.r_diss)
 
     def step(self, E_mol, n_steps=1, want_d=True):
@@ -344,7 +366,7 @@ class Coupled:
     """The self-consistent system: molecules + fields + maps, driven by
     coupled_step."""
 
-    def __init__(self, cfg, prec=None, n_mol=None, cells=None, mat=None, n_freq=None):
+    def __init__(self, cfg, prec=None, n_mol=None, cells=None, mat=None, n_freq=None, mol_every=1):
         from workloads.geometry import material_map
         prec = prec or cfg.precision
         self.cfg = cfg
@@ -367,7 +389,9 @@ class Coupled:
             cells = cells[:n_mol]
             occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
         self.cells_host = cells
-        self.mol = Molecules.from_config(cfg, n_mol=len(cells), prec=prec)
+        self.mol_every = max(1, int(mol_every))
+        self.mol = Molecules.from_config(cfg, n_mol=len(cells), prec=prec,
+                                         dt_au=cfg.dt_au * self.mol_every)
         it = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=dev)  # noqa: E731
         self.cell_of_mol = it(cells)
         self.occ_cell = it(occ)
@@ -377,7 +401,8 @@ class Coupled:
         self.E_mol = torch.zeros(max(nm, 1), dtype=torch.float64, device=dev)
         self.P_c = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
         self.J_mol = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
-        self.desc = cpl_desc(self.mol.desc, self.fields.desc, len(occ), float(cfg.mol_weight))
+        self.desc = cpl_desc(self.mol.desc, self.fields.desc, len(occ), float(cfg.mol_weight),
+                             self.mol_every)
         self.state = cpl_state(C.c_void_p(self.mol.psi.data_ptr()),
                                C.c_void_p(self.mol.absorbed.data_ptr()),
                                C.c_void_p(self.mol.d.data_ptr()), C.c_void_p(self.E_mol.data_ptr()),
@@ -445,6 +470,77 @@ class Coupled:
         return adj, t
 
 
+class Bloch:
+    """Frozen two-level emitters: descriptor and the [3][n] state planes."""
+
+    def __init__(self, n, omega0, mu, dt_au, prec="fp64", gamma1=0.0, gamma2=0.0):
+        self.prec = PREC[prec] if isinstance(prec, str) else prec
+        self.desc = bloch_desc(int(n), self.prec, float(omega0), float(mu), float(gamma1),
+                               float(gamma2), float(dt_au))
+        dt = torch.float64 if self.prec == FP64 else torch.float32
+        self.state = torch.empty((3, max(int(n), 1)), dtype=dt, device=_dev())
+        self.d = torch.zeros(max(int(n), 1), dtype=torch.float64, device=_dev())
+        _check(lib.bloch_init(C.byref(self.desc), _ptr(self.state), current_stream()))
+
+    @classmethod
+    def from_config(cls, cfg, n=None, prec=None, dt_au=None):
+        from workloads.molecule_inputs import bloch_parameters
+        w0, mu = bloch_parameters(cfg)
+        return cls(cfg.n_mol if n is None else n, w0, mu, cfg.dt_au if dt_au is None else dt_au,
+                   prec or cfg.precision)
+
+    def step(self, E, n_steps=1):
+        _check(lib.bloch_step(C.byref(self.desc), _ptr(self.state), _ptr(E), _ptr(self.d),
+                              int(n_steps), current_stream()))
+
+
+class CoupledBloch:
+    """The coupled system with Bloch emitters in place of the wavepackets."""
+
+    def __init__(self, cfg, prec=None, model=None, cells=None, mat=None, n_freq=None):
+        from workloads.geometry import material_map
+        prec = prec or cfg.precision
+        self.cfg = cfg
+        dev = _dev()
+        if mat is None:
+            mat = material_map(cfg)
+        self.fields = Fields(fdtd_desc_from_config(cfg, prec, n_freq), mat, cfg.freqs)
+        if cells is None:
+            if cfg.placement == "block":
+                from workloads.molecule_inputs import block_cell_list
+                cells = block_cell_list(cfg)
+                occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
+            else:
+                cells, occ, ptr, perm = map_build(cfg.n_mol, cfg.nx, cfg.ny, cfg.nz, cfg.seed,
+                                                  cfg.slab_k0, cfg.slab_nk)
+        else:
+            cells = np.asarray(cells, np.int32)
+            occ, ptr, perm = map_csr(cells, cfg.nx * cfg.ny * cfg.nz)
+        n = len(cells)
+        if model is None:
+            self.em = Bloch.from_config(cfg, n=n, prec=prec)
+        else:
+            w0, mu = model
+            self.em = Bloch(n, w0, mu, cfg.dt_au, prec)
+        it = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=dev)  # noqa: E731
+        self.cell_of_mol, self.occ_cell, self.occ_ptr, self.mol_perm = it(cells), it(occ), it(ptr), it(perm)
+        self.E_mol = torch.zeros(max(n, 1), dtype=torch.float64, device=dev)
+        self.P_c = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
+        self.J_mol = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
+        self.desc = cpl_bloch_desc(self.em.desc, self.fields.desc, len(occ), float(cfg.mol_weight))
+        self.state = cpl_bloch_state(_ptr(self.em.state), _ptr(self.em.d), _ptr(self.E_mol),
+                                     _ptr(self.P_c), _ptr(self.J_mol), _ptr(self.cell_of_mol),
+                                     _ptr(self.occ_cell), _ptr(self.occ_ptr), _ptr(self.mol_perm),
+                                     self.fields.f, _ptr(self.fields.ws))
+        self.n = 0
+
+    def step(self, src_values):
+        src, psrc = _np_dp(np.atleast_1d(src_values))
+        _check(lib.coupled_bloch_step(C.byref(self.desc), C.byref(self.state), psrc, self.n, len(src),
+                                      current_stream()))
+        self.n += len(src_values)
+
+
 def n_exports_ok():
     return all(hasattr(lib, n) for n in EXPORTS)
 
@@ -453,6 +549,6 @@ def version():
     return lib.msqd_version()
 
 
-__all__ = ["Molecules", "Fields", "Coupled", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
+__all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
            "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status",
            "MsqdError", "lib", "LIB_PATH", "EXPORTS"]

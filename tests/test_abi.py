@@ -96,3 +96,42 @@ def test_map_edge_cases(msqd):
         msqd.map_csr(np.array([0, 5, 64]), 64)  # index out of range
     occ, ptr, perm = msqd.map_csr(np.array([5, 2, 5, 5, 2]), 64)
     assert list(occ) == [2, 5] and list(ptr) == [0, 2, 5] and list(perm) == [1, 4, 0, 2, 3]
+
+
+def test_coupled_step_checks_multirate_step(msqd):
+    """coupled_step validates on the host, before any launch: the molecular
+    step must be mol_every field steps (here 4 dt against mol_every = 5), and
+    a negative mol_every is rejected.  The device pointers are never touched
+    (placeholder aligned addresses)."""
+    from workloads import get_config
+    cfg = get_config("cfg0")
+    qd = msqd.qd_desc(64, cfg.n_r, cfg.j_max, msqd.FP64, cfg.r_min, cfg.r_max, cfg.mass,
+                      cfg.dt_au * 4, cfg.absorb_width, cfg.r_diss)
+    fd = msqd.fdtd_desc_from_config(cfg, "fp64")
+    fake = C.c_void_p(1 << 20)
+    f = msqd.fdtd_fields(*([fake] * 11), fake)
+    st = msqd.cpl_state(fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, f, fake, fake)
+    src = np.zeros(1)
+    for every, code in [(5, msqd.MSQD_EINVAL), (-1, msqd.MSQD_EINVAL)]:
+        d = msqd.cpl_desc(qd, fd, 8, 1.0, every)
+        rc = msqd.lib.coupled_step(C.byref(d), C.byref(st), src.ctypes.data_as(C.POINTER(C.c_double)),
+                                   0, 1, None)
+        assert rc == code, (every, rc, msqd.last_error())
+    assert "mol_every" in msqd.last_error()
+    d = msqd.cpl_desc(qd, fd, 8, 1.0, 5)
+    rc = msqd.lib.coupled_step(C.byref(d), C.byref(st), src.ctypes.data_as(C.POINTER(C.c_double)),
+                               0, 1, None)
+    assert "mol_every" in msqd.last_error() and rc == msqd.MSQD_EINVAL
+
+
+def test_bloch_validation(msqd):
+    d = msqd.bloch_desc(10, msqd.FP64, 0.3, 1.0, 0.0, 0.0, -0.1)
+    assert msqd.lib.bloch_step(C.byref(d), None, None, None, 1, None) == msqd.MSQD_EINVAL
+    assert "dt_au" in msqd.last_error()
+    d = msqd.bloch_desc(10, 9, 0.3, 1.0, 0.0, 0.0, 0.1)
+    assert msqd.lib.bloch_init(C.byref(d), None, None) == msqd.MSQD_EPREC
+    d = msqd.bloch_desc(10, msqd.FP64, 0.3, 1.0, -1.0, 0.0, 0.1)
+    assert msqd.lib.bloch_step(C.byref(d), None, None, None, 1, None) == msqd.MSQD_EINVAL
+    d = msqd.bloch_desc(10, msqd.FP64, 0.3, 1.0, 0.0, 0.0, 0.1)
+    assert msqd.lib.bloch_step(C.byref(d), None, None, None, 1, None) == msqd.MSQD_EINVAL
+    assert "NULL" in msqd.last_error()

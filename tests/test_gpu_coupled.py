@@ -80,3 +80,49 @@ def test_coupled_tiny_reduced_precision_dipole_error(prec):
     err = np.linalg.norm(D - tr["D"]) / np.linalg.norm(tr["D"])
     print(f"{prec} relative dipole-trace error {err:.3e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("mol_every", [4, 7])
+def test_coupled_multirate_fp64_matches_oracle(mol_every):
+    """Molecules every M field steps (one molecular step of M dt under E_x^n,
+    the held current applied at every field step): the tiny workload over
+    steps 150..400 (the pulse crosses the molecules), FP64, against the
+    oracle's multi-rate scheme at 1e-10.  M = 7 does not divide the window
+    start or length, so updates fall inside calls of several steps."""
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg0")
+    n0, nsteps = 150, 250
+    banner(f"coupled cfg0 fp64 multi-rate M={mol_every}, steps {n0}..{n0 + nsteps}")
+    src = source_values(cfg, n0, nsteps)
+    sysm = msqd.Coupled(cfg, prec="fp64", mol_every=mol_every)
+    sysm.n = n0
+    D = np.zeros(nsteps)
+    chunk = 3
+    for s in range(0, nsteps, chunk):
+        sysm.step(src[s:s + chunk])
+        D[s:s + chunk] = float(sysm.mol.d.sum())   # constant between updates
+    torch.cuda.synchronize()
+    o = CoupledOracle(cfg, mol_every=mol_every)
+    Do = np.zeros(nsteps)
+    for s in range(nsteps):
+        o.step(n0 + s, src[s])
+        Do[s] = o.d.sum()
+    idx = np.arange(chunk - 1, nsteps, chunk)
+    assert np.abs(Do[idx]).max() > 0
+    assert np.linalg.norm(D[idx] - Do[idx]) / np.linalg.norm(Do[idx]) < 1e-10
+    f = sysm.fields
+    emax = max(np.abs(e).max() for e in o.yee.E)
+    for c, nm in enumerate(["Ex", "Ey", "Ez"]):
+        assert np.abs(getattr(f, nm).cpu().numpy() - o.yee.E[c]).max() < 1e-10 * emax, nm
+    assert rel_err(sysm.mol.psi.cpu().numpy(), o.psi) < 1e-10
+    assert rel_err(sysm.P_c.cpu().numpy(), o.P) < 1e-10
+    assert rel_err(sysm.J_mol.cpu().numpy(), o.Jmol) < 1e-10
+
+
+def test_coupled_multirate_rejects_step_mismatch():
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg0")
+    sysm = msqd.Coupled(cfg, prec="fp64", mol_every=4)
+    sysm.desc.mol_every = 5            # molecules were built for 4 dt
+    with pytest.raises(msqd.MsqdError):
+        sysm.step(np.zeros(2))

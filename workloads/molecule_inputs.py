@@ -60,3 +60,15 @@ def block_cell_list(cfg) -> np.ndarray:
                 out[idx] = (k * cfg.ny + j) * cfg.nx + i
                 idx += 1
     return out
+
+
+def bloch_parameters(cfg: Config):
+    """Two-level parameters of the workload's molecule with its ro-vibrations
+    frozen at r_e: (omega0, mu) in atomic units, omega0 the vertical gap
+    U_e(r_e) - U_g(r_e) and mu = mu12(r_e) / sqrt(3), the J = 0 -> 1 matrix
+    element of cos(theta) times the transition dipole."""
+    re = cfg.morse_re
+    ug = 0.0 if not cfg.morse_shift else -cfg.morse_d
+    ue = cfg.ue_c0 + cfg.ue_c1 * math.exp(-cfg.ue_b * (re - cfg.ue_r0))
+    mu = math.exp(-cfg.mu_b * (re - cfg.mu_r0) ** 2) / math.sqrt(3.0)
+    return ue - ug, mu
