@@ -183,6 +183,47 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def run_bloch(cfg, steps, warmup, n0, n_emitters):
+    """Coupled step with frozen two-level emitters in place of the
+    wavepackets (the paper's Bloch/RK4 comparison), timed like run_coupled;
+    plus the emitter kernel alone (bloch_step on a field array)."""
+    import torch
+
+    from paper_2209_04487_amd import msqd
+    from workloads.pulses import source_values
+    c = cfg.replace(n_mol=n_emitters)
+    sysm = msqd.CoupledBloch(c, prec="fp32")
+    src = source_values(c, n0, warmup + steps)
+    sysm.n = n0
+    sysm.step(src[:warmup])
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(torch.cuda.current_stream())
+    sysm.step(src[warmup:])
+    b.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    em = sysm.em
+    E = torch.full((n_emitters,), 1e-3, dtype=torch.float64, device="cuda")
+    em.step(E)
+    torch.cuda.synchronize()
+    a.record(torch.cuda.current_stream())
+    for _ in range(20):
+        em.step(E)
+    b.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    kms = a.elapsed_time(b) / 20
+    kbytes = n_emitters * (2 * 12 + 8 + 8)     # state in and out, field in, dipole out
+    out = {"n_emitters": n_emitters, "ms_per_step": ms / steps,
+           "emitter_steps_per_s": n_emitters * steps / (ms / 1e3),
+           "kernel_ms": kms, "kernel_GBs": kbytes / (kms / 1e3) / 1e9,
+           "kernel_frac_hbm": kbytes / (kms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    del sysm
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibration_copy(nbytes=1 << 30, reps=3):
     """Device-to-device copies of a known size, for scaling the HBM byte
     counters of a counter run (FETCH_SIZE / WRITE_SIZE) to bytes."""
@@ -358,6 +399,9 @@ def main():
                  "field_steps_per_s": k_mr / (mr["ms"] / 1e3),
                  "molecule_steps_per_s": mr["n_mol"] * (k_mr // M) / (mr["ms"] / 1e3)}
 
+    log("Bloch-emitter coupled run: 691,200 emitters")
+    bloch = run_bloch(cfg, K, W, n0, 691_200)
+
     log("kernel timing")
     launches = max(10, min(K, 100))
     mol_ms = time_mol_kernel(cfg, "mixed", launches)
@@ -415,6 +459,7 @@ def main():
         "speedup_vs_fp64": None if fp64 is None else fp64["ms"] / mixed["ms"],
         "accuracy_vs_fp64": acc,
         "multirate": multirate,
+        "bloch_emitters": bloch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

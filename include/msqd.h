@@ -102,6 +102,15 @@ int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
 int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
                    double* d_mol, double* norm_mol, double* yield_mol, void* stream);
 
+/* Excited-state internuclear distance, Eq. (8): per molecule (float64,
+ * device) r_num = <chi_e|R|chi_e> = sum_{J,k} r_k |psi_e,J(r_k)|^2 dr and
+ * pop = <chi_e|chi_e>; the ratio is the molecule's <R>_e.  sums: device
+ * float64 [2] = (sum r_num, sum pop) over all molecules in a fixed order (the
+ * ensemble <R>_e is their ratio), or NULL.  ws is unused but validated like
+ * the other readouts.  Errors: MSQD_EINVAL for NULL outputs. */
+int excited_r_readout(const qd_desc* d, const void* ws, const void* psi, double* r_num, double* pop,
+                      double* sums, void* stream);
+
 /* Synchronise `stream`, then report MSQD_ENONFINITE (and clear the flag) if
  * any molecular step since the last check produced a non-finite dipole,
  * norm or absorbed norm; MSQD_OK otherwise.  ws is a qd workspace. */
@@ -127,6 +136,8 @@ typedef struct {
   int32_t mon_k;          /* detection plane (npml < mon_k < nz - npml)     */
   int32_t n_freq;         /* monitor frequencies (0 = no monitor)           */
   int32_t mon_every;      /* monitor sampling interval in steps             */
+  int32_t mon_k2;         /* second detection plane on the incident side for
+                             reflection/absorption spectra (0 = none)       */
 } fdtd_desc;
 
 /* Device buffers of the field solver; element type is double (FP64) or
@@ -137,7 +148,8 @@ typedef struct {
   void* psi;       /* CPML auxiliaries: 4 x [2*npml][ny][nx] (psi_Ex, psi_Ey, psi_Hx, psi_Hy),
                       planes k < npml then k >= nz - npml                    */
   uint8_t* mat;    /* [3][nz][ny][nx] material id per E-component location  */
-  double* dft;     /* [4][n_freq][ny][nx] complex128 (E_x, E_y, H_x, H_y) or NULL */
+  double* dft;     /* [planes][4][n_freq][ny][nx] complex128 (E_x, E_y, H_x,
+                      H_y), planes = 2 with mon_k2, else 1; or NULL         */
 } fdtd_fields;
 
 size_t fdtd_workspace_bytes(const fdtd_desc* d);
@@ -159,7 +171,10 @@ int fdtd_step(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t 
               double src_value, void* stream);
 
 /* Plane-averaged z-flux S(w_f) = <1/2 Re(E_x H_y* - E_y H_x*)> of the monitor
- * DFTs into flux (device [n_freq] float64). */
+ * DFTs into flux (device float64 [planes][n_freq]: the mon_k plane, then the
+ * mon_k2 plane when set).  With a vacuum reference run's incident-side flux
+ * S_ref: T = S(mon_k)/S_ref, R = 1 - S(mon_k2)/S_ref, A = 1 - T - R (the
+ * short-pulse spectra of the section on 3D domain decomposition, Fig. 6a). */
 int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -62,6 +62,8 @@ class CoupledOracle:
         self.P = np.zeros(len(self.occ))
         self.Jmol = np.zeros(len(self.occ))
         self.monitor = FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k, cfg.freqs, cfg.dt, cfg.mon_every)
+        self.monitor2 = (FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k2, cfg.freqs, cfg.dt, cfg.mon_every)
+                         if cfg.mon_k2 else None)
         self.d = np.zeros(self.n_mol)
         self.e_mol = np.zeros(self.n_mol)
 
@@ -91,6 +93,8 @@ class CoupledOracle:
             self.e_mol = e_mol
         yee.update_E(src_value, cfg.src_k, self.occ, self.Jmol)
         self.monitor.sample(yee, n)
+        if self.monitor2 is not None:
+            self.monitor2.sample(yee, n)
         return self.e_mol
 
     def run(self, src_values, n0=0, record_fields=False):

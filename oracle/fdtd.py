@@ -218,6 +218,19 @@ class FluxMonitor:
         return s.mean(axis=(1, 2))
 
 
+def spectra(S_trans, S_inc_side, S_ref):
+    """Transmission, reflection and absorption from the net z-fluxes of one
+    run and of a vacuum reference run with the same source: S_trans on the
+    plane beyond the structure, S_inc_side on a plane between the source and
+    the structure (net flux = incident - reflected for plane waves), S_ref the
+    reference run's flux on that same incident-side plane.  T = S_trans/S_ref,
+    R = 1 - S_inc_side/S_ref, A = 1 - T - R (the spectra of the paper's
+    short-pulse technique, section on 3D domain decomposition and Fig. 6a)."""
+    T = np.asarray(S_trans) / np.asarray(S_ref)
+    R = 1.0 - np.asarray(S_inc_side) / np.asarray(S_ref)
+    return T, R, 1.0 - T - R
+
+
 def yee_from_config(cfg, mat, eps_table, periodic_z=False):
     return Yee(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dt, mat, eps_table, cfg.wp, cfg.gamma,
                cfg.npml, cfg.cpml_m, cfg.sigma_max_lo, cfg.sigma_max_hi,

@@ -165,6 +165,14 @@ class MoleculeModel:
         pe = np.sum(np.abs(psi[:, 1]) ** 2, axis=1)
         return np.sum(pe * self.r[None, :], axis=1) / np.sum(pe, axis=1)
 
+    def excited_r_moments(self, psi):
+        """Per molecule <chi_e|R|chi_e> and <chi_e|chi_e> (both states' J
+        lines summed over the excited state, times dr); the ensemble value
+        of Eq. (8) is sum(first) / sum(second), the excited population
+        weighting each molecule."""
+        pe = np.sum(np.abs(psi[:, 1]) ** 2, axis=1)
+        return (np.sum(pe * self.r[None, :], axis=1) * self.dr, np.sum(pe, axis=1) * self.dr)
+
     # ------------------------------------------------------------------- state
     def initial_state(self, n_mol, radial):
         """All molecules in (g, J=0) with the given radial function."""

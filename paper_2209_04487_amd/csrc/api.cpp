@@ -8,6 +8,7 @@
 
 #include "adjoint.h"
 #include "bloch.h"
+#include "readout.h"
 #include "fdtd.h"
 #include "host_tables.h"
 #include "mol.h"
@@ -128,6 +129,8 @@ static int check_qd(const qd_desc* d) {
   return MSQD_OK;
 }
 
+static int fd_planes(const fdtd_desc* d) { return (d->n_freq > 0 && d->mon_k2 != 0) ? 2 : 1; }
+
 static int check_fd(const fdtd_desc* d) {
   if (!d) return fail(MSQD_EINVAL, "fdtd_desc is NULL");
   if (d->nx < 1 || d->ny < 1 || d->nz < 4) return fail(MSQD_EINVAL, "grid too small");
@@ -148,6 +151,8 @@ static int check_fd(const fdtd_desc* d) {
     if (d->mon_k <= d->npml || d->mon_k >= d->nz - d->npml)
       return fail(MSQD_EINVAL, "mon_k must be inside the interior");
     if (d->mon_every < 1) return fail(MSQD_EINVAL, "mon_every must be >= 1");
+    if (d->mon_k2 != 0 && (d->mon_k2 <= d->npml || d->mon_k2 >= d->nz - d->npml))
+      return fail(MSQD_EINVAL, "mon_k2 must be 0 or inside the interior");
   }
   return MSQD_OK;
 }
@@ -401,6 +406,26 @@ int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const doub
   return launch_mol(d, a, static_cast<hipStream_t>(stream));
 }
 
+int excited_r_readout(const qd_desc* d, const void* ws, const void* psi, double* r_num, double* pop,
+                      double* sums, void* stream) {
+  int rc = check_qd(d);
+  if (rc) return rc;
+  if (d->n_mol == 0) return MSQD_OK;
+  if (!ws || !psi || !r_num || !pop) return fail(MSQD_EINVAL, "NULL pointer");
+  RdArgs a{};
+  a.n_mol = d->n_mol;
+  a.nj = d->j_max + 1;
+  a.n_r = d->n_r;
+  a.r_min = d->r_min;
+  a.dr = (d->r_max - d->r_min) / d->n_r;
+  a.psi = psi;
+  a.r_num = r_num;
+  a.pop = pop;
+  a.sums = sums;
+  const int e = launch_excited_r(a, d->prec != MSQD_FP64, static_cast<hipStream_t>(stream));
+  return e ? check_hip(static_cast<hipError_t>(e), "excited-state readout launch") : MSQD_OK;
+}
+
 int msqd_check_status(const void* ws, void* stream) {
   if (!ws) return fail(MSQD_EINVAL, "workspace NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -430,7 +455,7 @@ size_t fdtd_psi_bytes(const fdtd_desc* d) {
 
 size_t fdtd_dft_bytes(const fdtd_desc* d) {
   if (check_fd(d) != MSQD_OK) return 0;
-  return 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
+  return fd_planes(d) * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
 }
 
 static void cpml_profile(const fdtd_desc* d, double offset, std::vector<double>& b,
@@ -528,8 +553,14 @@ static int fd_monitor(const fdtd_desc* d, const fdtd_fields* f, const void* ws, 
   m.Hy = f->Hy;
   m.dft = f->dft;
   m.freqs = reinterpret_cast<const double*>(static_cast<const char*>(ws) + fd_layout(d).freqs);
-  const int e = launch_monitor(m, d->prec != MSQD_FP64, s);
+  int e = launch_monitor(m, d->prec != MSQD_FP64, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
+  if (fd_planes(d) == 2) {
+    m.mon_k = d->mon_k2;
+    m.dft = f->dft + 2 * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx;
+    e = launch_monitor(m, d->prec != MSQD_FP64, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
+  }
   return MSQD_OK;
 }
 
@@ -557,8 +588,12 @@ int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* s
   if (rc) return rc;
   if (d->n_freq <= 0) return fail(MSQD_EINVAL, "no monitor frequencies");
   if (!f || !f->dft || !flux) return fail(MSQD_EINVAL, "NULL pointer");
-  const int e = launch_flux(d->nx, d->ny, d->n_freq, f->dft, flux, static_cast<hipStream_t>(stream));
-  if (e) return check_hip(static_cast<hipError_t>(e), "flux launch");
+  const size_t plane = 2 * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx;  // doubles
+  for (int p = 0; p < fd_planes(d); ++p) {
+    const int e = launch_flux(d->nx, d->ny, d->n_freq, f->dft + p * plane, flux + p * d->n_freq,
+                              static_cast<hipStream_t>(stream));
+    if (e) return check_hip(static_cast<hipError_t>(e), "flux launch");
+  }
   return MSQD_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
-           "bloch_init", "bloch_step", "coupled_bloch_step"]
+           "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout"]
 
 
 class MsqdError(RuntimeError):
@@ -63,7 +63,8 @@ class fdtd_desc(C.Structure):
                 ("drude_gamma", C.c_double), ("cpml_m", C.c_double),
                 ("sigma_max_lo", C.c_double), ("sigma_max_hi", C.c_double),
                 ("kappa_max", C.c_double), ("alpha_max", C.c_double), ("src_k", C.c_int32),
-                ("mon_k", C.c_int32), ("n_freq", C.c_int32), ("mon_every", C.c_int32)]
+                ("mon_k", C.c_int32), ("n_freq", C.c_int32), ("mon_every", C.c_int32),
+                ("mon_k2", C.c_int32)]
 
 
 class fdtd_fields(C.Structure):
@@ -135,6 +136,7 @@ _sigs = {
                                      _vp]),
     "adjoint_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _vp, _vp,
                                C.POINTER(cpl_adj), C.c_int64, _vp, _vp]),
+    "excited_r_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp]),
     "bloch_init": (C.c_int, [C.POINTER(bloch_desc), _vp, _vp]),
     "bloch_step": (C.c_int, [C.POINTER(bloch_desc), _vp, _vp, _vp, C.c_int32, _vp]),
     "coupled_bloch_step": (C.c_int, [C.POINTER(cpl_bloch_desc), C.POINTER(cpl_bloch_state), _dp,
@@ -308,6 +310,32 @@ class Molecules:
         return d, nrm, yld
 
 
+def excited_r(mols):
+    """Eq. (8) readout of a Molecules batch: (per-molecule <R>_e numerators,
+    excited populations, ensemble <R>_e) as device tensors."""
+    n = max(mols.desc.n_mol, 1)
+    dev = mols.psi.device
+    num = torch.empty(n, dtype=torch.float64, device=dev)
+    pop = torch.empty(n, dtype=torch.float64, device=dev)
+    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    _check(lib.excited_r_readout(C.byref(mols.desc), _ptr(mols.ws), _ptr(mols.psi), _ptr(num),
+                                 _ptr(pop), _ptr(sums), current_stream()))
+    return num, pop, sums[0] / sums[1]
+
+
+def spectra(S_trans, S_inc_side, S_ref):
+    """T, R, A per monitor frequency from the flux readouts of a run (the
+    mon_k plane beyond the structure, the mon_k2 plane on the incident side)
+    and the incident-side flux of a reference run without the structure:
+    T = S_trans / S_ref, R = 1 - S_inc_side / S_ref, A = 1 - T - R."""
+    st = np.asarray(S_trans, np.float64)
+    si = np.asarray(S_inc_side, np.float64)
+    sr = np.asarray(S_ref, np.float64)
+    T = st / sr
+    R = (sr - si) / sr
+    return T, R, (si - st) / sr
+
+
 def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
     from workloads.geometry import eps_table
     p = PREC[prec or cfg.precision]
@@ -316,7 +344,7 @@ def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
     return fdtd_desc(cfg.nx, cfg.ny, cfg.nz, cfg.npml, p, 2, cfg.dx, cfg.dt,
                      (C.c_double * 4)(eps[0], eps[1], eps[2], 1.0), cfg.wp, cfg.gamma, cfg.cpml_m,
                      cfg.sigma_max_lo, cfg.sigma_max_hi, cfg.cpml_kappa_max, cfg.cpml_alpha_max,
-                     cfg.src_k, cfg.mon_k, nf, cfg.mon_every)
+                     cfg.src_k, cfg.mon_k, nf, cfg.mon_every, cfg.mon_k2)
 
 
 class Fields:
@@ -352,10 +380,17 @@ class Fields:
     def step(self, n, src_value):
         fdtd_step(self.desc, self.f, self.ws, n, src_value)
 
+    @property
+    def n_planes(self):
+        return 2 if (self.desc.n_freq > 0 and self.desc.mon_k2 != 0) else 1
+
     def flux(self):
-        out = torch.zeros(self.desc.n_freq, dtype=torch.float64, device=self.ws.device)
+        """Net z-flux per monitor frequency on the mon_k plane, or
+        [2, n_freq] (mon_k, then mon_k2) when the second plane is set."""
+        nf = self.desc.n_freq
+        out = torch.zeros(self.n_planes * nf, dtype=torch.float64, device=self.ws.device)
         flux_readout(self.desc, self.f, out)
-        return out
+        return out if self.n_planes == 1 else out.view(2, nf)
 
     def dft_planes(self):
         nf, ny, nx = self.desc.n_freq, self.desc.ny, self.desc.nx

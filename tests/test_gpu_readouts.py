@@ -1,0 +1,74 @@
+"""GPU parity of the spectroscopy readouts against the FP64 oracle:
+
+- the excited-state radial moments of Eq. (8) (excited_r_readout) on seeded
+  random states of several grid sizes, ragged molecule counts (FP64 1e-12,
+  FP32 states 1e-12 relative to the same FP32 state read in FP64) and the
+  ensemble <R>_e as the population-weighted ratio;
+- the two-plane monitor (transmitted side and incident side) of a coupled
+  run under the CW drive with a 5 fs turn-on: both planes' flux spectra at
+  1e-9 of the oracle's, and T/R/A from the GPU fluxes against the oracle's
+  spectra helper."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import banner, random_state, rel_err
+from oracle.coupled import CoupledOracle
+from oracle.fdtd import spectra as oracle_spectra
+from oracle.molecule import model_from_config
+from workloads import get_config
+from workloads.molecule_inputs import potentials
+from workloads.pulses import source_values
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,n_r,j_max,n_mol", [("fp64", 128, 4, 37), ("fp64", 256, 10, 5),
+                                                  ("fp32", 256, 10, 300), ("mixed", 64, 1, 1)])
+def test_excited_r_readout_matches_oracle(prec, n_r, j_max, n_mol):
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg0", n_r=n_r, j_max=j_max, n_mol=n_mol)
+    banner(f"excited_r_readout {prec} n_r={n_r} j_max={j_max} n_mol={n_mol}")
+    mols = msqd.Molecules.from_config(cfg, prec=prec)
+    psi = random_state(n_r + j_max, n_mol, j_max + 1, n_r, (cfg.r_max - cfg.r_min) / n_r)
+    mols.psi.copy_(torch.as_tensor(psi).to(mols.psi.dtype))
+    num, pop, ens = msqd.excited_r(mols)
+    torch.cuda.synchronize()
+    ug, ue, mu = potentials(cfg)
+    om = model_from_config(cfg, ug, ue, mu)
+    ref_psi = mols.psi.to(torch.complex128).cpu().numpy()     # the state as stored
+    onum, opop = om.excited_r_moments(ref_psi)
+    assert rel_err(num.cpu().numpy(), onum) < 1e-12
+    assert rel_err(pop.cpu().numpy(), opop) < 1e-12
+    assert abs(float(ens) - onum.sum() / opop.sum()) < 1e-12 * abs(onum.sum() / opop.sum())
+
+
+def test_two_plane_monitor_and_spectra_under_cw_drive():
+    from paper_2209_04487_amd import msqd
+    nsteps = 300
+    base = dict(pulse="cw", mon_k2=9, mol_weight=3e3, n_freq=8)
+    cfg = get_config("cfg0", **base)
+    ref_cfg = get_config("cfg0", n_mol=0, **base)
+    banner(f"coupled cfg0 fp64 CW drive, two monitor planes, {nsteps} steps")
+    src = source_values(cfg, 0, nsteps)
+    assert abs(src[0]) < 1e-3 * np.abs(src).max()            # smooth turn-on
+    sysm = msqd.Coupled(cfg, prec="fp64")
+    sysm.step(src)
+    S = sysm.fields.flux().cpu().numpy()
+    assert S.shape == (2, cfg.n_freq)
+    o = CoupledOracle(cfg)
+    for n in range(nsteps):
+        o.step(n, src[n])
+    scale = np.abs(o.monitor2.flux()).max()
+    assert np.abs(S[0] - o.monitor.flux()).max() < 1e-9 * scale
+    assert np.abs(S[1] - o.monitor2.flux()).max() < 1e-9 * scale
+    # vacuum reference run (no molecules) for the incident flux
+    ref = msqd.Coupled(ref_cfg, prec="fp64", cells=np.zeros(0, np.int32))
+    ref.step(src)
+    Sref = ref.fields.flux().cpu().numpy()
+    T, R, A = msqd.spectra(S[0], S[1], Sref[1])
+    oT, oR, oA = oracle_spectra(o.monitor.flux(), o.monitor2.flux(), Sref[1])
+    np.testing.assert_allclose(T, oT, rtol=1e-8)
+    np.testing.assert_allclose(R, oR, atol=1e-8)
+    np.testing.assert_allclose(A, oA, atol=1e-8)

@@ -105,6 +105,7 @@ def _run_1d(glass_from, nsteps, nz=300, dx=5e-9, npml=20, src_k=40, mon_k=220,
     yee = Yee(1, 1, nz, dx, dt, mat, [1.0, 2.25, 1.0], 0.0, 0.0, npml, 3.0,
               smax(1.0), smax(eps_hi))
     mon = FluxMonitor(1, 1, mon_k, omegas, dt, 1)
+    mon2 = FluxMonitor(1, 1, 100, omegas, dt, 1)
     tau = 1.0e-15
     t0 = 3.0e-15
     w0 = 0.10 / 2.4188843265857e-17
@@ -117,8 +118,10 @@ def _run_1d(glass_from, nsteps, nz=300, dx=5e-9, npml=20, src_k=40, mon_k=220,
         yee.update_H()
         yee.update_E(v, src_k)
         mon.sample(yee, n)
+        mon2.sample(yee, n)
         if record_energy:
             energy.append(yee.energy())
+    _run_1d.mon2 = mon2
     return yee, mon, np.array(src), dt, np.array(energy)
 
 
@@ -142,3 +145,32 @@ def test_cpml_absorbs_outgoing_pulse():
     omegas = np.array([0.1]) / 2.4188843265857e-17
     _, _, _, _, energy = _run_1d(None, 2400, omegas=omegas, record_energy=True)
     assert energy[-1] / energy.max() < 1e-6
+
+
+def test_reflection_and_absorption_spectra_of_a_dielectric_interface():
+    """Two detection planes (incident side and transmitted side) and a
+    vacuum reference run: a lossless glass interface reflects
+    ((n-1)/(n+1))^2, transmits 4n/(n+1)^2 and absorbs nothing."""
+    from oracle.fdtd import spectra
+    omegas = np.array([0.08, 0.10, 0.12]) / 2.4188843265857e-17
+    nsteps = 1500
+    _, mon_v, _, _, _ = _run_1d(None, nsteps, omegas=omegas)
+    ref2 = _run_1d.mon2.flux()
+    _, mon_g, _, _, _ = _run_1d(150, nsteps, omegas=omegas)
+    inc2 = _run_1d.mon2.flux()
+    T, R, A = spectra(mon_g.flux(), inc2, ref2)
+    n = 1.5
+    np.testing.assert_allclose(R, ((n - 1) / (n + 1)) ** 2, atol=2e-3)
+    np.testing.assert_allclose(T, 4 * n / (1 + n) ** 2, atol=2e-3)
+    np.testing.assert_allclose(A, 0.0, atol=3e-3)
+
+
+def test_product_spectra_helper_agrees_with_oracle_definition():
+    """The library's host helper (T, R, A from three flux spectra) against
+    the oracle's, on arbitrary positive spectra (no GPU needed)."""
+    from oracle.fdtd import spectra
+    from paper_2209_04487_amd.msqd import spectra as lib_spectra
+    rng = np.random.default_rng(2)
+    st, si, sr = rng.uniform(0.1, 1.0, (3, 16))
+    for a, b in zip(spectra(st, si, sr), lib_spectra(st, si, sr)):
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)

@@ -323,3 +323,24 @@ def test_dissociation_yield_identity():
     near = np.sum(np.abs(psi[..., m.r <= m.r_diss]) ** 2) * m.dr
     np.testing.assert_allclose(m.dissociated(psi, ab)[0], 1.0 - near, atol=1e-13)
     assert m.dissociated(psi, ab)[0] > 0.1
+
+
+def test_excited_mean_r_of_symmetric_packets():
+    """Eq. (8): a packet whose |chi_e|^2 is symmetric about a grid point r0
+    has <R>_e = r0 exactly; the ensemble value weights molecules by their
+    excited population; the ground state does not enter."""
+    m = _model(n_r=128, j_max=2)
+    psi = np.zeros((2, 2, m.n_j, m.n_r), complex)
+    k0, k1 = 40, 70
+    for mol, k in ((0, k0), (1, k1)):
+        g = np.exp(-((np.arange(m.n_r) - k) / 4.0) ** 2)
+        psi[mol, 1, 1] = g * (0.3 if mol == 0 else 0.9)
+        psi[mol, 1, 2] = 0.5j * g
+        psi[mol, 0, 0] = np.roll(g, 10)          # ground population elsewhere
+    mean = m.excited_mean_r(psi)
+    np.testing.assert_allclose(mean, [m.r[k0], m.r[k1]], rtol=1e-13)
+    num, pop = m.excited_r_moments(psi)
+    np.testing.assert_allclose(num / pop, mean, rtol=1e-13)
+    w = pop / pop.sum()
+    np.testing.assert_allclose(num.sum() / pop.sum(), w[0] * m.r[k0] + w[1] * m.r[k1], rtol=1e-13)
+    np.testing.assert_allclose(pop, np.sum(np.abs(psi[:, 1]) ** 2, axis=(1, 2)) * m.dr, rtol=1e-13)

@@ -49,6 +49,7 @@ class Config:
     freq_lo_h: float = 0.05
     freq_hi_h: float = 0.15
     mon_every: int = 4
+    mon_k2: int = 0                # incident-side detection plane (0 = none)
     # molecules
     n_mol: int = 64
     placement: str = "block"       # block | slab
@@ -77,7 +78,8 @@ class Config:
     absorb_width: float = 2.0
     r_diss: float = 8.0
     # incident pulse
-    pulse: str = "gauss"           # gauss | knots
+    pulse: str = "gauss"           # gauss | knots | cw
+    cw_ramp_fs: float = 5.0        # CW drive: sin^2 turn-on time
     omega_h: float = 0.10          # carrier, hartree
     fwhm_fs: float = 10.0
     e0_au: float = 1.0e-3

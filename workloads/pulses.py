@@ -69,6 +69,11 @@ def source_values(cfg: Config, n0: int = 0, n_steps: int | None = None,
         a = knot_values(cfg) if knots is None else np.asarray(knots, dtype=np.float64)
         env = np.interp(t, knot_times(cfg), a) * U.E_AU
         return env * np.cos(w * t)
+    if cfg.pulse == "cw":
+        # continuous wave switched on smoothly over the first cw_ramp_fs
+        t_on = cfg.cw_ramp_fs * U.FS
+        ramp = np.where(t < t_on, np.sin(0.5 * np.pi * np.clip(t, 0.0, None) / t_on) ** 2, 1.0)
+        return cfg.e0_au * U.E_AU * ramp * np.cos(w * t)
     raise ValueError(cfg.pulse)
 
 
