@@ -91,8 +91,16 @@ FdLayout fd_layout(const fdtd_desc* d) {
 
 size_t mol_lds_bytes(int n_r, int nj, int prec) {
   const size_t el = prec == MSQD_FP64 ? 16 : 8;
-  const int r2 = n_r / fft_r1(n_r, static_cast<int>(el / 2));
-  return el * static_cast<size_t>(lds_line_start(2 * nj, n_r + r2, static_cast<int>(el))) + 16 * 4 * sizeof(double);
+  const int r1 = fft_r1(n_r, static_cast<int>(el / 2));
+  const int r2 = n_r / r1;
+  // exchange rounds of the forward step (two for complex64 lines with an
+  // even number of columns per lane)
+  const int split = (el == 8 && (r1 / r2) % 2 == 0) ? 2 : 1;
+  // transform tables staged in LDS: kinetic factors, twiddles, mask
+  const bool staged = el == 8;
+  const size_t tables = staged ? (el * n_r + el * static_cast<size_t>(r1) * r1 + (el / 2) * n_r + 15) / 16 * 16 : 0;
+  return tables + el * static_cast<size_t>(lds_line_start(2 * nj, n_r / split + r2, static_cast<int>(el))) +
+         16 * 4 * sizeof(double);
 }
 
 size_t mol_lds_limit() {

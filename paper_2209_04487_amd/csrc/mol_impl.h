@@ -35,9 +35,43 @@ struct FftShape {
 
 template <int NR, typename T>
 constexpr int line_stride() { return NR + FftShape<NR, T>::R2; }
+
+// The fused forward step exchanges each line through LDS in SP rounds of
+// NR/SP radial points (the in-line transposes and the J<->angle exchange
+// alike), so that a molecule needs 1/SP of the LDS and more molecules fit on
+// a CU.  complex64 lines with an even number of columns per lane use two
+// rounds; complex128 lines (register-bound, one molecule per CU either way)
+// and the shortest grids use one.
+template <int NR, typename T>
+constexpr int fwd_split() {
+  return (sizeof(T) == 4 && (FftShape<NR, T>::R1 / FftShape<NR, T>::R2) % 2 == 0) ? 2 : 1;
+}
+template <int NR, typename T>
+constexpr int fwd_line_stride() { return NR / fwd_split<NR, T>() + FftShape<NR, T>::R2; }
+
+// Bytes of the per-workgroup LDS copy of the transform tables (kinetic
+// factors, four-step twiddles, absorber mask), kept ahead of the lines.
+// (complex64 forms only: the complex128 form holds one molecule per CU, where
+// the staged tables measured slower than reading them through the caches.)
+template <int NR, typename T>
+constexpr bool stage_tables() { return sizeof(T) == 4; }
+template <int NR, typename T>
+constexpr size_t lds_table_bytes() {
+  constexpr int R1 = FftShape<NR, T>::R1;
+  return stage_tables<NR, T>() ? ((NR * sizeof(cx<T>) + R1 * R1 * sizeof(cx<T>) + NR * sizeof(T)) + 15) / 16 * 16
+                               : 0;
+}
+
+// Cooperative copy of a table into LDS in 16-byte pieces.
+__device__ __forceinline__ void lds_stage(void* dst, const void* src, size_t bytes) {
+  const uint4* s = static_cast<const uint4*>(src);
+  uint4* d = static_cast<uint4*>(dst);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
 template <int NR, typename T>
 __device__ __forceinline__ int lds_row(int line) {
-  return lds_line_start(line, line_stride<NR, T>(), static_cast<int>(sizeof(cx<T>)));
+  return lds_line_start(line, fwd_line_stride<NR, T>(), static_cast<int>(sizeof(cx<T>)));
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -113,41 +147,52 @@ struct MolTabs {
 // includes the 1/NR of the inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
 // x, y < R1, so that every table access is a uniform base plus one lane
 // offset plus an immediate.
-template <typename T, int NR, bool CONJ = false>
+template <typename T, int NR, bool CONJ = false, int SP = 1>
 __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
                                              const cx<T>* __restrict__ tw2) {
-  constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2, RS = R1 + 1;
+  constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2;
+  // SP rounds of RH = R1/SP columns each; the slot holds R2 rows of RH + 1
+  constexpr int RH = R1 / SP, UH = U / SP, RS = RH + 1;
+  static_assert(U % SP == 0, "columns per lane must split evenly");
   // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
   dft<R1, false, T>(v);
 #pragma unroll
   for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw2[a * R1 + q]);
 #pragma unroll
-  for (int a = 0; a < R1; ++a) slot[q * RS + a] = v[a];
-  wave_lds_sync();
-  // pass 2 on the transposed data: frequency k = a + R1 b
+  for (int h = 0; h < SP; ++h) {
+    if (h > 0) wave_lds_sync();
+    // this lane's row of the columns [h RH, (h+1) RH)
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int a = q + R2 * u;
-    cx<T>* w = v + u * R2;
+    for (int al = 0; al < RH; ++al) slot[q * RS + al] = v[h * RH + al];
+    wave_lds_sync();
+    // pass 2 on the transposed data: frequency k = a + R1 b, columns
+    // a = q + R2 u of this round, held in the registers written above
 #pragma unroll
-    for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + a];
-    dft<R2, false, T>(w);
+    for (int uu = 0; uu < UH; ++uu) {
+      const int u = h * UH + uu;
+      const int a = q + R2 * u;
+      const int al = q + R2 * uu;
+      cx<T>* w = v + u * R2;
 #pragma unroll
-    for (int b = 0; b < R2; ++b) w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
-    dft<R2, true, T>(w);
+      for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + al];
+      dft<R2, false, T>(w);
 #pragma unroll
-    for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);
+      for (int b = 0; b < R2; ++b) w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
+      dft<R2, true, T>(w);
+#pragma unroll
+      for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int uu = 0; uu < UH; ++uu) {
+      const int al = q + R2 * uu;
+#pragma unroll
+      for (int qq = 0; qq < R2; ++qq) slot[qq * RS + al] = v[(h * UH + uu) * R2 + qq];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int al = 0; al < RH; ++al) v[h * RH + al] = slot[q * RS + al];
   }
-  wave_lds_sync();
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int a = q + R2 * u;
-#pragma unroll
-    for (int qq = 0; qq < R2; ++qq) slot[qq * RS + a] = v[u * R2 + qq];
-  }
-  wave_lds_sync();
-#pragma unroll
-  for (int a = 0; a < R1; ++a) v[a] = slot[q * RS + a];
   dft<R1, true, T>(v);
   wave_lds_sync();
 }
@@ -255,11 +300,12 @@ __device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short
 
 // frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16
 template <int NR>
-__device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj,
+__device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
                                            const unsigned short* __restrict__ frag,
                                            const float* __restrict__ x,
                                            const float* __restrict__ mudt, float E) {
   using T = float;
+  constexpr int NRH = NR / fwd_split<NR, float>();   // radial points of this round
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
@@ -277,8 +323,9 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj,
 #pragma unroll
   for (int i = 0; i < 4; ++i) xk[i] = (rb + i < nj) ? x[rb + i] : 0.0f;
 #pragma unroll 1
-  for (int tile = wave; tile * 16 < NR; tile += nwaves) {
-    const int r = tile * 16 + col;
+  for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
+    const int rl = tile * 16 + col;   // radial point within the round (LDS)
+    const int r = r0 + rl;            // on the grid (tables)
     // psi rows J = rb..rb+3 of both states at radial point r
     float gr[4], gi[4], er[4], ei[4];
 #pragma unroll
@@ -286,8 +333,8 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj,
       const int J = rb + i;
       cx<float> g = {0.f, 0.f}, e = {0.f, 0.f};
       if (J < nj) {
-        g = sh[lds_row<NR, T>(J) + r];
-        e = sh[lds_row<NR, T>(nj + J) + r];
+        g = sh[lds_row<NR, T>(J) + rl];
+        e = sh[lds_row<NR, T>(nj + J) + rl];
       }
       gr[i] = g.x; gi[i] = g.y; er[i] = e.x; ei[i] = e.y;
     }
@@ -332,8 +379,8 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj,
     for (int i = 0; i < 4; ++i) {
       const int J = rb + i;
       if (J < nj) {
-        sh[lds_row<NR, T>(J) + r] = {cgr[i], cgi[i]};
-        sh[lds_row<NR, T>(nj + J) + r] = {cer[i], cei[i]};
+        sh[lds_row<NR, T>(J) + rl] = {cgr[i], cgi[i]};
+        sh[lds_row<NR, T>(nj + J) + rl] = {cer[i], cei[i]};
       }
     }
   }
@@ -380,11 +427,12 @@ struct MfmaK4<double> {
 // frag: [2][64 lanes][4]: block 0 A_i = T[l%16][row(l/16, i)], block 1 the
 // transpose T[row(l/16, i)][l%16]; zero outside nj.
 template <typename T, int NR>
-__device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj,
+__device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
                                                     const T* __restrict__ frag,
                                                     const T* __restrict__ x,
                                                     const T* __restrict__ mudt, T E) {
   typedef typename MfmaK4<T>::acc acc_t;
+  constexpr int NRH = NR / fwd_split<NR, T>();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
@@ -400,16 +448,17 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj,
     xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
   }
 #pragma unroll 1
-  for (int tile = wave; tile * 16 < NR; tile += nwaves) {
-    const int r = tile * 16 + col;
+  for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
+    const int rl = tile * 16 + col;   // radial point within the round (LDS)
+    const int r = r0 + rl;            // on the grid (tables)
     acc_t cgr, cgi, cer, cei;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int J = rows[i];
       cx<T> g = {T(0), T(0)}, e = {T(0), T(0)};
       if (J < nj) {
-        g = sh[lds_row<NR, T>(J) + r];
-        e = sh[lds_row<NR, T>(nj + J) + r];
+        g = sh[lds_row<NR, T>(J) + rl];
+        e = sh[lds_row<NR, T>(nj + J) + rl];
       }
       cgr[i] = g.x; cgi[i] = g.y; cer[i] = e.x; cei[i] = e.y;
     }
@@ -446,8 +495,8 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj,
     for (int i = 0; i < 4; ++i) {
       const int J = rows[i];
       if (J < nj) {
-        sh[lds_row<NR, T>(J) + r] = {cgr[i], cgi[i]};
-        sh[lds_row<NR, T>(nj + J) + r] = {cer[i], cei[i]};
+        sh[lds_row<NR, T>(J) + rl] = {cgr[i], cgi[i]};
+        sh[lds_row<NR, T>(nj + J) + rl] = {cer[i], cei[i]};
       }
     }
   }
@@ -511,8 +560,13 @@ void mol_step_kernel(MolArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nj = a.nj;
   const int L = 2 * nj;
-  cx<T>* sh = reinterpret_cast<cx<T>*>(smem);
-  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * lds_row<NR, T>(L));
+  // LDS: transform tables | lines | reduction scratch
+  constexpr size_t TB = lds_table_bytes<NR, T>();
+  cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tw_s = kin_s + NR;
+  T* mask_s = reinterpret_cast<T*>(tw_s + R1 * R1);
+  cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TB);
+  double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * lds_row<NR, T>(L));
 
   const int mol = blockIdx.x;
   const int tid = threadIdx.x;
@@ -563,34 +617,63 @@ void mol_step_kernel(MolArgs a) {
 #pragma unroll
     for (int p = 0; p < R1; ++p) v[p] = psi[loff + R2 * p];
   }
+  // the tables read at every element go to LDS (the per-element L1/L2
+  // traffic and latency of these reads dominated the step otherwise)
+  if constexpr (stage_tables<NR, T>()) {
+    lds_stage(kin_s, tb.kin, NR * sizeof(cx<T>));
+    lds_stage(tw_s, tb.tw, R1 * R1 * sizeof(cx<T>));
+    lds_stage(mask_s, tb.mask, NR * sizeof(T));
+    __syncthreads();
+  }
 
+  // SP exchange rounds of NRH radial points; round h holds the registers
+  // p in [h PH, (h+1) PH), i.e. r = q + R2 p in [h NRH, (h+1) NRH)
+  constexpr int SP = fwd_split<NR, T>(), PH = R1 / SP, NRH = NR / SP;
   double ab = 0.0;
   for (int step = 0; step < a.n_steps; ++step) {
-    const cx<T>* kin = opaque(tb.kin);
-    const cx<T>* tw = opaque(tb.tw);
+    const cx<T>* kin;
+    const cx<T>* tw;
+    const T* mask;
+    if constexpr (stage_tables<NR, T>()) {
+      kin = kin_s;
+      tw = tw_s;
+      mask = mask_s;
+    } else {
+      kin = opaque(tb.kin);
+      tw = opaque(tb.tw);
+      mask = opaque(tb.mask);
+    }
     const cx<T>* vph = opaque(tb.vph);
-    const T* mask = opaque(tb.mask);
-    if (active) {
-      kinetic_half<T, NR>(v, slot, q, kin, tw);
+    if (active) kinetic_half<T, NR, false, SP>(v, slot, q, kin, tw);
 #pragma unroll
-      for (int p = 0; p < R1; ++p) {
-        v[p] = phase_mul(v[p], vph[loff + R2 * p]);
-        slot[q + R2 * p] = v[p];
+    for (int h = 0; h < SP; ++h) {
+      if (active) {
+#pragma unroll
+        for (int pp = 0; pp < PH; ++pp) {
+          const int p = h * PH + pp;
+          v[p] = phase_mul(v[p], vph[loff + R2 * p]);
+          slot[q + R2 * pp] = v[p];
+        }
+      }
+      __syncthreads();
+      if constexpr (CP == kCpBf16x3) {
+        coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag),
+                          tb.x, tb.mudt, E);
+      } else {
+        const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
+        coupling_mfma_exact<T, NR>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int pp = 0; pp < PH; ++pp) {
+          const int p = h * PH + pp;
+          v[p] = phase_mul(slot[q + R2 * pp], vph[loff + R2 * p]);
+        }
       }
     }
-    __syncthreads();
-    if constexpr (CP == kCpBf16x3) {
-      coupling_mfma<NR>(sh, nj, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag), tb.x,
-                    tb.mudt, E);
-    } else {
-      const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
-      coupling_mfma_exact<T, NR>(sh, nj, frag, tb.x, tb.mudt, E);
-    }
-    __syncthreads();
     if (active) {
-#pragma unroll
-      for (int p = 0; p < R1; ++p) v[p] = phase_mul(slot[q + R2 * p], vph[loff + R2 * p]);
-      kinetic_half<T, NR>(v, slot, q, opaque(kin), opaque(tw));
+      kinetic_half<T, NR, false, SP>(v, slot, q, kin, tw);
       // absorber: when it lies within the last quarter of the grid only
       // those registers are tested (one uniform branch), otherwise all
       constexpr int P0 = (3 * R1) / 4;
@@ -608,33 +691,39 @@ void mol_step_kernel(MolArgs a) {
   // for, as the finiteness check)
   double nrm = 0.0, yld = 0.0, dd = 0.0;
   const bool want_n = a.want_norm || !a.want_d;
-  if (active) {
-    if (want_n || a.want_yield) {
+  if (active && (want_n || a.want_yield)) {
 #pragma unroll
-      for (int p = 0; p < R1; ++p) {
-        const int r = q + R2 * p;
-        const double n2 = static_cast<double>(norm2(v[p]));
-        nrm += n2;
-        if (r >= a.kdiss) yld += n2;
-      }
+    for (int p = 0; p < R1; ++p) {
+      const int r = q + R2 * p;
+      const double n2 = static_cast<double>(norm2(v[p]));
+      nrm += n2;
+      if (r >= a.kdiss) yld += n2;
     }
-#pragma unroll
-    for (int p = 0; p < R1; ++p) slot[q + R2 * p] = v[p];
   }
   if (a.want_d) {
-    __syncthreads();
-    for (int r = tid; r < NR; r += nthr) {
-      double acc = 0.0;
-      cx<T> g0 = sh[r], e0 = sh[lds_row<NR, T>(nj) + r];
-      for (int J = 0; J + 1 < nj; ++J) {
-        const cx<T> g1 = sh[lds_row<NR, T>(J + 1) + r], e1 = sh[lds_row<NR, T>(nj + J + 1) + r];
-        const double t = static_cast<double>(g0.x) * e1.x + static_cast<double>(g0.y) * e1.y +
-                         static_cast<double>(g1.x) * e0.x + static_cast<double>(g1.y) * e0.y;
-        acc += tb.cj[J] * t;
-        g0 = g1;
-        e0 = e1;
+    // d = 2 dr sum_r mu(r) sum_J c_J Re[conj(g_J) e_{J+1} + conj(g_{J+1}) e_J],
+    // one round of radial points at a time; the J sum in the working
+    // precision, the r sum in FP64
+#pragma unroll
+    for (int h = 0; h < SP; ++h) {
+      if (h > 0) __syncthreads();   // the previous round's readers are done
+      if (active) {
+#pragma unroll
+        for (int pp = 0; pp < PH; ++pp) slot[q + R2 * pp] = v[h * PH + pp];
       }
-      dd += tb.mu[r] * acc;
+      __syncthreads();
+      for (int rl = tid; rl < NRH; rl += nthr) {
+        T acc = T(0);
+        cx<T> g0 = sh[rl], e0 = sh[lds_row<NR, T>(nj) + rl];
+        for (int J = 0; J + 1 < nj; ++J) {
+          const cx<T> g1 = sh[lds_row<NR, T>(J + 1) + rl], e1 = sh[lds_row<NR, T>(nj + J + 1) + rl];
+          const T t = g0.x * e1.x + g0.y * e1.y + g1.x * e0.x + g1.y * e0.y;
+          acc += static_cast<T>(tb.cj[J]) * t;
+          g0 = g1;
+          e0 = e1;
+        }
+        dd += tb.mu[h * NRH + rl] * static_cast<double>(acc);
+      }
     }
   }
   double sums[4] = {ab, nrm, yld, dd};
@@ -662,7 +751,8 @@ int launch_mol_t(const MolArgs& a, hipStream_t s) {
   const int L = 2 * a.nj;
   int threads = ((L * R2 + 63) / 64) * 64;
   if (threads < 64) threads = 64;
-  const size_t shm = sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, line_stride<NR, T>(), sizeof(cx<T>))) +
+  const size_t shm = lds_table_bytes<NR, T>() +
+                     sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
                      16 * 4 * sizeof(double);
   static bool attr_set = false;
   if (!attr_set && shm > 64 * 1024) {
