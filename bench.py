@@ -224,6 +224,64 @@ def run_bloch(cfg, steps, warmup, n0, n_emitters):
     return out
 
 
+def run_scale(steps):
+    """The scale workload (256 x 256 x 160 nanohole film, 700,000 molecules,
+    precision form): one run, and three incident carriers (0.08, 0.09,
+    0.10 Eh) advanced together as a batch on separate streams."""
+    import torch
+
+    from paper_2209_04487_amd import msqd
+    from workloads import get_config
+    from workloads.pulses import source_values
+    cfg = get_config("cfg4")
+    n0 = default_first_step(cfg)
+    out = {"workload": f"nanohole film {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.n_mol} molecules, "
+                       f"N_r={cfg.n_r}, J<={cfg.j_max}, precision form"}
+    one = run_coupled(cfg, "mixed", steps, 2, n0)
+    out["ms_per_step"] = one["ms"] / steps
+    out["molecule_steps_per_s"] = one["n_mol"] * steps / (one["ms"] / 1e3)
+    cfgs = [cfg.replace(omega_h=w) for w in (0.08, 0.09, 0.10)]
+    batch = msqd.CarrierBatch(cfgs, prec="mixed")
+    srcs = [source_values(c, n0, steps + 2) for c in cfgs]
+    for sysm in batch.systems:
+        sysm.n = n0
+    batch.step([s_[:2] for s_ in srcs])
+    torch.cuda.synchronize()
+    t = time.time()
+    batch.step([s_[2:] for s_ in srcs])
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    out["carriers"] = {"n": 3, "ms_per_step_all": dt * 1e3 / steps,
+                       "molecule_steps_per_s": 3 * cfg.n_mol * steps / dt}
+    del batch
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_adjoint(steps):
+    """Gradient of the dissociated population of the differentiation
+    workload (one SRR cell, 20,000 molecules, N_r = 128, J <= 6, FP32) over a
+    window of `steps` steps with one checkpoint per 200 steps: forward run,
+    segment recompute and reverse steps, timed as one call."""
+    import torch
+
+    from paper_2209_04487_amd.grad import yield_and_gradient
+    from workloads import get_config
+    from workloads.pulses import knot_values
+    cfg = get_config("cfg3", n_steps=steps)
+    kn = knot_values(cfg)
+    yield_and_gradient(cfg.replace(n_steps=10, ckpt_every=10), kn, cfg.omega, prec="fp32")   # warm-up
+    torch.cuda.synchronize()
+    t = time.time()
+    Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp32")
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    return {"workload": f"SRR cell {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.n_mol} molecules, N_r={cfg.n_r}, "
+                        f"J<={cfg.j_max}, FP32, checkpoint every {cfg.ckpt_every}",
+            "steps": steps, "s_total": dt, "ms_per_forward_plus_reverse_step": dt * 1e3 / steps,
+            "yield": Y, "grad_norm_knots": float(np.linalg.norm(dk)), "dY_domega": dw}
+
+
 def calibration_copy(nbytes=1 << 30, reps=3):
     """Device-to-device copies of a known size, for scaling the HBM byte
     counters of a counter run (FETCH_SIZE / WRITE_SIZE) to bytes."""
@@ -343,6 +401,8 @@ def main():
                     help="length of the accuracy comparison against the FP64 form (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 timing and comparison")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the 700,000-molecule and adjoint measurements")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64"], default=None,
                     help="only time the molecular-step kernel of this form (for counter runs), "
                          "followed by a 1 GiB calibration copy")
@@ -402,6 +462,14 @@ def main():
     log("Bloch-emitter coupled run: 691,200 emitters")
     bloch = run_bloch(cfg, K, W, n0, 691_200)
 
+    scale = None
+    adjoint = None
+    if not args.no_scale:
+        log("scale workload: 700,000 molecules, one run and a 3-carrier batch")
+        scale = run_scale(10)
+        log("adjoint: differentiation workload, 400 steps")
+        adjoint = run_adjoint(400)
+
     log("kernel timing")
     launches = max(10, min(K, 100))
     mol_ms = time_mol_kernel(cfg, "mixed", launches)
@@ -460,6 +528,8 @@ def main():
         "accuracy_vs_fp64": acc,
         "multirate": multirate,
         "bloch_emitters": bloch,
+        "scale": scale,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

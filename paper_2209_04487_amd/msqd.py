@@ -576,6 +576,32 @@ class CoupledBloch:
         self.n += len(src_values)
 
 
+class CarrierBatch:
+    """Several independent coupled runs (one per incident carrier, the
+    paper's frequency scans) advanced together: each run has its own state
+    and its own stream, and the runs' launches are interleaved step by step
+    so that the GPU overlaps one run's small field kernels with another's
+    molecular step.  Every run computes exactly what it computes alone."""
+
+    def __init__(self, cfgs, prec=None, **kw):
+        self.systems = [Coupled(c, prec=prec, **kw) for c in cfgs]
+        self.streams = [torch.cuda.Stream() for _ in cfgs]   # default priority
+        torch.cuda.synchronize()
+
+    def step(self, src_values_per_run, chunk=1):
+        """src_values_per_run: one array of source samples per run (same
+        length); advances every run by that many steps."""
+        n = len(src_values_per_run[0])
+        for t in range(0, n, chunk):
+            for sysm, st, src in zip(self.systems, self.streams, src_values_per_run):
+                with torch.cuda.stream(st):
+                    sysm.step(src[t:t + chunk])
+
+    def synchronize(self):
+        for st in self.streams:
+            st.synchronize()
+
+
 def n_exports_ok():
     return all(hasattr(lib, n) for n in EXPORTS)
 
@@ -584,6 +610,6 @@ def version():
     return lib.msqd_version()
 
 
-__all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
+__all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "CarrierBatch", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
            "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status",
            "MsqdError", "lib", "LIB_PATH", "EXPORTS"]
