@@ -224,6 +224,17 @@ def run_bloch(cfg, steps, warmup, n0, n_emitters):
     return out
 
 
+def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256):
+    """The paper's own molecular model: all (j, m) with j <= 1 and all three
+    field components, 691,200 molecules in the SRR slab (the paper's count),
+    precision form, one molecular step per field step."""
+    c = cfg.replace(n_mol=n_mol, j_max=1, basis="jm", n_r=n_r)
+    out = run_coupled(c, "fp32", steps, warmup, n0)
+    return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= 1, N_r={n_r}, FP32",
+            "ms_per_step": out["ms"] / steps,
+            "molecule_steps_per_s": out["n_mol"] * steps / (out["ms"] / 1e3)}
+
+
 def run_scale(steps):
     """The scale workload (256 x 256 x 160 nanohole film, 700,000 molecules,
     precision form): one run, and three incident carriers (0.08, 0.09,
@@ -459,6 +470,8 @@ def main():
                  "field_steps_per_s": k_mr / (mr["ms"] / 1e3),
                  "molecule_steps_per_s": mr["n_mol"] * (k_mr // M) / (mr["ms"] / 1e3)}
 
+    log("(j, m)-basis coupled run: 691,200 molecules, j <= 1")
+    jm = run_jm(cfg, 20, 2, n0)
     log("Bloch-emitter coupled run: 691,200 emitters")
     bloch = run_bloch(cfg, K, W, n0, 691_200)
 
@@ -527,6 +540,7 @@ def main():
         "speedup_vs_fp64": None if fp64 is None else fp64["ms"] / mixed["ms"],
         "accuracy_vs_fp64": acc,
         "multirate": multirate,
+        "jm_basis": jm,
         "bloch_emitters": bloch,
         "scale": scale,
         "adjoint": adjoint,

@@ -52,6 +52,9 @@ enum {
 };
 
 enum { MSQD_FP64 = 0, MSQD_FP32 = 1, MSQD_MIXED = 2 };
+/* rotational basis of the wavepackets (qd_desc.basis): m = 0 J lines, or
+ * the full (j, m) basis with all three field components (Eq. (3)) */
+enum { MSQD_BASIS_M0 = 0, MSQD_BASIS_JM = 1 };
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* msqd_last_error(void);
@@ -71,6 +74,12 @@ typedef struct {
   double dt_au;           /* molecular time step, atomic units             */
   double absorb_width_au; /* cos^(1/8) absorber over [r_max - w, r_max); 0 = none */
   double r_diss_au;       /* dissociated population counts r > r_diss      */
+  int32_t basis;          /* MSQD_BASIS_M0: J lines with m = 0, the field
+                             along the quantisation axis (E_mol, d_mol: one
+                             value per molecule); MSQD_BASIS_JM: all
+                             (j, m) with j <= j_max <= 1, all three field
+                             components (E_mol, d_mol: [n_mol][3] = x, y, z),
+                             psi lines ordered b = j^2 + m + j             */
 } qd_desc;
 
 /* Bytes of device workspace (tables and a status word) for qd_* calls. */
@@ -92,7 +101,11 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
  * E_mol: device [n_mol] float64 field along the quantisation axis (au).
  * absorbed: device [n_mol] float64, accumulated.  d_mol: device [n_mol]
  * float64 dipole <mu12 cos(theta) sigma_x> (e a0) after the last step, or
- * NULL. */
+ * NULL.
+ * With basis = MSQD_BASIS_JM: E_mol is [n_mol][3] (E_x, E_y, E_z) and d_mol
+ * [n_mol][3], the dipole <mu12 d_c sigma_x> along x, y, z; the coupling is
+ * exp(i mu12 dt sigma_x (x) sum_c E_c D_c) on the j <= 1 basis, D_c the
+ * direction cosines of the molecular axis (Eq. (3) with all m). */
 int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
             double* absorbed, double* d_mol, int32_t n_steps, void* stream);
 

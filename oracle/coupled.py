@@ -35,6 +35,7 @@ from workloads.molecule_inputs import morse_v0, potentials
 from .fdtd import FluxMonitor, yee_from_config
 from .maps import cells_from_config, csr
 from .molecule import model_from_config
+from .molecule_jm import jm_model_from_config
 
 E_AU = 5.14220674763e11      # V/m
 EA0 = 8.4783536255e-30       # C m
@@ -49,7 +50,11 @@ class CoupledOracle:
         self.mat = mat
         self.yee = yee if yee is not None else yee_from_config(cfg, mat, eps_table(cfg))
         ug, ue, mu = potentials(cfg)
-        self.mol = model_from_config(cfg, ug, ue, mu, dt_au=cfg.dt_au * self.mol_every)
+        # rotational basis: m = 0 J lines with the field along the axis, or
+        # all (j, m) with the three field components at each cell's own edges
+        self.jm = getattr(cfg, "basis", "m0") == "jm"
+        make = jm_model_from_config if self.jm else model_from_config
+        self.mol = make(cfg, ug, ue, mu, dt_au=cfg.dt_au * self.mol_every)
         if cells is None:
             cells = cells_from_config(cfg)
         if n_mol is not None:
@@ -59,13 +64,14 @@ class CoupledOracle:
         self.occ, self.ptr, self.perm = csr(self.cells)
         self.psi = self.mol.initial_state(self.n_mol, morse_v0(cfg))
         self.absorbed = np.zeros(self.n_mol)
-        self.P = np.zeros(len(self.occ))
-        self.Jmol = np.zeros(len(self.occ))
+        nc = 3 if self.jm else 1
+        self.P = np.zeros((nc, len(self.occ))) if self.jm else np.zeros(len(self.occ))
+        self.Jmol = np.zeros_like(self.P)
         self.monitor = FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k, cfg.freqs, cfg.dt, cfg.mon_every)
         self.monitor2 = (FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k2, cfg.freqs, cfg.dt, cfg.mon_every)
                          if cfg.mon_k2 else None)
-        self.d = np.zeros(self.n_mol)
-        self.e_mol = np.zeros(self.n_mol)
+        self.d = np.zeros((self.n_mol, 3)) if self.jm else np.zeros(self.n_mol)
+        self.e_mol = np.zeros((self.n_mol, 3)) if self.jm else np.zeros(self.n_mol)
 
     def cell_sums(self, d):
         """Per occupied cell, the sum of its molecules' dipoles in CSR order."""
@@ -84,10 +90,17 @@ class CoupledOracle:
         yee = self.yee
         yee.update_H()
         if n % self.mol_every == 0:
-            e_mol = yee.E[0].reshape(-1)[self.cells] / E_AU
+            if self.jm:
+                e_mol = np.stack([yee.E[c].reshape(-1)[self.cells] for c in range(3)], axis=1) / E_AU
+            else:
+                e_mol = yee.E[0].reshape(-1)[self.cells] / E_AU
             self.psi, self.absorbed = self.mol.step(self.psi, e_mol, self.absorbed)
             self.d = self.mol.dipole(self.psi)
-            P_new = cfg.mol_weight * self.cell_sums(self.d) * EA0 / cfg.dx ** 3
+            if self.jm:
+                sums = np.stack([self.cell_sums(self.d[:, c]) for c in range(3)])
+            else:
+                sums = self.cell_sums(self.d)
+            P_new = cfg.mol_weight * sums * EA0 / cfg.dx ** 3
             self.Jmol = (P_new - self.P) / (cfg.dt * self.mol_every)
             self.P = P_new
             self.e_mol = e_mol
@@ -100,11 +113,12 @@ class CoupledOracle:
     def run(self, src_values, n0=0, record_fields=False):
         """Run len(src_values) steps from step n0; returns per-step traces."""
         nst = len(src_values)
-        trace = {"D": np.zeros(nst), "d": np.zeros((nst, self.n_mol)),
-                 "E_mol": np.zeros((nst, self.n_mol))}
+        shape = self.d.shape
+        trace = {"D": np.zeros((nst,) + shape[1:]), "d": np.zeros((nst,) + shape),
+                 "E_mol": np.zeros((nst,) + shape)}
         for s in range(nst):
             e_mol = self.step(n0 + s, src_values[s])
-            trace["D"][s] = self.d.sum()
+            trace["D"][s] = self.d.sum(axis=0)
             trace["d"][s] = self.d
             trace["E_mol"][s] = e_mol
         return trace

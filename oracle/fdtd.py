@@ -136,8 +136,8 @@ class Yee:
     def update_E(self, src_value=0.0, src_k=None, jmol_cells=None, jmol=None):
         """Advance E by one step.  src_value: E_inc(t_{n+1/2}) in V/m of the
         soft current sheet J_x = -2 E_inc/(eta0 dz) on plane src_k; jmol:
-        polarisation current density (A/m^2) added to J_x at the flat E_x
-        indices jmol_cells."""
+        polarisation current density (A/m^2) added at the flat indices
+        jmol_cells, to J_x ([n]) or to each of J_x, J_y, J_z ([3, n])."""
         Hx, Hy, Hz = self.H
         dx = self.dx
         b = self.bE[:, None, None]
@@ -163,12 +163,15 @@ class Yee:
             jd = np.where(self.metal[c], self.alpha_d * self.JD[c] + self.beta_d * self.E[c], 0.0)
             self.JD[c] = jd
             J += jd
-            if c == 0:
-                if src_k is not None and src_value != 0.0:
-                    J[src_k] += -2.0 * src_value / (ETA0 * dx)
-                if jmol is not None:
+            if c == 0 and src_k is not None and src_value != 0.0:
+                J[src_k] += -2.0 * src_value / (ETA0 * dx)
+            if jmol is not None:
+                jm = np.asarray(jmol)
+                # [n] : current on E_x only; [3, n] : on E_x, E_y, E_z at each
+                # cell's own edges (the same flat index in each component array)
+                if jm.ndim == 2 or c == 0:
                     Jf = J.reshape(-1)
-                    np.add.at(Jf, np.asarray(jmol_cells), np.asarray(jmol))
+                    np.add.at(Jf, np.asarray(jmol_cells), jm[c] if jm.ndim == 2 else jm)
             newE = self.E[c] + self.ce[c] * (curls[c] - J)
             if c < 2 and not self.periodic_z:
                 newE[0] = 0.0          # tangential E = 0 at the bottom end

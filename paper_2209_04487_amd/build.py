@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmsqd.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "host_tables.cpp", "fdtd.hip", "mol_fp64.hip", "mol_fp32.hip",
-           "mol_mixed.hip", "adjoint.hip", "bloch.hip", "readout.hip"]
+           "mol_mixed.hip", "adjoint.hip", "bloch.hip", "readout.hip", "mol_jm.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

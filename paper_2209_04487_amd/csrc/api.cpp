@@ -121,6 +121,12 @@ size_t mol_lds_limit() {
 // ------------------------------------------------------------ validation
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// wavepacket lines per molecule: 2 states x (J lines, or (j_max+1)^2 (j, m) lines)
+static int qd_lines(const qd_desc* d) {
+  const int nj = d->j_max + 1;
+  return 2 * (d->basis == MSQD_BASIS_JM ? nj * nj : nj);
+}
+
 static int check_qd(const qd_desc* d) {
   if (!d) return fail(MSQD_EINVAL, "qd_desc is NULL");
   if (d->n_mol < 0) return fail(MSQD_EINVAL, "n_mol < 0");
@@ -130,6 +136,9 @@ static int check_qd(const qd_desc* d) {
   if (d->prec != MSQD_FP64 && d->prec != MSQD_FP32 && d->prec != MSQD_MIXED)
     return fail(MSQD_EPREC, "unknown precision");
   if (!(d->r_max > d->r_min) || !(d->r_min > 0.0)) return fail(MSQD_EINVAL, "need 0 < r_min < r_max");
+  if (d->basis != MSQD_BASIS_M0 && d->basis != MSQD_BASIS_JM) return fail(MSQD_EINVAL, "unknown basis");
+  if (d->basis == MSQD_BASIS_JM && d->j_max != 1)
+    return fail(MSQD_EUNSUP, "the (j, m) basis is provided for j_max = 1");
   if (!(d->mass_au > 0.0) || !(d->dt_au > 0.0)) return fail(MSQD_EINVAL, "mass and dt must be > 0");
   if (d->absorb_width_au < 0.0 || d->absorb_width_au > d->r_max - d->r_min)
     return fail(MSQD_EINVAL, "absorber width outside the box");
@@ -244,6 +253,11 @@ static MolArgs make_mol_args(const qd_desc* d, const void* ws) {
 static int launch_mol(const qd_desc* d, const MolArgs& a, hipStream_t s) {
   int e = 0;
   if (a.n_mol == 0) return MSQD_OK;
+  if (d->basis == MSQD_BASIS_JM) {
+    e = launch_mol_jm(a, d->n_r, d->prec != MSQD_FP64, s);
+    if (e != 0) return check_hip(static_cast<hipError_t>(e), "(j, m) molecule step launch");
+    return MSQD_OK;
+  }
   const size_t need = mol_lds_bytes(d->n_r, d->j_max + 1, d->prec);
   if (need > mol_lds_limit())
     return fail(MSQD_EUNSUP, "n_r x (j_max+1) too large for one workgroup's LDS in this precision (" +
@@ -361,7 +375,7 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
 
   MSQD_HIP(hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s));
   if (d->n_mol > 0) {
-    const int lines = 2 * nj;
+    const int lines = qd_lines(d);
     const size_t total = static_cast<size_t>(lines) * nr * d->n_mol;
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -422,7 +436,7 @@ int excited_r_readout(const qd_desc* d, const void* ws, const void* psi, double*
   if (!ws || !psi || !r_num || !pop) return fail(MSQD_EINVAL, "NULL pointer");
   RdArgs a{};
   a.n_mol = d->n_mol;
-  a.nj = d->j_max + 1;
+  a.nj = qd_lines(d) / 2;   // lines per electronic state
   a.n_r = d->n_r;
   a.r_min = d->r_min;
   a.dr = (d->r_max - d->r_min) / d->n_r;
@@ -681,6 +695,17 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
   da.P_c = st->P_c;
   da.J_mol = st->J_mol;
   da.Ex = st->f.Ex;
+  da.ncomp = 1;
+  if (d->qd.basis == MSQD_BASIS_JM) {
+    // all three components: gathered at, and deposited on, each cell's own
+    // E_x, E_y, E_z edges; P_c and J_mol are [n_occ][3]
+    ma.Ey = st->f.Ey;
+    ma.Ez = st->f.Ez;
+    da.ncomp = 3;
+    da.Ey = st->f.Ey;
+    da.Ez = st->f.Ez;
+  }
+  da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
@@ -798,6 +823,8 @@ int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* st, const
   da.P_c = st->P_c;
   da.J_mol = st->J_mol;
   da.Ex = st->f.Ex;
+  da.ncomp = 1;
+  da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
@@ -832,6 +859,7 @@ static int check_adj(const cpl_desc* d, const cpl_state* st, const cpl_adj* adj)
   if (d->qd.prec == MSQD_MIXED || d->fd.prec == MSQD_MIXED)
     return fail(MSQD_EUNSUP, "the adjoint is provided for the FP64 and FP32 forms");
   if (d->mol_every > 1) return fail(MSQD_EUNSUP, "the adjoint is provided for mol_every <= 1");
+  if (d->qd.basis != MSQD_BASIS_M0) return fail(MSQD_EUNSUP, "the adjoint is provided for the m = 0 basis");
   if (d->qd.prec != d->fd.prec) return fail(MSQD_EPREC, "molecule and field precision differ");
   const fdtd_fields& f = adj->lf;
   const void* ptrs[] = {f.Ex, f.Ey, f.Ez, f.Hx, f.Hy, f.Hz, f.JDx, f.JDy, f.JDz, f.psi, adj->scratch};

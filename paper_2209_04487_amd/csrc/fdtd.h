@@ -49,9 +49,12 @@ struct DepArgs {
   const int* occ_ptr;
   const int* mol_perm;
   const uint8_t* mat;                  // E_x material ids
-  double* P_c;
-  double* J_mol;
+  double* P_c;                         // [n_occ][ncomp]
+  double* J_mol;                       // [n_occ][ncomp]
   void* Ex;
+  int ncomp;                           // 1: E_x only; 3: E_x, E_y, E_z (d_mol [n][3])
+  void *Ey, *Ez;
+  long ncells;                         // cells per component array (material planes)
 };
 int launch_deposit(const DepArgs& a, bool f32, hipStream_t s);
 

@@ -266,22 +266,26 @@ template <typename T>
 __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n_occ) return;
-  double J;
-  if (a.update) {
-    double s = 0.0;
-    const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
-    for (int t = b; t < e; ++t) s += a.d_mol[a.mol_perm[t]];
-    const double p_new = s * a.pfac;
-    J = (p_new - a.P_c[c]) * a.inv_dt;
-    a.P_c[c] = p_new;
-    a.J_mol[c] = J;
-  } else {
-    J = a.J_mol[c];
-  }
+  const int nc = a.ncomp;
   const int cell = a.occ_cell[c];
-  const int m = a.mat[cell] & 3;
-  T* Ex = static_cast<T*>(a.Ex);
-  Ex[cell] = Ex[cell] - static_cast<T>(a.ce[m] * J);
+  void* fld[3] = {a.Ex, a.Ey, a.Ez};
+  for (int k = 0; k < nc; ++k) {
+    double J;
+    if (a.update) {
+      double s = 0.0;
+      const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
+      for (int t = b; t < e; ++t) s += a.d_mol[static_cast<size_t>(a.mol_perm[t]) * nc + k];
+      const double p_new = s * a.pfac;
+      J = (p_new - a.P_c[static_cast<size_t>(c) * nc + k]) * a.inv_dt;
+      a.P_c[static_cast<size_t>(c) * nc + k] = p_new;
+      a.J_mol[static_cast<size_t>(c) * nc + k] = J;
+    } else {
+      J = a.J_mol[static_cast<size_t>(c) * nc + k];
+    }
+    const int m = a.mat[static_cast<size_t>(k) * a.ncells + cell] & 3;
+    T* E = static_cast<T*>(fld[k]);
+    E[cell] = E[cell] - static_cast<T>(a.ce[m] * J);
+  }
 }
 
 int launch_deposit(const DepArgs& a, bool f32, hipStream_t s) {

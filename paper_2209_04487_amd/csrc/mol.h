@@ -43,6 +43,8 @@ struct MolArgs {
   void* psi;            // cx<T> [n_mol][2][nj][n_r]
   const double* E_mol;  // [n_mol] field (au), used when Ex == nullptr
   const void* Ex;       // field array (double or float) or nullptr
+  const void* Ey;       // (j, m) basis: the other two components, same cells
+  const void* Ez;
   int ex_is_float;      // element type of Ex
   const int* cell_of_mol;
   double inv_eau;       // 1 / (V/m per au)
@@ -63,6 +65,8 @@ size_t mol_lds_limit();
 
 // launchers (return a hipError_t value cast to int)
 int launch_mol_fp64(const MolArgs& a, int n_r, hipStream_t s);
+// the (j, m)-basis step (j <= 1, three field components)
+int launch_mol_jm(const MolArgs& a, int n_r, bool f32, hipStream_t s);
 int launch_mol_fp32(const MolArgs& a, int n_r, hipStream_t s);
 int launch_mol_mixed(const MolArgs& a, int n_r, hipStream_t s);
 

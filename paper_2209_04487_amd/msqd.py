@@ -25,6 +25,8 @@ MSQD_OK, MSQD_EINVAL, MSQD_ESHAPE, MSQD_EPREC, MSQD_EUNSUP, MSQD_EDEVICE, MSQD_E
     0, -1, -2, -3, -4, -5, -6)
 FP64, FP32, MIXED = 0, 1, 2
 PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+BASIS_M0, BASIS_JM = 0, 1
+BASIS = {"m0": BASIS_M0, "jm": BASIS_JM}
 
 # CODATA 2018 (for converting readouts; the library has its own copy)
 E_AU = 5.14220674763e11
@@ -53,7 +55,8 @@ class qd_desc(C.Structure):
     _fields_ = [("n_mol", C.c_int32), ("n_r", C.c_int32), ("j_max", C.c_int32),
                 ("prec", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
                 ("mass_au", C.c_double), ("dt_au", C.c_double),
-                ("absorb_width_au", C.c_double), ("r_diss_au", C.c_double)]
+                ("absorb_width_au", C.c_double), ("r_diss_au", C.c_double),
+                ("basis", C.c_int32)]
 
 
 class fdtd_desc(C.Structure):
@@ -275,17 +278,21 @@ class Molecules:
     """Wavepacket batch: descriptor, workspace, psi, absorbed, readout buffers."""
 
     def __init__(self, n_mol, n_r, j_max, r_min, r_max, mass, dt_au, U_g, U_e, mu12, psi0,
-                 prec="fp64", absorb_width=2.0, r_diss=8.0):
+                 prec="fp64", absorb_width=2.0, r_diss=8.0, basis="m0"):
         self.prec = PREC[prec] if isinstance(prec, str) else prec
+        self.basis = BASIS[basis] if isinstance(basis, str) else basis
         self.desc = qd_desc(int(n_mol), int(n_r), int(j_max), self.prec, float(r_min), float(r_max),
-                            float(mass), float(dt_au), float(absorb_width), float(r_diss))
+                            float(mass), float(dt_au), float(absorb_width), float(r_diss), self.basis)
         dev = _dev()
         nbytes = qd_workspace_bytes(self.desc)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         cdt = torch.complex128 if self.prec == FP64 else torch.complex64
-        self.psi = torch.empty((int(n_mol), 2, int(j_max) + 1, int(n_r)), dtype=cdt, device=dev)
+        nj = int(j_max) + 1
+        self.n_ang = nj * nj if self.basis == BASIS_JM else nj     # lines per electronic state
+        self.psi = torch.empty((int(n_mol), 2, self.n_ang, int(n_r)), dtype=cdt, device=dev)
         self.absorbed = torch.zeros(int(n_mol), dtype=torch.float64, device=dev)
-        self.d = torch.zeros(int(n_mol), dtype=torch.float64, device=dev)
+        dshape = (int(n_mol), 3) if self.basis == BASIS_JM else (int(n_mol),)
+        self.d = torch.zeros(dshape, dtype=torch.float64, device=dev)
         qd_init(self.desc, U_g, U_e, mu12, psi0, self.ws, self.psi, self.absorbed)
 
     @classmethod
@@ -294,7 +301,7 @@ class Molecules:
         ug, ue, mu = potentials(cfg)
         return cls(cfg.n_mol if n_mol is None else n_mol, cfg.n_r, cfg.j_max, cfg.r_min, cfg.r_max,
                    cfg.mass, cfg.dt_au if dt_au is None else dt_au, ug, ue, mu, morse_v0(cfg),
-                   prec or cfg.precision, cfg.absorb_width, cfg.r_diss)
+                   prec or cfg.precision, cfg.absorb_width, cfg.r_diss, cfg.basis)
 
     def step(self, E_mol, n_steps=1, want_d=True):
         qd_step(self.desc, self.ws, self.psi, E_mol, self.absorbed, self.d if want_d else None,
@@ -303,7 +310,7 @@ class Molecules:
     def readout(self):
         n = self.desc.n_mol
         dev = self.psi.device
-        d = torch.empty(n, dtype=torch.float64, device=dev)
+        d = torch.empty(tuple(self.d.shape), dtype=torch.float64, device=dev)
         nrm = torch.empty(n, dtype=torch.float64, device=dev)
         yld = torch.empty(n, dtype=torch.float64, device=dev)
         dipole_readout(self.desc, self.ws, self.psi, self.absorbed, d, nrm, yld)
@@ -433,9 +440,11 @@ class Coupled:
         self.occ_ptr = it(ptr)
         self.mol_perm = it(perm)
         nm = len(cells)
-        self.E_mol = torch.zeros(max(nm, 1), dtype=torch.float64, device=dev)
-        self.P_c = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
-        self.J_mol = torch.zeros(max(len(occ), 1), dtype=torch.float64, device=dev)
+        nc = 3 if self.mol.basis == BASIS_JM else 1       # field components coupled
+        shp = (lambda n: (max(n, 1), 3)) if nc == 3 else (lambda n: (max(n, 1),))  # noqa: E731
+        self.E_mol = torch.zeros(shp(nm), dtype=torch.float64, device=dev)
+        self.P_c = torch.zeros(shp(len(occ)), dtype=torch.float64, device=dev)
+        self.J_mol = torch.zeros(shp(len(occ)), dtype=torch.float64, device=dev)
         self.desc = cpl_desc(self.mol.desc, self.fields.desc, len(occ), float(cfg.mol_weight),
                              self.mol_every)
         self.state = cpl_state(C.c_void_p(self.mol.psi.data_ptr()),

@@ -40,9 +40,9 @@ def test_library_exports_every_declared_symbol(msqd):
 
 
 def test_workspace_queries_and_validation(msqd):
-    d = msqd.qd_desc(10, 256, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0)
+    d = msqd.qd_desc(10, 256, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 0)
     assert msqd.lib.qd_workspace_bytes(C.byref(d)) > 0
-    bad = msqd.qd_desc(10, 100, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0)
+    bad = msqd.qd_desc(10, 100, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 0)
     assert msqd.lib.qd_workspace_bytes(C.byref(bad)) == 0
     assert "n_r" in msqd.last_error()
     bad = msqd.qd_desc(10, 256, 16, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0)
@@ -135,3 +135,15 @@ def test_bloch_validation(msqd):
     d = msqd.bloch_desc(10, msqd.FP64, 0.3, 1.0, 0.0, 0.0, 0.1)
     assert msqd.lib.bloch_step(C.byref(d), None, None, None, 1, None) == msqd.MSQD_EINVAL
     assert "NULL" in msqd.last_error()
+
+
+def test_jm_basis_validation(msqd):
+    """The (j, m) basis is provided for j_max = 1; an unknown basis value is
+    rejected before anything touches a device."""
+    d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_JM)
+    assert msqd.lib.qd_workspace_bytes(C.byref(d)) > 0
+    d = msqd.qd_desc(4, 128, 2, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_JM)
+    assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0
+    assert "j_max = 1" in msqd.last_error()
+    d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 7)
+    assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0
