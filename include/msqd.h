@@ -133,7 +133,7 @@ int msqd_check_status(const void* ws, void* stream);
  * Fields: Yee leap-frog of Eq. (1) with the Drude current of Eq. (2).
  * ---------------------------------------------------------------------- */
 typedef struct {
-  int32_t nx, ny, nz;     /* cells; x and y periodic                        */
+  int32_t nx, ny, nz;     /* cells; x and y periodic; nz <= 65535, nx*ny*nz <= 2e9 (else MSQD_EUNSUP) */
   int32_t npml;           /* CPML thickness (cells) at each z end, >= 1     */
   int32_t prec;           /* MSQD_FP64 | MSQD_FP32 | MSQD_MIXED (FP32 fields) */
   int32_t metal_id;       /* material id that carries the Drude current     */

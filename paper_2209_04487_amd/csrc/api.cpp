@@ -152,6 +152,7 @@ static int check_fd(const fdtd_desc* d) {
   if (!d) return fail(MSQD_EINVAL, "fdtd_desc is NULL");
   if (d->nx < 1 || d->ny < 1 || d->nz < 4) return fail(MSQD_EINVAL, "grid too small");
   if (static_cast<double>(d->nx) * d->ny * d->nz > 2.0e9) return fail(MSQD_EUNSUP, "grid too large");
+  if (d->nz > 65535) return fail(MSQD_EUNSUP, "nz above 65535 (one launch row of planes)");
   if (d->npml < 1 || 2 * d->npml >= d->nz) return fail(MSQD_EINVAL, "npml must satisfy 1 <= npml < nz/2");
   if (d->prec != MSQD_FP64 && d->prec != MSQD_FP32 && d->prec != MSQD_MIXED)
     return fail(MSQD_EPREC, "unknown precision");

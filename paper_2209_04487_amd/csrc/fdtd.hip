@@ -37,141 +37,184 @@ __device__ __forceinline__ const T* prof(const FdArgs& a, size_t off_d, size_t o
     return reinterpret_cast<const T*>(a.ws + off_f);
 }
 
+// Launch geometry of both updates: blockIdx.y is the z plane, blockIdx.x a
+// run of 256 cells of that plane in x-fastest order (so the dispatch order is
+// the memory order), and the in-plane (i, j) come from 32-bit arithmetic.
+struct CellIdx {
+  long idx;   // linear cell index
+  int i, j, k;
+};
+__device__ __forceinline__ bool cell_of_thread(const FdArgs& a, CellIdx& c) {
+  const int plane = a.nx * a.ny;
+  const int p = static_cast<int>(blockIdx.x) * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+  if (p >= plane) return false;
+  c.k = static_cast<int>(blockIdx.y);
+  c.j = p / a.nx;
+  c.i = p - c.j * a.nx;
+  c.idx = static_cast<long>(c.k) * plane + p;
+  return true;
+}
+
+// Material coefficient dt/(eps0 eps_r[m]) by selects instead of an indexed
+// load (a lane-dependent index into the argument block is a memory access
+// that every E component would wait on).
+template <typename T>
+__device__ __forceinline__ T ce_select(const FdArgs& a, int m) {
+  const T c0 = static_cast<T>(a.ce[0]), c1 = static_cast<T>(a.ce[1]);
+  const T c2 = static_cast<T>(a.ce[2]), c3 = static_cast<T>(a.ce[3]);
+  const T lo = (m & 1) ? c1 : c0, hi = (m & 1) ? c3 : c2;
+  return (m & 2) ? hi : lo;
+}
+
 // H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n, with the CPML stretching of the
 // z derivatives: d/dz -> (1/kappa) d/dz + psi, psi <- b psi + a d/dz.
+// Every load is issued before the first store (the arrays are distinct), so
+// the loads of a cell overlap instead of waiting behind the stores.
 template <typename T>
 __global__ __launch_bounds__(256) void yee_h_kernel(FdArgs a) {
+  CellIdx cl;
+  if (!cell_of_thread(a, cl)) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const long n = static_cast<long>(nx) * ny * nz;
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int i = static_cast<int>(idx % nx);
-  const long jk = idx / nx;
-  const int j = static_cast<int>(jk % ny);
-  const int k = static_cast<int>(jk / ny);
-  const long sx = 1, sy = nx, sz = static_cast<long>(nx) * ny;
-  const long ip = (i + 1 == nx) ? idx - (nx - 1) * sx : idx + sx;
-  const long jp = (j + 1 == ny) ? idx - static_cast<long>(ny - 1) * sy : idx + sy;
+  const int i = cl.i, j = cl.j, k = cl.k;
+  const long idx = cl.idx;
+  const long sy = nx, sz = static_cast<long>(nx) * ny;
+  const long ip = (i + 1 == nx) ? idx - (nx - 1) : idx + 1;
+  const long jp = (j + 1 == ny) ? idx - (ny - 1) * sy : idx + sy;
   FdPtr<T> f = fd_ptrs<T>(a);
+  const T* __restrict__ Ex = f.Ex;
+  const T* __restrict__ Ey = f.Ey;
+  const T* __restrict__ Ez = f.Ez;
+  const bool below_top = k + 1 < nz;
+  const T ex = Ex[idx], ey = Ey[idx], ez = Ez[idx];
+  const T ex_kp = below_top ? Ex[idx + sz] : T(0);
+  const T ey_kp = below_top ? Ey[idx + sz] : T(0);
+  const T ez_jp = Ez[jp], ez_ip = Ez[ip], ey_ip = Ey[ip], ex_jp = Ex[jp];
+  const T hx = f.Hx[idx], hy = f.Hy[idx], hz = f.Hz[idx];
   const T inv_dx = static_cast<T>(a.inv_dx);
   const T cH = static_cast<T>(a.cH);
 
-  const T ex = f.Ex[idx], ey = f.Ey[idx], ez = f.Ez[idx];
-  const T ex_kp = (k + 1 < nz) ? f.Ex[idx + sz] : T(0);
-  const T ey_kp = (k + 1 < nz) ? f.Ey[idx + sz] : T(0);
-  const T dEz_dy = (f.Ez[jp] - ez) * inv_dx;
-  const T dEz_dx = (f.Ez[ip] - ez) * inv_dx;
+  const T dEz_dy = (ez_jp - ez) * inv_dx;
+  const T dEz_dx = (ez_ip - ez) * inv_dx;
   T dEy_dz = (ey_kp - ey) * inv_dx;
   T dEx_dz = (ex_kp - ex) * inv_dx;
-  const T dEy_dx = (f.Ey[ip] - ey) * inv_dx;
-  const T dEx_dy = (f.Ex[jp] - ex) * inv_dx;
+  const T dEy_dx = (ey_ip - ey) * inv_dx;
+  const T dEx_dy = (ex_jp - ex) * inv_dx;
 
   const int kk = pml_plane(k, nz, a.npml);
   if (kk >= 0) {
     const T b = prof<T>(a, a.lay.bH, a.lay.bHf)[k];
     const T c = prof<T>(a, a.lay.aH, a.lay.aHf)[k];
     const T ki = prof<T>(a, a.lay.kH, a.lay.kHf)[k];
-    const long plane = static_cast<long>(nx) * ny;
-    const long np = 2L * a.npml * plane;
-    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    const long np = 2L * a.npml * sz;
+    const long o = kk * sz + (idx - static_cast<long>(k) * sz);
     T* psiHx = f.psi + 2 * np;
     T* psiHy = f.psi + 3 * np;
-    const T phx = b * psiHx[o] + c * dEy_dz;
-    const T phy = b * psiHy[o] + c * dEx_dz;
+    const T p0 = psiHx[o], p1 = psiHy[o];
+    const T phx = b * p0 + c * dEy_dz;
+    const T phy = b * p1 + c * dEx_dz;
     psiHx[o] = phx;
     psiHy[o] = phy;
     dEy_dz = dEy_dz * ki + phx;
     dEx_dz = dEx_dz * ki + phy;
   }
-  f.Hx[idx] -= cH * (dEz_dy - dEy_dz);
-  f.Hy[idx] -= cH * (dEx_dz - dEz_dx);
-  f.Hz[idx] -= cH * (dEy_dx - dEx_dy);
+  f.Hx[idx] = hx - cH * (dEz_dy - dEy_dz);
+  f.Hy[idx] = hy - cH * (dEx_dz - dEz_dx);
+  f.Hz[idx] = hz - cH * (dEy_dx - dEx_dy);
 }
 
 // Drude current (centred form of Eq. (2)) and
 // E^{n+1} = E^n + dt/(eps0 eps_r) [curl H^{n+1/2} - J_D^{n+1/2} - J_src].
 // E_x, E_y at k = 0 stay zero (the grid ends on tangential E = 0).
+// Loads first, as in the H update.
 template <typename T>
 __global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
+  CellIdx cl;
+  if (!cell_of_thread(a, cl)) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int i = cl.i, j = cl.j, k = cl.k;
+  const long idx = cl.idx;
   const long n = static_cast<long>(nx) * ny * nz;
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  const int i = static_cast<int>(idx % nx);
-  const long jk = idx / nx;
-  const int j = static_cast<int>(jk % ny);
-  const int k = static_cast<int>(jk / ny);
-  const long sx = 1, sy = nx, sz = static_cast<long>(nx) * ny;
-  const long im = (i == 0) ? idx + (nx - 1) * sx : idx - sx;
-  const long jm = (j == 0) ? idx + static_cast<long>(ny - 1) * sy : idx - sy;
+  const long sy = nx, sz = static_cast<long>(nx) * ny;
+  const long im = (i == 0) ? idx + (nx - 1) : idx - 1;
+  const long jm = (j == 0) ? idx + (ny - 1) * sy : idx - sy;
   FdPtr<T> f = fd_ptrs<T>(a);
+  const T* __restrict__ Hx = f.Hx;
+  const T* __restrict__ Hy = f.Hy;
+  const T* __restrict__ Hz = f.Hz;
+  const T hx = Hx[idx], hy = Hy[idx], hz = Hz[idx];
+  const T hx_km = (k > 0) ? Hx[idx - sz] : T(0);
+  const T hy_km = (k > 0) ? Hy[idx - sz] : T(0);
+  const T hz_jm = Hz[jm], hz_im = Hz[im], hy_im = Hy[im], hx_jm = Hx[jm];
+  const uint8_t* mat = a.mat;
+  const int mc[3] = {mat[idx], mat[n + idx], mat[2 * n + idx]};
+  T* E[3] = {f.Ex, f.Ey, f.Ez};
+  T* JD[3] = {f.JDx, f.JDy, f.JDz};
+  T e0[3], jd0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) e0[c] = E[c][idx];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) jd0[c] = (mc[c] == a.metal_id) ? JD[c][idx] : T(0);
   const T inv_dx = static_cast<T>(a.inv_dx);
 
-  const T hx = f.Hx[idx], hy = f.Hy[idx], hz = f.Hz[idx];
-  const T hx_km = (k > 0) ? f.Hx[idx - sz] : T(0);
-  const T hy_km = (k > 0) ? f.Hy[idx - sz] : T(0);
-  const T dHz_dy = (hz - f.Hz[jm]) * inv_dx;
-  const T dHz_dx = (hz - f.Hz[im]) * inv_dx;
+  const T dHz_dy = (hz - hz_jm) * inv_dx;
+  const T dHz_dx = (hz - hz_im) * inv_dx;
   T dHy_dz = (hy - hy_km) * inv_dx;
   T dHx_dz = (hx - hx_km) * inv_dx;
-  const T dHy_dx = (hy - f.Hy[im]) * inv_dx;
-  const T dHx_dy = (hx - f.Hx[jm]) * inv_dx;
+  const T dHy_dx = (hy - hy_im) * inv_dx;
+  const T dHx_dy = (hx - hx_jm) * inv_dx;
 
   const int kk = pml_plane(k, nz, a.npml);
   if (kk >= 0) {
     const T b = prof<T>(a, a.lay.bE, a.lay.bEf)[k];
     const T c = prof<T>(a, a.lay.aE, a.lay.aEf)[k];
     const T ki = prof<T>(a, a.lay.kE, a.lay.kEf)[k];
-    const long plane = static_cast<long>(nx) * ny;
-    const long np = 2L * a.npml * plane;
-    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+    const long np = 2L * a.npml * sz;
+    const long o = kk * sz + (idx - static_cast<long>(k) * sz);
     T* psiEx = f.psi;
     T* psiEy = f.psi + np;
-    const T pex = b * psiEx[o] + c * dHy_dz;
-    const T pey = b * psiEy[o] + c * dHx_dz;
+    const T p0 = psiEx[o], p1 = psiEy[o];
+    const T pex = b * p0 + c * dHy_dz;
+    const T pey = b * p1 + c * dHx_dz;
     psiEx[o] = pex;
     psiEy[o] = pey;
     dHy_dz = dHy_dz * ki + pex;
     dHx_dz = dHx_dz * ki + pey;
   }
   const T curl[3] = {dHz_dy - dHy_dz, dHx_dz - dHz_dx, dHy_dx - dHx_dy};
-  T* E[3] = {f.Ex, f.Ey, f.Ez};
-  T* JD[3] = {f.JDx, f.JDy, f.JDz};
-  const uint8_t* mat = a.mat;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const int m = mat[c * n + idx];
-    const T e0 = E[c][idx];
+    const int m = mc[c];
     T J = T(0);
     if (m == a.metal_id) {
-      const T jd = static_cast<T>(a.alpha_d) * JD[c][idx] + static_cast<T>(a.beta_d) * e0;
+      const T jd = static_cast<T>(a.alpha_d) * jd0[c] + static_cast<T>(a.beta_d) * e0[c];
       JD[c][idx] = jd;
       J = jd;
     }
     if (c == 0 && k == a.src_k) J += static_cast<T>(a.src_term);
-    T e1 = e0 + static_cast<T>(a.ce[m & 3]) * (curl[c] - J);
+    T e1 = e0[c] + ce_select<T>(a, m & 3) * (curl[c] - J);
     if (c < 2 && k == 0) e1 = T(0);
     E[c][idx] = e1;
   }
 }
 
+static dim3 yee_grid(const FdArgs& a) {
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  return dim3(static_cast<unsigned>((plane + 255) / 256), static_cast<unsigned>(a.nz));
+}
+
 int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s) {
-  const long n = static_cast<long>(a.nx) * a.ny * a.nz;
-  const int blocks = static_cast<int>((n + 255) / 256);
   if (f32)
-    hipLaunchKernelGGL(yee_h_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_kernel<float>, yee_grid(a), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(yee_h_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_kernel<double>, yee_grid(a), dim3(256), 0, s, a);
   return static_cast<int>(hipGetLastError());
 }
 
 int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s) {
-  const long n = static_cast<long>(a.nx) * a.ny * a.nz;
-  const int blocks = static_cast<int>((n + 255) / 256);
   if (f32)
-    hipLaunchKernelGGL(yee_e_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_e_kernel<float>, yee_grid(a), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(yee_e_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_e_kernel<double>, yee_grid(a), dim3(256), 0, s, a);
   return static_cast<int>(hipGetLastError());
 }
 

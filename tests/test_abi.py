@@ -67,6 +67,10 @@ def test_fdtd_validation(msqd):
     assert msqd.lib.fdtd_workspace_bytes(C.byref(d)) == 0
     rc = msqd.lib.fdtd_step(C.byref(d), None, None, 0, 0.0, None)
     assert rc == msqd.MSQD_EINVAL
+    d = msqd.fdtd_desc_from_config(cfg)
+    d.nx, d.ny, d.nz = 1, 1, 70000   # one launch row holds at most 65535 planes
+    assert msqd.lib.fdtd_workspace_bytes(C.byref(d)) == 0
+    assert "65535" in msqd.last_error()
 
 
 @pytest.mark.parametrize("cfgname", ["cfg1", "cfg3"])
