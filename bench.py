@@ -414,8 +414,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 timing and comparison")
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the 700,000-molecule and adjoint measurements")
-    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64"], default=None,
-                    help="only time the molecular-step kernel of this form (for counter runs), "
+    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil"], default=None,
+                    help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -432,6 +432,15 @@ def main():
     cfg64 = get_config("cfg1")
     K, W = args.steps, args.warmup
     n0 = default_first_step(cfg) if args.n0 is None else args.n0
+    if args.kernel == "stencil":
+        ms = time_stencil(cfg, "mixed", K)
+        cells = cfg.nx * cfg.ny * cfg.nz
+        b = stencil_bytes_per_cell("mixed") * cells
+        calibration_copy()
+        print(json.dumps({"kernel": "stencil", "launches": K, "ms": ms, "cells": cells,
+                          "GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "calibration_copy_bytes": 1 << 30}))
+        return
     if args.kernel:
         c = cfg if args.kernel != "fp64" else cfg64
         ms = time_mol_kernel(c, args.kernel, K)

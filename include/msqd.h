@@ -147,7 +147,7 @@ typedef struct {
   double kappa_max, alpha_max;        /* CPML kappa_max (>= 1), alpha_max (S/m) */
   int32_t src_k;          /* plane of the soft current sheet on E_x         */
   int32_t mon_k;          /* detection plane (npml < mon_k < nz - npml)     */
-  int32_t n_freq;         /* monitor frequencies (0 = no monitor)           */
+  int32_t n_freq;         /* monitor frequencies (0 = no monitor, at most 65536) */
   int32_t mon_every;      /* monitor sampling interval in steps             */
   int32_t mon_k2;         /* second detection plane on the incident side for
                              reflection/absorption spectra (0 = none)       */

@@ -165,6 +165,7 @@ static int check_fd(const fdtd_desc* d) {
     return fail(MSQD_EINVAL, "bad CPML parameters");
   if (d->src_k < 1 || d->src_k >= d->nz) return fail(MSQD_EINVAL, "src_k outside the grid");
   if (d->n_freq < 0) return fail(MSQD_EINVAL, "n_freq < 0");
+  if (d->n_freq > 65536) return fail(MSQD_EUNSUP, "n_freq above 65536");
   if (d->n_freq > 0) {
     if (d->mon_k <= d->npml || d->mon_k >= d->nz - d->npml)
       return fail(MSQD_EINVAL, "mon_k must be inside the interior");

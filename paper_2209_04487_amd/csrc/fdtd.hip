@@ -221,17 +221,27 @@ int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s) {
 // ------------------------------------------------------------- monitor
 // dft layout [4][n_freq][ny][nx] complex128: E_x, E_y at t_E, and H_x, H_y
 // averaged over the planes mon_k -+ 1/2 at t_H.
+// Grid: (plane / 256, frequency groups of kMonFreqs).  Each thread reads the
+// plane point's fields and updates the accumulators of its group's
+// frequencies: all of the group's loads are issued before its stores, and
+// the frequency axis spreads the update over enough workgroups to fill the
+// chip on small planes.
+constexpr int kMonFreqs = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void monitor_kernel(MonArgs a) {
-  extern __shared__ double ph[];  // [n_freq][4]: cos tE, sin tE, cos tH, sin tH
-  for (int f = threadIdx.x; f < a.n_freq; f += blockDim.x) {
+  __shared__ double ph[kMonFreqs][4];  // cos tE, sin tE, cos tH, sin tH (times the weight)
+  const int f0 = static_cast<int>(blockIdx.y) * kMonFreqs;
+  const int nf = min(kMonFreqs, a.n_freq - f0);
+  if (threadIdx.x < nf) {
+    const int f = f0 + threadIdx.x;
     double s, c;
     sincos(a.freqs[f] * a.tE, &s, &c);
-    ph[4 * f + 0] = c * a.wdt;
-    ph[4 * f + 1] = s * a.wdt;
+    ph[threadIdx.x][0] = c * a.wdt;
+    ph[threadIdx.x][1] = s * a.wdt;
     sincos(a.freqs[f] * a.tH, &s, &c);
-    ph[4 * f + 2] = c * a.wdt;
-    ph[4 * f + 3] = s * a.wdt;
+    ph[threadIdx.x][2] = c * a.wdt;
+    ph[threadIdx.x][3] = s * a.wdt;
   }
   __syncthreads();
   const long plane = static_cast<long>(a.nx) * a.ny;
@@ -246,28 +256,39 @@ __global__ __launch_bounds__(256) void monitor_kernel(MonArgs a) {
                            static_cast<const T*>(a.Hy)[o]);
   const double val[4] = {ex, ey, hx, hy};
   double2* acc = reinterpret_cast<double2*>(a.dft);
-  for (int f = 0; f < a.n_freq; ++f) {
+  double2 z[kMonFreqs][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double cw = ph[4 * f + (c < 2 ? 0 : 2)];
-      const double sw = ph[4 * f + (c < 2 ? 1 : 3)];
-      const long q = (static_cast<long>(c) * a.n_freq + f) * plane + p;
-      double2 z = acc[q];
-      z.x += val[c] * cw;
-      z.y += val[c] * sw;
-      acc[q] = z;
+  for (int fi = 0; fi < kMonFreqs; ++fi) {
+    if (fi < nf) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) z[fi][c] = acc[(static_cast<long>(c) * a.n_freq + f0 + fi) * plane + p];
+    }
+  }
+#pragma unroll
+  for (int fi = 0; fi < kMonFreqs; ++fi) {
+    if (fi < nf) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double cw = ph[fi][c < 2 ? 0 : 2];
+        const double sw = ph[fi][c < 2 ? 1 : 3];
+        double2 w = z[fi][c];
+        w.x += val[c] * cw;
+        w.y += val[c] * sw;
+        acc[(static_cast<long>(c) * a.n_freq + f0 + fi) * plane + p] = w;
+      }
     }
   }
 }
 
 int launch_monitor(const MonArgs& a, bool f32, hipStream_t s) {
+  if (a.n_freq <= 0) return 0;
   const long plane = static_cast<long>(a.nx) * a.ny;
-  const int blocks = static_cast<int>((plane + 255) / 256);
-  const size_t shm = sizeof(double) * 4 * static_cast<size_t>(a.n_freq);
+  const dim3 grid(static_cast<unsigned>((plane + 255) / 256),
+                  static_cast<unsigned>((a.n_freq + kMonFreqs - 1) / kMonFreqs));
   if (f32)
-    hipLaunchKernelGGL(monitor_kernel<float>, dim3(blocks), dim3(256), shm, s, a);
+    hipLaunchKernelGGL(monitor_kernel<float>, grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(monitor_kernel<double>, dim3(blocks), dim3(256), shm, s, a);
+    hipLaunchKernelGGL(monitor_kernel<double>, grid, dim3(256), 0, s, a);
   return static_cast<int>(hipGetLastError());
 }
 

@@ -49,24 +49,50 @@ constexpr int fwd_split() {
 template <int NR, typename T>
 constexpr int fwd_line_stride() { return NR / fwd_split<NR, T>() + FftShape<NR, T>::R2; }
 
-// Bytes of the per-workgroup LDS copy of the transform tables (kinetic
-// factors, four-step twiddles, absorber mask), kept ahead of the lines.
-// (complex64 forms only: the complex128 form holds one molecule per CU, where
-// the staged tables measured slower than reading them through the caches.)
+// The per-workgroup LDS copy of the transform tables (kinetic factors,
+// four-step twiddles, absorber mask), kept ahead of the lines (complex64
+// forms only: the complex128 form holds one molecule per CU, where the staged
+// tables measured slower than reading them through the caches).  The twiddle
+// table is either the full R1 x R1 table or, with COMPACT, only the R2 rows
+// that the transforms read, in rows of R1 + 1 (the pad spreads the lanes of a
+// line over distinct banks): the compact form is for kernels whose
+// occupancy is bounded by LDS.
+template <int NR, typename T, bool COMPACT = false>
+struct StagedTables {
+  static constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  static constexpr bool on = sizeof(T) == 4;
+  static constexpr int TWC = (on && COMPACT) ? R1 + 1 : 0;   // compact row stride (0: full layout)
+  static constexpr size_t tw_elems =
+      on ? (COMPACT ? static_cast<size_t>(R2) * (R1 + 1) : static_cast<size_t>(R1) * R1) : 0;
+  static constexpr size_t bytes =
+      on ? (NR * sizeof(cx<T>) + tw_elems * sizeof(cx<T>) + NR * sizeof(T) + 15) / 16 * 16 : 0;
+};
 template <int NR, typename T>
-constexpr bool stage_tables() { return sizeof(T) == 4; }
+constexpr bool stage_tables() { return StagedTables<NR, T>::on; }
 template <int NR, typename T>
-constexpr size_t lds_table_bytes() {
-  constexpr int R1 = FftShape<NR, T>::R1;
-  return stage_tables<NR, T>() ? ((NR * sizeof(cx<T>) + R1 * R1 * sizeof(cx<T>) + NR * sizeof(T)) + 15) / 16 * 16
-                               : 0;
-}
+constexpr size_t lds_table_bytes() { return StagedTables<NR, T>::bytes; }
 
 // Cooperative copy of a table into LDS in 16-byte pieces.
 __device__ __forceinline__ void lds_stage(void* dst, const void* src, size_t bytes) {
   const uint4* s = static_cast<const uint4*>(src);
   uint4* d = static_cast<uint4*>(dst);
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+// Stage the tables: kin [NR], the twiddles of the R1 x R1 table tw_g (all,
+// or the rows x < R2 in the compact layout), and mask [NR]; the caller
+// synchronises the workgroup afterwards.
+template <int NR, typename T, bool COMPACT = false>
+__device__ __forceinline__ void stage_tables_to_lds(cx<T>* kin_s, cx<T>* tw_s, T* mask_s, const cx<T>* kin_g,
+                                                    const cx<T>* tw_g, const T* mask_g) {
+  typedef StagedTables<NR, T, COMPACT> ST;
+  lds_stage(kin_s, kin_g, NR * sizeof(cx<T>));
+  if constexpr (COMPACT) {
+    for (int t = threadIdx.x; t < ST::R2 * ST::R1; t += blockDim.x) tw_s[(t / ST::R1) * ST::TWC + t % ST::R1] = tw_g[t];
+  } else {
+    lds_stage(tw_s, tw_g, ST::tw_elems * sizeof(cx<T>));
+  }
+  lds_stage(mask_s, mask_g, NR * sizeof(T));
 }
 
 template <int NR, typename T>
@@ -146,8 +172,10 @@ struct MolTabs {
 // region (R2 * (R1 + 1) elements).  kin is applied by kin_mul, which
 // includes the 1/NR of the inverse transform.  tw2[x * R1 + y] = exp(-2 pi i x y / NR) for
 // x, y < R1, so that every table access is a uniform base plus one lane
-// offset plus an immediate.
-template <typename T, int NR, bool CONJ = false, int SP = 1>
+// offset plus an immediate.  With TWC > 0 the table is the compact one that
+// holds only the rows x < R2 that are read (exp(-2 pi i x y / NR) at
+// x * TWC + y, TWC >= R1): one lane offset x = q serves both passes.
+template <typename T, int NR, bool CONJ = false, int SP = 1, int TWC = 0>
 __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
                                              const cx<T>* __restrict__ tw2) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2;
@@ -157,7 +185,7 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
   // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
   dft<R1, false, T>(v);
 #pragma unroll
-  for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], tw2[a * R1 + q]);
+  for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], TWC > 0 ? tw2[q * TWC + a] : tw2[a * R1 + q]);
 #pragma unroll
   for (int h = 0; h < SP; ++h) {
     if (h > 0) wave_lds_sync();
@@ -180,7 +208,7 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
       for (int b = 0; b < R2; ++b) w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
       dft<R2, true, T>(w);
 #pragma unroll
-      for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * R1 + a]);
+      for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * (TWC > 0 ? TWC : R1) + a]);
     }
     wave_lds_sync();
 #pragma unroll
@@ -564,7 +592,7 @@ void mol_step_kernel(MolArgs a) {
   constexpr size_t TB = lds_table_bytes<NR, T>();
   cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
   cx<T>* tw_s = kin_s + NR;
-  T* mask_s = reinterpret_cast<T*>(tw_s + R1 * R1);
+  T* mask_s = reinterpret_cast<T*>(tw_s + StagedTables<NR, T>::tw_elems);
   cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TB);
   double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * lds_row<NR, T>(L));
 
@@ -620,9 +648,7 @@ void mol_step_kernel(MolArgs a) {
   // the tables read at every element go to LDS (the per-element L1/L2
   // traffic and latency of these reads dominated the step otherwise)
   if constexpr (stage_tables<NR, T>()) {
-    lds_stage(kin_s, tb.kin, NR * sizeof(cx<T>));
-    lds_stage(tw_s, tb.tw, R1 * R1 * sizeof(cx<T>));
-    lds_stage(mask_s, tb.mask, NR * sizeof(T));
+    stage_tables_to_lds<NR, T>(kin_s, tw_s, mask_s, tb.kin, tb.tw, tb.mask);
     __syncthreads();
   }
 

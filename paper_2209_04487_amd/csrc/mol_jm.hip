@@ -57,14 +57,29 @@ __device__ __forceinline__ void coupling_jm_point(cx<T>* g, cx<T>* e, const cx<T
 
 }  // namespace
 
+// Same work decomposition as the m = 0 step (mol_impl.h): lanes own radial
+// columns of one line for the transforms, and complex64 lines go through LDS
+// in two rounds of half the radial points, the pointwise coupling included.
+// The tables are staged in the compact layout (complex64 forms), which keeps
+// a workgroup small enough for ten molecules per CU.
+// Occupancy target: three waves per SIMD for the complex64 form (168
+// registers); the complex128 form takes what it needs.
+template <typename T>
+struct JmOcc { static constexpr int waves = sizeof(T) == 4 ? 3 : 1; };
+
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void mol_jm_kernel(MolArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::waves))) void mol_jm_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   constexpr int NB = 4, L = 2 * NB;
-  constexpr int LS = line_stride<NR, T>();
+  constexpr int SP = fwd_split<NR, T>(), PH = R1 / SP, NRH = NR / SP;
+  typedef StagedTables<NR, T, true> TBL;
+  constexpr size_t TB = TBL::bytes;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* sh = reinterpret_cast<cx<T>*>(smem);
-  double* red = reinterpret_cast<double*>(smem + sizeof(cx<T>) * L * LS);
+  cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tw_s = kin_s + NR;
+  T* mask_s = reinterpret_cast<T*>(tw_s + TBL::tw_elems);
+  cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TB);
+  double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * lds_row<NR, T>(L));
 
   const int mol = blockIdx.x;
   const int tid = threadIdx.x;
@@ -75,11 +90,11 @@ __global__ __launch_bounds__(256) void mol_jm_kernel(MolArgs a) {
 
   const char* ws = a.ws;
   const bool dbl = sizeof(T) == 8;
-  const cx<T>* kin = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.kin_d : a.lay.kin_f));
-  const cx<T>* tw = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.tw_d : a.lay.tw_f));
-  const cx<T>* vph = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.vph_d : a.lay.vph_f));
+  const cx<T>* kin_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.kin_d : a.lay.kin_f));
+  const cx<T>* tw_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.tw_d : a.lay.tw_f));
+  const cx<T>* vph_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.vph_d : a.lay.vph_f));
   const T* mudt = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mudt_d : a.lay.mudt_f));
-  const T* mask = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mask_d : a.lay.mask_f));
+  const T* mask_g = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mask_d : a.lay.mask_f));
   const double* mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
 
   // field at the molecule (each component at its own edge of the cell)
@@ -106,72 +121,113 @@ __global__ __launch_bounds__(256) void mol_jm_kernel(MolArgs a) {
   const T a2 = static_cast<T>(a2d), aa = static_cast<T>(sqrt(a2d));
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
-  cx<T>* slot = sh + line * LS;
+  cx<T>* slot = sh + lds_row<NR, T>(line);
   const int loff = line * NR + q;
   const int voff = (st * a.nj + jl) * NR + q;   // potential phases depend on (state, j)
   cx<T> vv[R1];
 #pragma unroll
   for (int p = 0; p < R1; ++p) vv[p] = psi[loff + R2 * p];
+  if constexpr (stage_tables<NR, T>()) {
+    stage_tables_to_lds<NR, T, true>(kin_s, tw_s, mask_s, kin_g, tw_g, mask_g);
+    __syncthreads();
+  }
 
   double ab = 0.0;
   for (int step = 0; step < a.n_steps; ++step) {
-    kinetic_half<T, NR>(vv, slot, q, kin, tw);
+    const cx<T>* kin;
+    const cx<T>* tw;
+    const T* mask;
+    if constexpr (stage_tables<NR, T>()) {
+      kin = kin_s;
+      tw = tw_s;
+      mask = mask_s;
+    } else {
+      kin = opaque(kin_g);
+      tw = opaque(tw_g);
+      mask = opaque(mask_g);
+    }
+    const cx<T>* vph = opaque(vph_g);
+    kinetic_half<T, NR, false, SP, TBL::TWC>(vv, slot, q, kin, tw);
 #pragma unroll
-    for (int p = 0; p < R1; ++p) slot[q + R2 * p] = phase_mul(vv[p], vph[voff + R2 * p]);
-    __syncthreads();
-    for (int r = tid; r < NR; r += nthr) {
-      cx<T> g[NB], e[NB];
+    for (int h = 0; h < SP; ++h) {
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        g[k] = sh[k * LS + r];
-        e[k] = sh[(NB + k) * LS + r];
+      for (int pp = 0; pp < PH; ++pp) {
+        const int p = h * PH + pp;
+        slot[q + R2 * pp] = phase_mul(vv[p], vph[voff + R2 * p]);
       }
-      coupling_jm_point(g, e, v, aa, a2, mudt[r]);
+      __syncthreads();
+      for (int rl = tid; rl < NRH; rl += nthr) {
+        cx<T> g[NB], e[NB];
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        sh[k * LS + r] = g[k];
-        sh[(NB + k) * LS + r] = e[k];
+        for (int k = 0; k < NB; ++k) {
+          g[k] = sh[lds_row<NR, T>(k) + rl];
+          e[k] = sh[lds_row<NR, T>(NB + k) + rl];
+        }
+        coupling_jm_point(g, e, v, aa, a2, mudt[h * NRH + rl]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          sh[lds_row<NR, T>(k) + rl] = g[k];
+          sh[lds_row<NR, T>(NB + k) + rl] = e[k];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int pp = 0; pp < PH; ++pp) {
+        const int p = h * PH + pp;
+        vv[p] = phase_mul(slot[q + R2 * pp], vph[voff + R2 * p]);
       }
     }
-    __syncthreads();
+    kinetic_half<T, NR, false, SP, TBL::TWC>(vv, slot, q, kin, tw);
+    // absorber: when it lies within the last quarter of the grid only those
+    // registers are tested (one uniform branch), otherwise all
+    constexpr int P0 = (3 * R1) / 4;
+    if (a.kmask >= R2 * P0) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) vv[p] = phase_mul(slot[q + R2 * p], vph[voff + R2 * p]);
-    kinetic_half<T, NR>(vv, slot, q, kin, tw);
+      for (int p = P0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
+    } else {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
+      for (int p = 0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
+    }
   }
 
-  // readouts: norm, yield, and the dipole vector
+  // readouts: norm, yield, and the dipole vector (in the same rounds of
+  // radial points)
   double nrm = 0.0, yld = 0.0;
 #pragma unroll
   for (int p = 0; p < R1; ++p) {
     const double n2 = static_cast<double>(norm2(vv[p]));
     nrm += n2;
     if (q + R2 * p >= a.kdiss) yld += n2;
-    slot[q + R2 * p] = vv[p];
   }
-  __syncthreads();
   double dc[3] = {0.0, 0.0, 0.0};
-  for (int r = tid; r < NR; r += nthr) {
-    cx<double> g[NB], e[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const cx<T> gt = sh[k * LS + r], et = sh[(NB + k) * LS + r];
-      g[k] = {static_cast<double>(gt.x), static_cast<double>(gt.y)};
-      e[k] = {static_cast<double>(et.x), static_cast<double>(et.y)};
+  for (int h = 0; h < SP; ++h) {
+    __syncthreads();   // the previous users of the slots are done
+#pragma unroll
+    for (int pp = 0; pp < PH; ++pp) slot[q + R2 * pp] = vv[h * PH + pp];
+    __syncthreads();
+    for (int rl = tid; rl < NRH; rl += nthr) {
+      cx<double> g[NB], e[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const cx<T> gt = sh[lds_row<NR, T>(k) + rl], et = sh[lds_row<NR, T>(NB + k) + rl];
+        g[k] = {static_cast<double>(gt.x), static_cast<double>(gt.y)};
+        e[k] = {static_cast<double>(et.x), static_cast<double>(et.y)};
+      }
+      // Re[conj(g0) <w|e_1> + <g_1|w> e0] for w_x, w_y, w_z
+      const cx<double> ex_ = {(e[1].x - e[3].x) * kInvSqrt6, (e[1].y - e[3].y) * kInvSqrt6};   // <w_x|e_1>
+      const cx<double> gx_ = {(g[1].x - g[3].x) * kInvSqrt6, -(g[1].y - g[3].y) * kInvSqrt6};  // <g_1|w_x>
+      // <w_y|e_1> = -i (e_-1 + e_+1)/sqrt6 ; <g_1|w_y> = i conj(g_-1 + g_+1)/sqrt6
+      const cx<double> ey_ = {(e[1].y + e[3].y) * kInvSqrt6, -(e[1].x + e[3].x) * kInvSqrt6};
+      const cx<double> gy_ = {(g[1].y + g[3].y) * kInvSqrt6, (g[1].x + g[3].x) * kInvSqrt6};
+      const double tx = (g[0].x * ex_.x + g[0].y * ex_.y) + (gx_.x * e[0].x - gx_.y * e[0].y);
+      const double ty = (g[0].x * ey_.x + g[0].y * ey_.y) + (gy_.x * e[0].x - gy_.y * e[0].y);
+      const double tz = kInvSqrt3 * ((g[0].x * e[2].x + g[0].y * e[2].y) + (g[2].x * e[0].x + g[2].y * e[0].y));
+      const double m = mu[h * NRH + rl];
+      dc[0] += m * tx;
+      dc[1] += m * ty;
+      dc[2] += m * tz;
     }
-    // Re[conj(g0) <w|e_1> + <g_1|w> e0] for w_x, w_y, w_z
-    const cx<double> ex_ = {(e[1].x - e[3].x) * kInvSqrt6, (e[1].y - e[3].y) * kInvSqrt6};   // <w_x|e_1>
-    const cx<double> gx_ = {(g[1].x - g[3].x) * kInvSqrt6, -(g[1].y - g[3].y) * kInvSqrt6};  // <g_1|w_x>
-    // <w_y|e_1> = -i (e_-1 + e_+1)/sqrt6 ; <g_1|w_y> = i conj(g_-1 + g_+1)/sqrt6
-    const cx<double> ey_ = {(e[1].y + e[3].y) * kInvSqrt6, -(e[1].x + e[3].x) * kInvSqrt6};
-    const cx<double> gy_ = {(g[1].y + g[3].y) * kInvSqrt6, (g[1].x + g[3].x) * kInvSqrt6};
-    const double tx = (g[0].x * ex_.x + g[0].y * ex_.y) + (gx_.x * e[0].x - gx_.y * e[0].y);
-    const double ty = (g[0].x * ey_.x + g[0].y * ey_.y) + (gy_.x * e[0].x - gy_.y * e[0].y);
-    const double tz = kInvSqrt3 * ((g[0].x * e[2].x + g[0].y * e[2].y) + (g[2].x * e[0].x + g[2].y * e[0].y));
-    dc[0] += mu[r] * tx;
-    dc[1] += mu[r] * ty;
-    dc[2] += mu[r] * tz;
   }
   // workgroup sums of (ab, nrm, yld, dx, dy, dz) in a fixed order
   double vals[6] = {ab, nrm, yld, dc[0], dc[1], dc[2]};
@@ -208,11 +264,21 @@ __global__ __launch_bounds__(256) void mol_jm_kernel(MolArgs a) {
   }
 }
 
+// LDS bytes of one (j, m) workgroup: staged tables, the eight line slots,
+// and the reduction scratch
+template <typename T, int NR>
+constexpr size_t jm_lds_bytes() {
+  return StagedTables<NR, T, true>::bytes +
+         sizeof(cx<T>) * static_cast<size_t>(lds_line_start(8, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
+         6 * 16 * sizeof(double);
+}
+
 template <typename T, int NR>
 int launch_jm_t(const MolArgs& a, hipStream_t s) {
   constexpr int R2 = FftShape<NR, T>::R2;
   const int threads = 8 * R2;
-  const size_t shm = sizeof(cx<T>) * 8 * static_cast<size_t>(line_stride<NR, T>()) + 6 * 16 * sizeof(double);
+  const size_t shm = jm_lds_bytes<T, NR>();
+  if (shm > mol_lds_limit()) return static_cast<int>(hipErrorInvalidValue);
   static bool attr_set = false;
   if (!attr_set && shm > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_jm_kernel<T, NR>),

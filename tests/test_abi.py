@@ -71,6 +71,10 @@ def test_fdtd_validation(msqd):
     d.nx, d.ny, d.nz = 1, 1, 70000   # one launch row holds at most 65535 planes
     assert msqd.lib.fdtd_workspace_bytes(C.byref(d)) == 0
     assert "65535" in msqd.last_error()
+    d = msqd.fdtd_desc_from_config(cfg)
+    d.n_freq = 70000
+    assert msqd.lib.fdtd_workspace_bytes(C.byref(d)) == 0
+    assert "n_freq" in msqd.last_error()
 
 
 @pytest.mark.parametrize("cfgname", ["cfg1", "cfg3"])
