@@ -39,6 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed-FP32 instructions (not used by this
 # library): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 78.6
+# dense BF16 matrix-core peak (no structured sparsity)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "mol_step_mixed_srr100k_counters.md")
 METRIC = "molecule-steps/s, coupled step, FP32/BF16 vs FP64 at ≤1e-4 rel dipole err"
 
@@ -394,7 +396,17 @@ def cpu_baseline(cfg, budget_s=20.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": rate, "unit": "molecule-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_count": os.cpu_count(), "cpu_model": model,
             "sample": (f"FP64 NumPy oracle: full {cfg.nx}x{cfg.ny}x{cfg.nz} field update x{n_f} "
                        f"({t_field:.3f} s/step) and {n_blk} molecules x {n_m} steps "
                        f"({t_mol * 1e3:.3f} ms/molecule-step), combined for {cfg.n_mol} molecules; "
@@ -537,6 +549,12 @@ def main():
             "kernel": "mol_step_kernel<float,256,bf16x3>", "kernel_ms": mol_ms,
             "flops_per_molecule_step": unit_flops,
             "mfma_flops_per_molecule_step": mol_mfma_flops_per_step(cfg),
+            "mfma": {"achieved": mol_mfma_flops_per_step(cfg) * cfg.n_mol / (mol_ms / 1e3) / 1e12,
+                     "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": mol_mfma_flops_per_step(cfg) * cfg.n_mol / (mol_ms / 1e3) / 1e12
+                     / BF16_MFMA_PEAK_TFLOPS,
+                     "counted": "the J<->angle contractions at N_J; not the three BF16 products per "
+                                "contraction nor the padding of N_J to 16"},
             "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved_gbs / HBM_PEAK_GBS, "bytes_per_molecule_step": unit_bytes,
                     "algorithmic_bytes_per_launch": unit_bytes * cfg.n_mol},

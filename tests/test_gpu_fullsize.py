@@ -4,8 +4,11 @@ times.
 - molecular step with 100,000 molecules (N_r = 256, J <= 10) in the FP64 and
   precision forms: a seeded sample of molecules compared element by element
   with the oracle stepping the same molecules under the same seeded fields;
-- field solver on the full 192 x 192 x 120 SRR grid (FP64): every component
-  after 40 steps against the oracle;
+- field solver on the full 192 x 192 x 120 SRR grid (FP64): every E and H
+  component after 40, 120 and 240 steps against the oracle;
+- decoupled replay: the fields that 64 seeded molecules saw in a 600-step
+  FP64 coupled run of the full workload drive the oracle's molecules, whose
+  dipoles match the coupled run's at every step;
 - coupled step on the full workload (precision form): properties that hold
   at any size (norm + absorbed = 1, the gathered field equals E_x at the
   molecule's edge, each cell's polarisation equals its molecules' dipole sum);
@@ -64,23 +67,71 @@ def test_full_batch_sampled_molecules(name, prec):
 
 
 def test_full_grid_fields_fp64():
+    """The field solver on the full grid until the pulse has crossed the
+    split rings, the molecule slab and the lower CPML: every E and H component
+    against the oracle after 40, 120 and 240 steps."""
     from paper_2209_04487_amd import msqd
     cfg = get_config("cfg1", t0_steps=30.0, t0_fs=None, fwhm_fs=1.0)
-    nsteps = 40
+    checks = [40, 120, 240]
+    nsteps = checks[-1]
     banner(f"full grid fields cfg1 fp64: {cfg.nx}x{cfg.ny}x{cfg.nz}, {nsteps} steps")
     mat = material_map(cfg)
     src = source_values(cfg, 0, nsteps)
     fl = msqd.Fields(msqd.fdtd_desc_from_config(cfg, "fp64", n_freq=0), mat, [])
-    for n in range(nsteps):
-        fl.step(n, src[n])
-    torch.cuda.synchronize()
     yee = yee_from_config(cfg, mat, eps_table(cfg))
+    n = 0
+    for stop in checks:
+        for m in range(n, stop):
+            fl.step(m, src[m])
+            yee.update_H()
+            yee.update_E(src[m], cfg.src_k)
+        n = stop
+        torch.cuda.synchronize()
+        emax = max(np.abs(e).max() for e in yee.E)
+        hmax = max(np.abs(h).max() for h in yee.H)
+        for c, nm in enumerate(["Ex", "Ey", "Ez"]):
+            assert np.abs(getattr(fl, nm).cpu().numpy() - yee.E[c]).max() < 1e-11 * emax, (stop, nm)
+        for c, nm in enumerate(["Hx", "Hy", "Hz"]):
+            assert np.abs(getattr(fl, nm).cpu().numpy() - yee.H[c]).max() < 1e-11 * hmax, (stop, nm)
+
+
+def test_decoupled_replay_full_workload_fp64():
+    """Parity of the coupled run at the full workload (100,000 molecules, the
+    192 x 192 x 120 grid, FP64) over 600 steps around the pulse peak: the
+    field that each of 64 seeded molecules saw, recorded from the coupled run,
+    drives the oracle's molecules from the same initial state, and their
+    dipoles agree with the coupled run's at every step."""
+    from paper_2209_04487_amd import msqd
+    from workloads.molecule_inputs import morse_v0
+    cfg = get_config("cfg1")
+    n0, nsteps = 5400, 600
+    banner(f"decoupled replay cfg1 fp64: {cfg.n_mol} molecules, steps {n0}..{n0 + nsteps}")
+    sysm = msqd.Coupled(cfg, prec="fp64", n_freq=0)
+    sysm.n = n0
+    rng = np.random.default_rng(21)
+    sample = np.sort(rng.choice(cfg.n_mol, 64, replace=False))
+    sample[-1] = cfg.n_mol - 1
+    idx = torch.as_tensor(sample, device="cuda")
+    src = source_values(cfg, n0, nsteps)
+    E_rec = np.empty((nsteps, len(sample)))
+    d_rec = np.empty((nsteps, len(sample)))
     for n in range(nsteps):
-        yee.update_H()
-        yee.update_E(src[n], cfg.src_k)
-    emax = max(np.abs(e).max() for e in yee.E)
-    for c, nm in enumerate(["Ex", "Ey", "Ez"]):
-        assert np.abs(getattr(fl, nm).cpu().numpy() - yee.E[c]).max() < 1e-11 * emax, nm
+        sysm.step(src[n:n + 1])
+        E_rec[n] = sysm.E_mol[idx].cpu().numpy()
+        d_rec[n] = sysm.mol.d[idx].cpu().numpy()
+    msqd.check_status(sysm.mol.ws)
+    assert np.abs(E_rec).max() > 1e-6        # the pulse reached the molecules
+    om = model_from_config(cfg, *potentials(cfg))
+    psi = om.initial_state(len(sample), morse_v0(cfg))
+    ab = np.zeros(len(sample))
+    d_or = np.empty_like(d_rec)
+    for n in range(nsteps):
+        psi, ab = om.step(psi, E_rec[n], ab)
+        d_or[n] = om.dipole(psi)
+    assert np.abs(d_or).max() > 0
+    assert rel_err(d_rec, d_or) < 1e-10
+    got = sysm.mol.psi[idx].cpu().numpy()
+    assert rel_err(got, psi) < 1e-10
 
 
 def test_full_coupled_invariants_mixed():
