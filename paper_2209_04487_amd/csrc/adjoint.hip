@@ -236,14 +236,10 @@ static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
   int threads = ((L * R2 + 63) / 64) * 64;
   if (threads < 64) threads = 64;
   const size_t shm = mol_adj_lds_bytes(NR, a.nj, sizeof(T) == 4);
-  static bool attr_set = false;
-  if (!attr_set && shm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(mol_lds_limit()));
-    (void)hipGetLastError();
+  static std::atomic<unsigned long long> lds_set{0};
+  if (shm > 64 * 1024) {
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
-    attr_set = true;
   }
   hipLaunchKernelGGL((mol_adj_kernel<T, NR>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());

@@ -96,26 +96,40 @@ size_t mol_lds_bytes(int n_r, int nj, int prec) {
   // exchange rounds of the forward step (two for complex64 lines with an
   // even number of columns per lane)
   const int split = (el == 8 && (r1 / r2) % 2 == 0) ? 2 : 1;
-  // transform tables staged in LDS: kinetic factors, twiddles, mask
+  // tables staged in LDS: kinetic factors, twiddles, mask, and the
+  // contraction operands (2 KB of matrix-core fragments, 16 angle nodes)
   const bool staged = el == 8;
-  const size_t tables = staged ? (el * n_r + el * static_cast<size_t>(r1) * r1 + (el / 2) * n_r + 15) / 16 * 16 : 0;
+  const size_t tables =
+      staged ? (el * n_r + el * static_cast<size_t>(r1) * r1 + (el / 2) * n_r + 15) / 16 * 16 + 2048 + 64 : 0;
   return tables + el * static_cast<size_t>(lds_line_start(2 * nj, n_r / split + r2, static_cast<int>(el))) +
          16 * 4 * sizeof(double);
 }
 
 size_t mol_lds_limit() {
-  static int cached = -1;
-  if (cached < 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0) {
-      cached = v;
-    } else {
-      cached = 64 * 1024;
-    }
+  static std::atomic<int> cached{-1};
+  int v = cached.load(std::memory_order_acquire);
+  if (v < 0) {
+    int dev = 0;
+    v = 0;
+    if (!(hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0))
+      v = 64 * 1024;
     (void)hipGetLastError();
+    cached.store(v, std::memory_order_release);
   }
-  return static_cast<size_t>(cached);
+  return static_cast<size_t>(v);
+}
+
+hipError_t allow_large_lds(const void* kernel, std::atomic<unsigned long long>& done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const unsigned long long bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0ull;
+  if (bit != 0 && (done.load(std::memory_order_acquire) & bit) != 0) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(mol_lds_limit()));
+  (void)hipGetLastError();
+  if (e == hipSuccess && bit != 0) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
 }
 
 // ------------------------------------------------------------ validation

@@ -1,6 +1,8 @@
 // Molecular step: kernel arguments and the workspace layout of the tables.
 #pragma once
 
+#include <atomic>
+
 #include "common.h"
 
 namespace msqd {
@@ -62,6 +64,11 @@ struct MolArgs {
 // LDS limit (queried once).
 size_t mol_lds_bytes(int n_r, int nj, int prec);
 size_t mol_lds_limit();
+
+// Let a kernel use more than 64 KB of dynamic LDS on the current device.  The
+// attribute is per device: `done` keeps one bit per device id already set
+// (ids >= 64 are set on every call).  Safe to call from several host threads.
+hipError_t allow_large_lds(const void* kernel, std::atomic<unsigned long long>& done);
 
 // launchers (return a hipError_t value cast to int)
 int launch_mol_fp64(const MolArgs& a, int n_r, hipStream_t s);

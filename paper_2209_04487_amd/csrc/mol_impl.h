@@ -57,15 +57,22 @@ constexpr int fwd_line_stride() { return NR / fwd_split<NR, T>() + FftShape<NR, 
 // that the transforms read, in rows of R1 + 1 (the pad spreads the lanes of a
 // line over distinct banks): the compact form is for kernels whose
 // occupancy is bounded by LDS.
-template <int NR, typename T, bool COMPACT = false>
+//
+// With CPOPS the copy also holds the operands of the J <-> angle contraction
+// (the matrix-core fragments of T and T^T, 2 KB, and the angle nodes padded
+// with zeros to 16), which every exchange round of every step reads.
+template <int NR, typename T, bool COMPACT = false, bool CPOPS = true>
 struct StagedTables {
   static constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   static constexpr bool on = sizeof(T) == 4;
   static constexpr int TWC = (on && COMPACT) ? R1 + 1 : 0;   // compact row stride (0: full layout)
   static constexpr size_t tw_elems =
       on ? (COMPACT ? static_cast<size_t>(R2) * (R1 + 1) : static_cast<size_t>(R1) * R1) : 0;
-  static constexpr size_t bytes =
-      on ? (NR * sizeof(cx<T>) + tw_elems * sizeof(cx<T>) + NR * sizeof(T) + 15) / 16 * 16 : 0;
+  static constexpr size_t fft_bytes = (NR * sizeof(cx<T>) + tw_elems * sizeof(cx<T>) + NR * sizeof(T) + 15) / 16 * 16;
+  static constexpr size_t frag_bytes = 4 * 64 * 4 * 2;   // bf16 [4][64][4] or float [2][64][4]
+  static constexpr int x_pad = 16;
+  static constexpr size_t cp_bytes = (on && CPOPS) ? frag_bytes + x_pad * sizeof(float) : 0;
+  static constexpr size_t bytes = on ? fft_bytes + cp_bytes : 0;
 };
 template <int NR, typename T>
 constexpr bool stage_tables() { return StagedTables<NR, T>::on; }
@@ -85,7 +92,7 @@ __device__ __forceinline__ void lds_stage(void* dst, const void* src, size_t byt
 template <int NR, typename T, bool COMPACT = false>
 __device__ __forceinline__ void stage_tables_to_lds(cx<T>* kin_s, cx<T>* tw_s, T* mask_s, const cx<T>* kin_g,
                                                     const cx<T>* tw_g, const T* mask_g) {
-  typedef StagedTables<NR, T, COMPACT> ST;
+  typedef StagedTables<NR, T, COMPACT, false> ST;
   lds_stage(kin_s, kin_g, NR * sizeof(cx<T>));
   if constexpr (COMPACT) {
     for (int t = threadIdx.x; t < ST::R2 * ST::R1; t += blockDim.x) tw_s[(t / ST::R1) * ST::TWC + t % ST::R1] = tw_g[t];
@@ -300,6 +307,15 @@ __device__ __forceinline__ void rotate(cx<T>& g, cx<T>& e, T c, T s) {
 // r0 + l%16 and J (or node) rows 4(l/16) .. 4(l/16)+3, which is the operand
 // layout of the 16x16x16 instruction, so the forward product's output is
 // directly the inverse product's B operand.
+// The lane index, hidden from the optimiser so that the lane-dependent
+// addresses of a contraction round are recomputed there (a few integer
+// operations) instead of being kept live, or spilled, across the transforms.
+__device__ __forceinline__ int fresh_lane() {
+  int l = static_cast<int>(threadIdx.x) & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 typedef short mf_short4 __attribute__((ext_vector_type(4)));
 typedef float mf_float4 __attribute__((ext_vector_type(4)));
 
@@ -326,7 +342,8 @@ __device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short
   return c;
 }
 
-// frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16
+// frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16;
+// x: the angle nodes padded with zeros to 16
 template <int NR>
 __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
                                            const unsigned short* __restrict__ frag,
@@ -334,8 +351,8 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
                                            const float* __restrict__ mudt, float E) {
   using T = float;
   constexpr int NRH = NR / fwd_split<NR, float>();   // radial points of this round
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int lane = fresh_lane();
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int nwaves = (blockDim.x + 63) >> 6;
   const int col = lane & 15;
   const int rb = (lane >> 4) * 4;  // first J (inputs) / node (outputs) row of this lane
@@ -349,7 +366,7 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
   }
   float xk[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) xk[i] = (rb + i < nj) ? x[rb + i] : 0.0f;
+  for (int i = 0; i < 4; ++i) xk[i] = x[rb + i];   // x holds 16 nodes, zero beyond nj
 #pragma unroll 1
   for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
     const int rl = tile * 16 + col;   // radial point within the round (LDS)
@@ -461,8 +478,8 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
                                                     const T* __restrict__ mudt, T E) {
   typedef typename MfmaK4<T>::acc acc_t;
   constexpr int NRH = NR / fwd_split<NR, T>();
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int lane = fresh_lane();
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int nwaves = (blockDim.x + 63) >> 6;
   const int col = lane & 15;
   const int grp = lane >> 4;
@@ -560,7 +577,16 @@ __device__ __forceinline__ void block_sum4(double* v, double* red) {
 template <typename T>
 __device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
 
-// absorber mask at one point: the removed probability is accumulated in FP64
+// Absorber mask at one point: the removed probability is accumulated in
+// FP64.  absorb_point_nb is the same without the branch (bit-identical: m = 1
+// adds 0 and scales by 1), for the few registers that may lie in the
+// absorber: one read-modify-write of the accumulator per step instead of one
+// per taken branch.
+template <typename T>
+__device__ __forceinline__ void absorb_point_nb(cx<T>& v, T m, double& ab) {
+  ab += static_cast<double>((T(1) - m * m) * norm2(v));
+  v = cscale(v, m);
+}
 template <typename T>
 __device__ __forceinline__ void absorb_point(cx<T>& v, T m, double& ab) {
   if (m != T(1)) {
@@ -570,10 +596,11 @@ __device__ __forceinline__ void absorb_point(cx<T>& v, T m, double& ab) {
 }
 
 // --------------------------------------------------------------- kernel
-// Occupancy target (waves per SIMD) of the fused step.  The FP32 forms
-// (three waves per molecule at J_max = 10, n_r = 256) run three molecules per
-// CU, bounded by LDS, within 168 VGPRs; the FP64 form is bounded by LDS (one
-// molecule of complex128 lines per CU) and may use 256 VGPRs.
+// Occupancy target (waves per SIMD) of the fused step.  The complex64 forms
+// (three waves per molecule at J_max = 10, n_r = 256) run four molecules per
+// CU within 168 VGPRs, which the LDS copy of a molecule also allows; the FP64
+// form is bounded by LDS (one molecule of complex128 lines per CU) and may use
+// 256 VGPRs.
 template <typename T>
 struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : 3; };
 
@@ -593,6 +620,8 @@ void mol_step_kernel(MolArgs a) {
   cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
   cx<T>* tw_s = kin_s + NR;
   T* mask_s = reinterpret_cast<T*>(tw_s + StagedTables<NR, T>::tw_elems);
+  unsigned char* frag_s = smem + StagedTables<NR, T>::fft_bytes;
+  float* x_s = reinterpret_cast<float*>(frag_s + StagedTables<NR, T>::frag_bytes);
   cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TB);
   double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * lds_row<NR, T>(L));
 
@@ -649,6 +678,8 @@ void mol_step_kernel(MolArgs a) {
   // traffic and latency of these reads dominated the step otherwise)
   if constexpr (stage_tables<NR, T>()) {
     stage_tables_to_lds<NR, T>(kin_s, tw_s, mask_s, tb.kin, tb.tw, tb.mask);
+    lds_stage(frag_s, ws + (CP == kCpBf16x3 ? a.lay.tmfrag : a.lay.tmfrag_f), StagedTables<NR, T>::frag_bytes);
+    if (tid < StagedTables<NR, T>::x_pad) x_s[tid] = tid < nj ? static_cast<float>(tb.x[tid]) : 0.0f;
     __syncthreads();
   }
 
@@ -682,9 +713,13 @@ void mol_step_kernel(MolArgs a) {
         }
       }
       __syncthreads();
+      // contraction operands: from the LDS copy (complex64 forms) or the workspace
       if constexpr (CP == kCpBf16x3) {
-        coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(ws + a.lay.tmfrag),
-                          tb.x, tb.mudt, E);
+        coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(frag_s),
+                          reinterpret_cast<const float*>(x_s), tb.mudt, E);
+      } else if constexpr (stage_tables<NR, T>()) {
+        coupling_mfma_exact<T, NR>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
+                                   reinterpret_cast<const T*>(x_s), tb.mudt, E);
       } else {
         const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
         coupling_mfma_exact<T, NR>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
@@ -705,7 +740,7 @@ void mol_step_kernel(MolArgs a) {
       constexpr int P0 = (3 * R1) / 4;
       if (a.kmask >= R2 * P0) {
 #pragma unroll
-        for (int p = P0; p < R1; ++p) absorb_point(v[p], mask[q + R2 * p], ab);
+        for (int p = P0; p < R1; ++p) absorb_point_nb(v[p], mask[q + R2 * p], ab);
       } else {
 #pragma unroll
         for (int p = 0; p < R1; ++p) absorb_point(v[p], mask[q + R2 * p], ab);
@@ -780,14 +815,10 @@ int launch_mol_t(const MolArgs& a, hipStream_t s) {
   const size_t shm = lds_table_bytes<NR, T>() +
                      sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
                      16 * 4 * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set && shm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, CP>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(mol_lds_limit()));
-    (void)hipGetLastError();
+  static std::atomic<unsigned long long> lds_set{0};
+  if (shm > 64 * 1024) {
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_step_kernel<T, NR, CP>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
-    attr_set = true;
   }
   hipLaunchKernelGGL((mol_step_kernel<T, NR, CP>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());

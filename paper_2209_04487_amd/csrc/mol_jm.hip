@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   constexpr int NB = 4, L = 2 * NB;
   constexpr int SP = fwd_split<NR, T>(), PH = R1 / SP, NRH = NR / SP;
-  typedef StagedTables<NR, T, true> TBL;
+  typedef StagedTables<NR, T, true, false> TBL;
   constexpr size_t TB = TBL::bytes;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
     constexpr int P0 = (3 * R1) / 4;
     if (a.kmask >= R2 * P0) {
 #pragma unroll
-      for (int p = P0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
+      for (int p = P0; p < R1; ++p) absorb_point_nb(vv[p], mask[q + R2 * p], ab);
     } else {
 #pragma unroll
       for (int p = 0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
 // and the reduction scratch
 template <typename T, int NR>
 constexpr size_t jm_lds_bytes() {
-  return StagedTables<NR, T, true>::bytes +
+  return StagedTables<NR, T, true, false>::bytes +
          sizeof(cx<T>) * static_cast<size_t>(lds_line_start(8, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
          6 * 16 * sizeof(double);
 }
@@ -279,14 +279,10 @@ int launch_jm_t(const MolArgs& a, hipStream_t s) {
   const int threads = 8 * R2;
   const size_t shm = jm_lds_bytes<T, NR>();
   if (shm > mol_lds_limit()) return static_cast<int>(hipErrorInvalidValue);
-  static bool attr_set = false;
-  if (!attr_set && shm > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mol_jm_kernel<T, NR>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(mol_lds_limit()));
-    (void)hipGetLastError();
+  static std::atomic<unsigned long long> lds_set{0};
+  if (shm > 64 * 1024) {
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_jm_kernel<T, NR>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
-    attr_set = true;
   }
   hipLaunchKernelGGL((mol_jm_kernel<T, NR>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());
