@@ -238,17 +238,22 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
 // summed directly (truncation below 1e-18 relative, and no cancellation in
 // 1 - cos); larger angles take an out-of-line path through the library
 // sine/cosine.
-__device__ __noinline__ void sin_vers_large(double a, double* s, double* v) {
-  double c;
-  sincos(a, s, &c);
+// The large-angle path returns by value, so that the outputs of sin_vers
+// never have their address taken (which would put them in scratch memory on
+// the common path too).
+struct SinVers64 { double s, v; };
+struct SinVers32 { float s, v; };
+__device__ __noinline__ SinVers64 sin_vers_large(double a) {
+  double s, c;
+  sincos(a, &s, &c);
   const double h = sin(0.5 * a);
-  *v = 2.0 * h * h;
+  return {s, 2.0 * h * h};
 }
-__device__ __noinline__ void sin_vers_large(float a, float* s, float* v) {
-  float c;
-  sincosf(a, s, &c);
+__device__ __noinline__ SinVers32 sin_vers_large(float a) {
+  float s, c;
+  sincosf(a, &s, &c);
   const float h = sinf(0.5f * a);
-  *v = 2.0f * h * h;
+  return {s, 2.0f * h * h};
 }
 __device__ __forceinline__ void sin_vers(double a, double* s, double* v) {
   if (fabs(a) < 0.03125) {
@@ -267,7 +272,9 @@ __device__ __forceinline__ void sin_vers(double a, double* s, double* v) {
     pc = pc * a2 + 0.5;
     *v = a2 * pc;
   } else {
-    sin_vers_large(a, s, v);
+    const SinVers64 r = sin_vers_large(a);
+    *s = r.s;
+    *v = r.v;
   }
 }
 __device__ __forceinline__ void sin_vers(float a, float* s, float* v) {
@@ -285,7 +292,9 @@ __device__ __forceinline__ void sin_vers(float a, float* s, float* v) {
     pc = pc * a2 + 0.5f;
     *v = a2 * pc;
   } else {
-    sin_vers_large(a, s, v);
+    const SinVers32 r = sin_vers_large(a);
+    *s = r.s;
+    *v = r.v;
   }
 }
 
