@@ -77,6 +77,21 @@ def mol_flops_per_step(cfg):
     return lines * per_line + rot + readout
 
 
+def jm_flops_per_step(n_r):
+    """Algorithmic vector flops of one molecule-step in the (j, m) basis with
+    j <= 1 (four lines per state): four N_r-point complex FFTs per line, the
+    kinetic and the two potential phase multiplies (6 flops per point each),
+    and the closed-form coupling at every r: the two projections <v|g_1>,
+    <v|e_1> (3 complex multiply-adds each, 8 flops), the update of the eight
+    amplitudes (each a complex product with v_b or a scaled copy: 14 flops),
+    and sin/versine with the two quotients (20 flops)."""
+    lines = 8
+    fft = 5 * n_r * int(np.log2(n_r))
+    per_line = 4 * fft + 2 * 6 * n_r + 2 * 6 * n_r
+    coupling = n_r * (2 * 3 * 8 + 8 * 14 + 20)
+    return lines * per_line + coupling
+
+
 def mol_mfma_flops_per_step(cfg):
     """Algorithmic flops of the J->angle and angle->J contractions (a real
     n_j x n_j matrix applied to the complex wavepacket of both states)."""
@@ -232,9 +247,12 @@ def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256):
     precision form, one molecular step per field step."""
     c = cfg.replace(n_mol=n_mol, j_max=1, basis="jm", n_r=n_r)
     out = run_coupled(c, "fp32", steps, warmup, n0)
+    rate = out["n_mol"] * steps / (out["ms"] / 1e3)
     return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= 1, N_r={n_r}, FP32",
-            "ms_per_step": out["ms"] / steps,
-            "molecule_steps_per_s": out["n_mol"] * steps / (out["ms"] / 1e3)}
+            "ms_per_step": out["ms"] / steps, "molecule_steps_per_s": rate,
+            "flops_per_molecule_step": jm_flops_per_step(n_r),
+            "coupled_step_TFLOPs": rate * jm_flops_per_step(n_r) / 1e12,
+            "coupled_step_frac_of_vector_peak": rate * jm_flops_per_step(n_r) / 1e12 / VALU_F32_PEAK_TFLOPS}
 
 
 def run_scale(steps):
