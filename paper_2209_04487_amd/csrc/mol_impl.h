@@ -621,6 +621,8 @@ template <typename T, int NR, int CP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T>::waves)))
 void mol_step_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  static_assert(CP != kCpBf16x3 || stage_tables<NR, T>(),
+                "the BF16 contraction reads its operands from the LDS copy of the tables");
   extern __shared__ __align__(16) unsigned char smem[];
   const int nj = a.nj;
   const int L = 2 * nj;
