@@ -30,6 +30,12 @@ CASES = [
     ("mixed", 128, 4, 6, 3),
     ("mixed", 512, 15, 2, 1),
     ("mixed", 64, 1, 3, 2),
+    # single-step launches take their own kernel instantiation in the
+    # complex64 forms
+    ("mixed", 256, 10, 5, 1),
+    ("fp32", 128, 6, 7, 1),
+    ("fp32", 256, 10, 4, 1),
+    ("mixed", 64, 1, 3, 1),
 ]
 
 
