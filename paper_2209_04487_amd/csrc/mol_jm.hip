@@ -67,7 +67,8 @@ __device__ __forceinline__ void coupling_jm_point(cx<T>* g, cx<T>* e, const cx<T
 template <typename T>
 struct JmOcc { static constexpr int waves = sizeof(T) == 4 ? 3 : 1; };
 
-template <typename T, int NR>
+// ONE: the launch advances exactly one step (as in the m = 0 kernel).
+template <typename T, int NR, bool ONE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::waves))) void mol_jm_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   constexpr int NB = 4, L = 2 * NB;
@@ -133,7 +134,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
   }
 
   double ab = 0.0;
-  for (int step = 0; step < a.n_steps; ++step) {
+  const int n_steps = ONE ? 1 : a.n_steps;
+  for (int step = 0; step < n_steps; ++step) {
     const cx<T>* kin;
     const cx<T>* tw;
     const T* mask;
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
     }
     const double dr = a.dr;
     const double absorbed = a.absorbed[mol] + sm[0] * dr;
-    if (a.n_steps > 0) a.absorbed[mol] = absorbed;
+    if (n_steps > 0) a.absorbed[mol] = absorbed;
     if (a.want_d && a.d_mol) {
       for (int k = 0; k < 3; ++k) a.d_mol[3 * mol + k] = 2.0 * dr * sm[3 + k];
     }
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
     if (!isfinite(sm[1]) || !isfinite(sm[3]) || !isfinite(sm[4]) || !isfinite(sm[5]) || !isfinite(absorbed))
       atomicOr(a.status, 1);
   }
-  if (a.n_steps > 0) {
+  if (n_steps > 0) {
 #pragma unroll
     for (int p = 0; p < R1; ++p) psi[loff + R2 * p] = vv[p];
   }
@@ -273,19 +275,28 @@ constexpr size_t jm_lds_bytes() {
          6 * 16 * sizeof(double);
 }
 
-template <typename T, int NR>
-int launch_jm_t(const MolArgs& a, hipStream_t s) {
+template <typename T, int NR, bool ONE>
+int launch_jm_t1(const MolArgs& a, hipStream_t s) {
   constexpr int R2 = FftShape<NR, T>::R2;
   const int threads = 8 * R2;
   const size_t shm = jm_lds_bytes<T, NR>();
   if (shm > mol_lds_limit()) return static_cast<int>(hipErrorInvalidValue);
   static std::atomic<unsigned long long> lds_set{0};
   if (shm > 64 * 1024) {
-    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_jm_kernel<T, NR>), lds_set);
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_jm_kernel<T, NR, ONE>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
   }
-  hipLaunchKernelGGL((mol_jm_kernel<T, NR>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  hipLaunchKernelGGL((mol_jm_kernel<T, NR, ONE>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());
+}
+
+// complex64: a single-step instantiation for the coupled step's launches
+template <typename T, int NR>
+int launch_jm_t(const MolArgs& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.n_steps == 1) return launch_jm_t1<T, NR, true>(a, s);
+  }
+  return launch_jm_t1<T, NR, false>(a, s);
 }
 
 template <typename T>

@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("prec,n_r,n_mol,n_steps", [("fp64", 128, 7, 3), ("fp64", 256, 3, 2),
                                                     ("fp64", 64, 2, 4), ("fp32", 256, 5, 2),
-                                                    ("mixed", 128, 9, 3)])
+                                                    ("mixed", 128, 9, 3), ("fp32", 256, 5, 1),
+                                                    ("mixed", 128, 9, 1)])
 def test_jm_step_matches_oracle(prec, n_r, n_mol, n_steps):
     from paper_2209_04487_amd import msqd
     cfg = get_config("cfg0", n_r=n_r, j_max=1, basis="jm", n_mol=n_mol)
