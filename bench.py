@@ -564,7 +564,7 @@ def main():
             "frac": achieved_tf / VALU_F32_PEAK_TFLOPS,
             "traffic": None if traffic is None else traffic,
             "traffic_source": traffic_src,
-            "kernel": "mol_step_kernel<float,256,bf16x3>", "kernel_ms": mol_ms,
+            "kernel": "mol_step_kernel<float,256,bf16x3,single-step>", "kernel_ms": mol_ms,
             "flops_per_molecule_step": unit_flops,
             "mfma_flops_per_molecule_step": mol_mfma_flops_per_step(cfg),
             "mfma": {"achieved": mol_mfma_flops_per_step(cfg) * cfg.n_mol / (mol_ms / 1e3) / 1e12,
