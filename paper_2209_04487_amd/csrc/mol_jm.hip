@@ -30,14 +30,62 @@ __device__ __forceinline__ cx<T> cconj_mul(cx<T> a, cx<T> b) {  // conj(a) * b
 template <typename T>
 __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.y, a.x}; }
 
+// The three factors of the closed form at one radial point, x = phi a:
+// vs = 1 - cos x, f = sin(x) / a, wv = (1 - cos x) / a^2.  For small |x| they
+// come from the series of sin(x)/x and (1 - cos x)/x^2 times phi and phi^2,
+// which needs no division and stays finite as the field goes to zero; larger
+// angles use the library sine and the per-molecule reciprocals of a and a^2
+// (a is then far from zero).
+__device__ __forceinline__ void sinc_versc(double x2, double* sc, double* vc) {
+  double ps = 1.0 / 362880.0;
+  ps = ps * x2 - 1.0 / 5040.0;
+  ps = ps * x2 + 1.0 / 120.0;
+  ps = ps * x2 - 1.0 / 6.0;
+  *sc = 1.0 + x2 * ps;
+  double pc = 1.0 / 3628800.0;
+  pc = pc * x2 - 1.0 / 40320.0;
+  pc = pc * x2 + 1.0 / 720.0;
+  pc = pc * x2 - 1.0 / 24.0;
+  *vc = pc * x2 + 0.5;
+}
+__device__ __forceinline__ void sinc_versc(float x2, float* sc, float* vc) {
+  float ps = 1.0f / 362880.0f;
+  ps = ps * x2 - 1.0f / 5040.0f;
+  ps = ps * x2 + 1.0f / 120.0f;
+  ps = ps * x2 - 1.0f / 6.0f;
+  *sc = 1.0f + x2 * ps;
+  float pc = 1.0f / 3628800.0f;
+  pc = pc * x2 - 1.0f / 40320.0f;
+  pc = pc * x2 + 1.0f / 720.0f;
+  pc = pc * x2 - 1.0f / 24.0f;
+  *vc = pc * x2 + 0.5f;
+}
+template <typename T>
+__device__ __forceinline__ void jm_factors(T phi, T a, T inv_a, T inv_a2, T* vs, T* f, T* wv) {
+  const T x = phi * a;
+  const T lim = sizeof(T) == 8 ? T(0.03125) : T(0.125);
+  if (fabs(x) < lim) {
+    T sc, vc;
+    sinc_versc(x * x, &sc, &vc);
+    *f = phi * sc;
+    *wv = (phi * phi) * vc;
+    *vs = (x * x) * vc;
+  } else {
+    T sn, v;
+    sin_vers(x, &sn, &v);
+    *f = sn * inv_a;
+    *wv = v * inv_a2;
+    *vs = v;
+  }
+}
+
 // exp(i phi sigma_x (x) A) at one radial point: g, e hold the four (j, m)
 // amplitudes of each state
 template <typename T>
-__device__ __forceinline__ void coupling_jm_point(cx<T>* g, cx<T>* e, const cx<T>* v, T a, T a2, T phi) {
-  T sn, vs;
-  sin_vers(phi * a, &sn, &vs);               // sin(phi a), 1 - cos(phi a)
-  const T f = a > T(0) ? sn / a : T(0);
-  const T wv = a2 > T(0) ? vs / a2 : T(0);
+__device__ __forceinline__ void coupling_jm_point(cx<T>* g, cx<T>* e, const cx<T>* v, T a, T inv_a, T inv_a2,
+                                                  T phi) {
+  T vs, f, wv;
+  jm_factors(phi, a, inv_a, inv_a2, &vs, &f, &wv);
   cx<T> vg = {T(0), T(0)}, ve = {T(0), T(0)};  // <v|g_1>, <v|e_1>
 #pragma unroll
   for (int b = 1; b < 4; ++b) {
@@ -119,7 +167,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
                       {static_cast<T>(E3[2] * kInvSqrt3), T(0)},
                       {static_cast<T>(-E3[0] * kInvSqrt6), static_cast<T>(E3[1] * kInvSqrt6)}};
   const double a2d = (E3[0] * E3[0] + E3[1] * E3[1] + E3[2] * E3[2]) / 3.0;
-  const T a2 = static_cast<T>(a2d), aa = static_cast<T>(sqrt(a2d));
+  const T aa = static_cast<T>(sqrt(a2d));
+  // reciprocals for the large-angle branch only (|phi a| >= 1/32 there)
+  const T inv_a = a2d > 0.0 ? static_cast<T>(1.0 / sqrt(a2d)) : T(0);
+  const T inv_a2 = a2d > 0.0 ? static_cast<T>(1.0 / a2d) : T(0);
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
   cx<T>* slot = sh + lds_row<NR, T>(line);
@@ -165,7 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JmOcc<T>::w
           g[k] = sh[lds_row<NR, T>(k) + rl];
           e[k] = sh[lds_row<NR, T>(NB + k) + rl];
         }
-        coupling_jm_point(g, e, v, aa, a2, mudt[h * NRH + rl]);
+        coupling_jm_point(g, e, v, aa, inv_a, inv_a2, mudt[h * NRH + rl]);
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
           sh[lds_row<NR, T>(k) + rl] = g[k];

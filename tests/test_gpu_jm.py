@@ -34,6 +34,9 @@ def test_jm_step_matches_oracle(prec, n_r, n_mol, n_steps):
     rng = np.random.default_rng(n_mol)
     E3 = rng.uniform(-0.05, 0.05, (n_mol, 3))
     E3[0] = 0.0                               # a molecule with no field at all
+    E3[1] = [1e-30, 0.0, 0.0]                 # a vanishing field (series branch, no division)
+    if n_mol > 2:
+        E3[2] = [0.3, -0.2, 0.25]             # a strong field (large-angle branch in every form)
     mols.step(torch.as_tensor(E3, device="cuda"), n_steps=n_steps)
     d, nrm, yld = mols.readout()
     torch.cuda.synchronize()
