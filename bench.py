@@ -444,6 +444,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 timing and comparison")
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the 700,000-molecule and adjoint measurements")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the differentiation workload (400 forward + reverse steps) and its "
+                         "forward-only timing, for a kernel trace of the adjoint")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
@@ -462,6 +465,13 @@ def main():
     cfg64 = get_config("cfg1")
     K, W = args.steps, args.warmup
     n0 = default_first_step(cfg) if args.n0 is None else args.n0
+    if args.adjoint_only:
+        adj = run_adjoint(400)
+        cfg3 = get_config("cfg3")
+        fwd = run_coupled(cfg3, "fp32", 200, 20, default_first_step(cfg3))
+        adj["forward_ms_per_step"] = fwd["ms"] / 200
+        print(json.dumps(adj))
+        return
     if args.kernel == "stencil":
         ms = time_stencil(cfg, "mixed", K)
         cells = cfg.nx * cfg.ny * cfg.nz
