@@ -13,102 +13,120 @@
 namespace msqd {
 
 // ------------------------------------------------------------ molecules
-// Adjoint of the coupling at one radial point.  A holds chi (the coupling's
-// input), B holds the adjoint at its output and receives the adjoint at its
-// input.  Phi = T chi, Phi' = R(phi) Phi; Lambda = T lambda_out;
-// dY/dE += sum_k mu12 x_k dt * (-Im[conj(L_g) Phi'_e + conj(L_e) Phi'_g]);
-// lambda_in = T^T R(-phi) Lambda.
-template <typename T>
-__device__ __forceinline__ double coupling_point_adj(const cx<T>* A, cx<T>* B, int LS, int r, int nj,
-                                                     const T* __restrict__ tm, const T* __restrict__ x,
-                                                     T md) {
-  cx<T> ag[kMaxNJ], ae[kMaxNJ];
+// The coupling and its adjoint on the matrix cores, in the working
+// precision (16x16x4 instructions, as the forward FP32 and FP64 forms), one
+// wavefront per tile of 16 radial points.  A holds chi (the coupling's input)
+// and B, on entry, the adjoint at its output; lane l works on radial point
+// l%16 and the J (or node) rows MfmaK4<T>::row(l/16, i).  frag: [2][64][4],
+// block 0 T and block 1 T^T in operand order, zero outside nj; x: the nodes.
+//
+// Forward (segment recompute): B = T^T R(phi) T A.
+// Adjoint: Phi = T chi, Phi' = R(phi) Phi, Lambda = T lambda_out;
+//   dY/dE += sum_{k,r} mu12(r) x_k dt (-Im[conj(L_g) Phi'_e + conj(L_e) Phi'_g]);
+//   lambda_in = T^T R(-phi) Lambda -> B.
+// Returns this lane's share of dY/dE (zero for the forward).
+template <typename T, int NR, bool ADJ>
+__device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, int LS, int nj,
+                                                    const T* __restrict__ frag, const T* __restrict__ x,
+                                                    const T* __restrict__ mudt, T E) {
+  typedef typename MfmaK4<T>::acc acc_t;
+  const int lane = fresh_lane();
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int nwaves = (blockDim.x + 63) >> 6;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  T Tf[4], Tt[4], xk[4];
+  int rows[4];
 #pragma unroll
-  for (int J = 0; J < kMaxNJ; ++J) {
-    ag[J] = {T(0), T(0)};
-    ae[J] = {T(0), T(0)};
+  for (int i = 0; i < 4; ++i) {
+    rows[i] = MfmaK4<T>::row(grp, i);
+    Tf[i] = frag[(0 * 64 + lane) * 4 + i];
+    Tt[i] = frag[(1 * 64 + lane) * 4 + i];
+    xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
   }
   double grad = 0.0;
-  for (int k = 0; k < nj; ++k) {
-    cx<T> Lg = {T(0), T(0)}, Le = {T(0), T(0)}, Pg = {T(0), T(0)}, Pe = {T(0), T(0)};
-    for (int J = 0; J < nj; ++J) {
-      const T t = tm[k * nj + J];
-      Lg = Lg + cscale(B[J * LS + r], t);
-      Le = Le + cscale(B[(nj + J) * LS + r], t);
-      Pg = Pg + cscale(A[J * LS + r], t);
-      Pe = Pe + cscale(A[(nj + J) * LS + r], t);
-    }
-    T sn, vs;
-    sin_vers(md * x[k], &sn, &vs);
-    const T c = T(1) - vs;
-    // Phi' = R(phi) Phi
-    const cx<T> Qg = {c * Pg.x - sn * Pe.y, c * Pg.y + sn * Pe.x};
-    const cx<T> Qe = {c * Pe.x - sn * Pg.y, c * Pe.y + sn * Pg.x};
-    // -Im[conj(L_g) Q_e + conj(L_e) Q_g]
-    const double im = static_cast<double>(Lg.x * Qe.y - Lg.y * Qe.x) +
-                      static_cast<double>(Le.x * Qg.y - Le.y * Qg.x);
-    grad -= static_cast<double>(x[k]) * im;
-    // R(-phi) Lambda: [c L_g - i s L_e, -i s L_g + c L_e]
-    const cx<T> Rg = {c * Lg.x + sn * Le.y, c * Lg.y - sn * Le.x};
-    const cx<T> Re = {c * Le.x + sn * Lg.y, c * Le.y - sn * Lg.x};
+  const acc_t z = {T(0), T(0), T(0), T(0)};
+#pragma unroll 1
+  for (int tile = wave; tile * 16 < NR; tile += nwaves) {
+    const int r = tile * 16 + col;
+    // chi (and lambda_out) rows of this lane at radial point r
+    acc_t agr, agi, aer, aei, bgr, bgi, ber, bei;
 #pragma unroll
-    for (int J = 0; J < kMaxNJ; ++J) {
+    for (int i = 0; i < 4; ++i) {
+      const int J = rows[i];
+      cx<T> g = {T(0), T(0)}, e = {T(0), T(0)}, lg = {T(0), T(0)}, le = {T(0), T(0)};
       if (J < nj) {
-        const T t = tm[k * nj + J];
-        ag[J] = ag[J] + cscale(Rg, t);
-        ae[J] = ae[J] + cscale(Re, t);
+        g = A[J * LS + r];
+        e = A[(nj + J) * LS + r];
+        if constexpr (ADJ) {
+          lg = B[J * LS + r];
+          le = B[(nj + J) * LS + r];
+        }
+      }
+      agr[i] = g.x; agi[i] = g.y; aer[i] = e.x; aei[i] = e.y;
+      bgr[i] = lg.x; bgi[i] = lg.y; ber[i] = le.x; bei[i] = le.y;
+    }
+    acc_t Pgr = z, Pgi = z, Per = z, Pei = z, Lgr = z, Lgi = z, Ler = z, Lei = z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Pgr = MfmaK4<T>::mma(Tf[i], agr[i], Pgr);
+      Pgi = MfmaK4<T>::mma(Tf[i], agi[i], Pgi);
+      Per = MfmaK4<T>::mma(Tf[i], aer[i], Per);
+      Pei = MfmaK4<T>::mma(Tf[i], aei[i], Pei);
+      if constexpr (ADJ) {
+        Lgr = MfmaK4<T>::mma(Tf[i], bgr[i], Lgr);
+        Lgi = MfmaK4<T>::mma(Tf[i], bgi[i], Lgi);
+        Ler = MfmaK4<T>::mma(Tf[i], ber[i], Ler);
+        Lei = MfmaK4<T>::mma(Tf[i], bei[i], Lei);
       }
     }
-  }
+    MfmaK4<T>::settle(Pgr, Pgi, Per, Pei);
+    if constexpr (ADJ) MfmaK4<T>::settle(Lgr, Lgi, Ler, Lei);
+    const T md = mudt[r] * E;
+    double gl = 0.0;
+    acc_t Ogr, Ogi, Oer, Oei;   // the operand of the T^T product
 #pragma unroll
-  for (int J = 0; J < kMaxNJ; ++J) {
-    if (J < nj) {
-      B[J * LS + r] = ag[J];
-      B[(nj + J) * LS + r] = ae[J];
+    for (int i = 0; i < 4; ++i) {
+      T sn, vs;
+      sin_vers(md * xk[i], &sn, &vs);
+      const T c = T(1) - vs;
+      // Phi' = R(phi) Phi: [c Pg + i s Pe, i s Pg + c Pe]
+      const T qgr = c * Pgr[i] - sn * Pei[i], qgi = c * Pgi[i] + sn * Per[i];
+      const T qer = c * Per[i] - sn * Pgi[i], qei = c * Pei[i] + sn * Pgr[i];
+      if constexpr (ADJ) {
+        // -Im[conj(L_g) Q_e + conj(L_e) Q_g]
+        const double im = static_cast<double>(Lgr[i] * qei - Lgi[i] * qer) +
+                          static_cast<double>(Ler[i] * qgi - Lei[i] * qgr);
+        gl -= static_cast<double>(xk[i]) * im;
+        // R(-phi) Lambda: [c L_g - i s L_e, -i s L_g + c L_e]
+        Ogr[i] = c * Lgr[i] + sn * Lei[i];
+        Ogi[i] = c * Lgi[i] - sn * Ler[i];
+        Oer[i] = c * Ler[i] + sn * Lgi[i];
+        Oei[i] = c * Lei[i] - sn * Lgr[i];
+      } else {
+        Ogr[i] = qgr; Ogi[i] = qgi; Oer[i] = qer; Oei[i] = qei;
+      }
+    }
+    if constexpr (ADJ) grad += static_cast<double>(mudt[r]) * gl;
+    acc_t cgr = z, cgi = z, cer = z, cei = z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cgr = MfmaK4<T>::mma(Tt[i], Ogr[i], cgr);
+      cgi = MfmaK4<T>::mma(Tt[i], Ogi[i], cgi);
+      cer = MfmaK4<T>::mma(Tt[i], Oer[i], cer);
+      cei = MfmaK4<T>::mma(Tt[i], Oei[i], cei);
+    }
+    MfmaK4<T>::settle(cgr, cgi, cer, cei);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = rows[i];
+      if (J < nj) {
+        B[J * LS + r] = {cgr[i], cgi[i]};
+        B[(nj + J) * LS + r] = {cer[i], cei[i]};
+      }
     }
   }
   return grad;
-}
-
-// forward coupling (full form, VALU) from A into B, used by the recompute
-template <typename T>
-__device__ __forceinline__ void coupling_point_fwd(const cx<T>* A, cx<T>* B, int LS, int r, int nj,
-                                                   const T* __restrict__ tm, const T* __restrict__ x,
-                                                   T md) {
-  cx<T> ag[kMaxNJ], ae[kMaxNJ];
-#pragma unroll
-  for (int J = 0; J < kMaxNJ; ++J) {
-    ag[J] = {T(0), T(0)};
-    ae[J] = {T(0), T(0)};
-  }
-  for (int k = 0; k < nj; ++k) {
-    cx<T> Pg = {T(0), T(0)}, Pe = {T(0), T(0)};
-    for (int J = 0; J < nj; ++J) {
-      const T t = tm[k * nj + J];
-      Pg = Pg + cscale(A[J * LS + r], t);
-      Pe = Pe + cscale(A[(nj + J) * LS + r], t);
-    }
-    T sn, vs;
-    sin_vers(md * x[k], &sn, &vs);
-    const T c = T(1) - vs;
-    const cx<T> Qg = {c * Pg.x - sn * Pe.y, c * Pg.y + sn * Pe.x};
-    const cx<T> Qe = {c * Pe.x - sn * Pg.y, c * Pe.y + sn * Pg.x};
-#pragma unroll
-    for (int J = 0; J < kMaxNJ; ++J) {
-      if (J < nj) {
-        const T t = tm[k * nj + J];
-        ag[J] = ag[J] + cscale(Qg, t);
-        ae[J] = ae[J] + cscale(Qe, t);
-      }
-    }
-  }
-#pragma unroll
-  for (int J = 0; J < kMaxNJ; ++J) {
-    if (J < nj) {
-      B[J * LS + r] = ag[J];
-      B[(nj + J) * LS + r] = ae[J];
-    }
-  }
 }
 
 template <typename T, int NR>
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   const cx<T>* kin = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.kin_d : a.lay.kin_f));
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.tw_d : a.lay.tw_f));
   const cx<T>* vph = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.vph_d : a.lay.vph_f));
-  const T* tm = reinterpret_cast<const T*>(ws + (dbl ? a.lay.tm_d : a.lay.tm_f));
+  const T* frag = reinterpret_cast<const T*>(ws + (dbl ? a.lay.tmfrag_d : a.lay.tmfrag_f));
   const T* xk = reinterpret_cast<const T*>(ws + (dbl ? a.lay.x_d : a.lay.x_f));
   const T* mudt = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mudt_d : a.lay.mudt_f));
   const T* mask = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mask_d : a.lay.mask_f));
@@ -159,7 +177,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
     for (int p = 0; p < R1; ++p) A[line * LS + q + R2 * p] = phase_mul(v[p], vph[loff + R2 * p]);
   }
   __syncthreads();
-  for (int r = tid; r < NR; r += nthr) coupling_point_fwd<T>(A, B, LS, r, nj, tm, xk, mudt[r] * E);
+  coupling_adj_mfma<T, NR, false>(A, B, LS, nj, frag, xk, mudt, E);
   __syncthreads();
   if (active) {
 #pragma unroll
@@ -204,9 +222,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
     for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = phase_mul_conj(lam[p], vph[loff + R2 * p]);
   }
   __syncthreads();
-  double grad = 0.0;
-  for (int r = tid; r < NR; r += nthr)
-    grad += static_cast<double>(mudt[r]) * coupling_point_adj<T>(A, B, LS, r, nj, tm, xk, mudt[r] * E);
+  const double grad = coupling_adj_mfma<T, NR, true>(A, B, LS, nj, frag, xk, mudt, E);
   __syncthreads();
   if (active) {
 #pragma unroll
