@@ -92,6 +92,17 @@ def jm_flops_per_step(n_r):
     return lines * per_line + coupling
 
 
+def jm_bytes_per_step(n_r):
+    """Algorithmic HBM bytes of one (j, m) molecule-step: the eight lines read
+    and written once (complex64), the three field components, the dipole
+    vector and the absorbed accumulator (read + write)."""
+    return 2 * 8 * n_r * 8 + 3 * 8 + 3 * 8 + 16
+
+
+def jm_config(cfg, n_mol=691_200, n_r=256):
+    return cfg.replace(n_mol=n_mol, j_max=1, basis="jm", n_r=n_r)
+
+
 def mol_mfma_flops_per_step(cfg):
     """Algorithmic flops of the J->angle and angle->J contractions (a real
     n_j x n_j matrix applied to the complex wavepacket of both states)."""
@@ -245,14 +256,20 @@ def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256):
     """The paper's own molecular model: all (j, m) with j <= 1 and all three
     field components, 691,200 molecules in the SRR slab (the paper's count),
     precision form, one molecular step per field step."""
-    c = cfg.replace(n_mol=n_mol, j_max=1, basis="jm", n_r=n_r)
+    c = jm_config(cfg, n_mol, n_r)
     out = run_coupled(c, "fp32", steps, warmup, n0)
     rate = out["n_mol"] * steps / (out["ms"] / 1e3)
+    kms = time_mol_kernel(c, "fp32", 10)
+    kt = jm_flops_per_step(n_r) * n_mol / (kms / 1e3) / 1e12
+    kb = jm_bytes_per_step(n_r) * n_mol / (kms / 1e3) / 1e9
     return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= 1, N_r={n_r}, FP32",
             "ms_per_step": out["ms"] / steps, "molecule_steps_per_s": rate,
             "flops_per_molecule_step": jm_flops_per_step(n_r),
             "coupled_step_TFLOPs": rate * jm_flops_per_step(n_r) / 1e12,
-            "coupled_step_frac_of_vector_peak": rate * jm_flops_per_step(n_r) / 1e12 / VALU_F32_PEAK_TFLOPS}
+            "coupled_step_frac_of_vector_peak": rate * jm_flops_per_step(n_r) / 1e12 / VALU_F32_PEAK_TFLOPS,
+            "kernel": "mol_jm_kernel<float,256,single-step>", "kernel_ms": kms,
+            "kernel_TFLOPs": kt, "kernel_frac_of_vector_peak": kt / VALU_F32_PEAK_TFLOPS,
+            "kernel_GBs": kb, "kernel_frac_of_hbm": kb / HBM_PEAK_GBS}
 
 
 def run_scale(steps):
@@ -334,7 +351,8 @@ def time_mol_kernel(cfg, prec, launches):
 
     from paper_2209_04487_amd import msqd
     mols = msqd.Molecules.from_config(cfg, prec=prec)
-    E = torch.full((mols.desc.n_mol,), 1e-4, dtype=torch.float64, device="cuda")
+    shape = (mols.desc.n_mol, 3) if cfg.basis == "jm" else (mols.desc.n_mol,)
+    E = torch.full(shape, 1e-4, dtype=torch.float64, device="cuda")
     for _ in range(3):
         mols.step(E)
     stream = torch.cuda.current_stream()
@@ -447,7 +465,7 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload (400 forward + reverse steps) and its "
                          "forward-only timing, for a kernel trace of the adjoint")
-    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil"], default=None,
+    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
     args = ap.parse_args()
@@ -479,6 +497,15 @@ def main():
         calibration_copy()
         print(json.dumps({"kernel": "stencil", "launches": K, "ms": ms, "cells": cells,
                           "GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "calibration_copy_bytes": 1 << 30}))
+        return
+    if args.kernel == "jm":
+        c = jm_config(cfg)
+        ms = time_mol_kernel(c, "fp32", K)
+        calibration_copy()
+        print(json.dumps({"kernel": "jm", "launches": K, "ms": ms, "n_mol": c.n_mol,
+                          "GBs": jm_bytes_per_step(c.n_r) * c.n_mol / (ms / 1e3) / 1e9,
+                          "TFLOPs": jm_flops_per_step(c.n_r) * c.n_mol / (ms / 1e3) / 1e12,
                           "calibration_copy_bytes": 1 << 30}))
         return
     if args.kernel:

@@ -43,7 +43,6 @@ QdLayout qd_layout(int n_r, int nj) {
   L.kin_d = take(16 * nr);
   L.tw_d = take(16 * 32 * 32);
   L.vph_d = take(16 * 2 * J * nr);
-  L.tm_d = take(8 * J * J);
   L.x_d = take(8 * J);
   L.mudt_d = take(8 * nr);
   L.mask_d = take(8 * nr);
@@ -52,7 +51,6 @@ QdLayout qd_layout(int n_r, int nj) {
   L.kin_f = take(8 * nr);
   L.tw_f = take(8 * 32 * 32);
   L.vph_f = take(8 * 2 * J * nr);
-  L.tm_f = take(4 * J * J);
   L.x_f = take(4 * J);
   L.mudt_f = take(4 * nr);
   L.mask_f = take(4 * nr);
@@ -342,7 +340,6 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   put(L.kin_d, t.kin.data(), 16 * nr);
   put(L.tw_d, t.tw.data(), 16 * t.tw.size());
   put(L.vph_d, t.vph.data(), 16 * t.vph.size());
-  put(L.tm_d, t.tm.data(), 8 * t.tm.size());
   put(L.x_d, t.x.data(), 8 * nj);
   put(L.mudt_d, t.mudt.data(), 8 * nr);
   put(L.mask_d, t.mask.data(), 8 * nr);
@@ -367,7 +364,6 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   put_lift(L.kin_f, t.kin, static_cast<double>(nr));
   put_unit(L.tw_f, t.tw_f);
   put_lift(L.vph_f, t.vph, 1.0);
-  putf(L.tm_f, t.tm);
   putf(L.x_f, t.x);
   putf(L.mudt_f, t.mudt);
   putf(L.mask_f, t.mask);

@@ -19,13 +19,12 @@ struct QdLayout {
   size_t kin_d;       // cx<double> [n_r]  exp(-i k^2 dt / 4mu) / n_r, frequency order
   size_t tw_d;        // cx<double> [n_r]  exp(-2 pi i j / n_r)
   size_t vph_d;       // cx<double> [2][nj][n_r]
-  size_t tm_d;        // double [nj][nj]  T[k][J]
   size_t x_d;         // double [nj]      Gauss-Legendre nodes (ascending)
   size_t mudt_d;      // double [n_r]     mu12(r) dt
   size_t mask_d;      // double [n_r]
   size_t mu_d;        // double [n_r]     mu12(r) (readout)
   size_t cj_d;        // double [nj]      <J|cos|J+1>
-  size_t kin_f, tw_f, vph_f, tm_f, x_f, mudt_f, mask_f;   // float versions
+  size_t kin_f, tw_f, vph_f, x_f, mudt_f, mask_f;   // float versions
   size_t tmfrag;      // bf16 matrix-core fragments of T and T^T (hi, lo)
   size_t tmfrag_d;    // double [2][64][4] matrix-core fragments of T and T^T
   size_t tmfrag_f;    // float  [2][64][4]

@@ -166,7 +166,6 @@ struct MolTabs {
   const cx<T>* kin;
   const cx<T>* tw;
   const cx<T>* vph;
-  const T* tm;
   const T* x;
   const T* mudt;
   const T* mask;
@@ -298,13 +297,6 @@ __device__ __forceinline__ void sin_vers(float a, float* s, float* v) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void rotate(cx<T>& g, cx<T>& e, T c, T s) {
-  // [g, e] <- [c g + i s e, i s g + c e]
-  const cx<T> g0 = g, e0 = e;
-  g = {c * g0.x - s * e0.y, c * g0.y + s * e0.x};
-  e = {c * e0.x - s * g0.y, c * e0.y + s * g0.x};
-}
 
 // ----------------------------------------------- C(E) on the matrix cores
 // Mixed form: psi += T^T (R - I) T psi over the J axis, per radial point, as
@@ -583,8 +575,6 @@ __device__ __forceinline__ void block_sum4(double* v, double* red) {
   __syncthreads();
 }
 
-template <typename T>
-__device__ __forceinline__ bool finite_t(T v) { return isfinite(v); }
 
 // Absorber mask at one point: the removed probability is accumulated in
 // FP64.  absorb_point_nb is the same without the branch (bit-identical: m = 1
@@ -652,7 +642,6 @@ void mol_step_kernel(MolArgs a) {
     tb.kin = reinterpret_cast<const cx<T>*>(ws + a.lay.kin_d);
     tb.tw = reinterpret_cast<const cx<T>*>(ws + a.lay.tw_d);
     tb.vph = reinterpret_cast<const cx<T>*>(ws + a.lay.vph_d);
-    tb.tm = reinterpret_cast<const T*>(ws + a.lay.tm_d);
     tb.x = reinterpret_cast<const T*>(ws + a.lay.x_d);
     tb.mudt = reinterpret_cast<const T*>(ws + a.lay.mudt_d);
     tb.mask = reinterpret_cast<const T*>(ws + a.lay.mask_d);
@@ -660,7 +649,6 @@ void mol_step_kernel(MolArgs a) {
     tb.kin = reinterpret_cast<const cx<T>*>(ws + a.lay.kin_f);
     tb.tw = reinterpret_cast<const cx<T>*>(ws + a.lay.tw_f);
     tb.vph = reinterpret_cast<const cx<T>*>(ws + a.lay.vph_f);
-    tb.tm = reinterpret_cast<const T*>(ws + a.lay.tm_f);
     tb.x = reinterpret_cast<const T*>(ws + a.lay.x_f);
     tb.mudt = reinterpret_cast<const T*>(ws + a.lay.mudt_f);
     tb.mask = reinterpret_cast<const T*>(ws + a.lay.mask_f);
