@@ -470,7 +470,7 @@ def main():
                          "followed by a 1 GiB calibration copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(see the sharding design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
