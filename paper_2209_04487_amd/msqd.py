@@ -319,7 +319,9 @@ class Molecules:
 
 def excited_r(mols):
     """Eq. (8) readout of a Molecules batch: (per-molecule <R>_e numerators,
-    excited populations, ensemble <R>_e) as device tensors."""
+    excited populations, ensemble <R>_e) as device tensors.  The ensemble
+    value is the ratio of the two sums, so it is NaN while the excited
+    population is exactly zero."""
     n = max(mols.desc.n_mol, 1)
     dev = mols.psi.device
     num = torch.empty(n, dtype=torch.float64, device=dev)

@@ -2,7 +2,8 @@
 times.
 
 - molecular step with 100,000 molecules (N_r = 256, J <= 10) in the FP64 and
-  precision forms: a seeded sample of molecules compared element by element
+  precision forms, and with the 700,000 molecules of the nanohole workload
+  (precision form): a seeded sample of molecules compared element by element
   with the oracle stepping the same molecules under the same seeded fields;
 - field solver on the full 192 x 192 x 120 SRR grid (FP64): every E and H
   component after 40, 120 and 240 steps against the oracle;
@@ -35,7 +36,7 @@ E_AU = 5.14220674763e11
 EA0 = 8.4783536255e-30
 
 
-@pytest.mark.parametrize("name,prec", [("cfg1", "fp64"), ("cfg2", "mixed")])
+@pytest.mark.parametrize("name,prec", [("cfg1", "fp64"), ("cfg2", "mixed"), ("cfg4", "mixed")])
 def test_full_batch_sampled_molecules(name, prec):
     from paper_2209_04487_amd import msqd
     cfg = get_config(name)
