@@ -2,8 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The reference for the hand-written adjoint: the dissociated population at
-the end of the run, Y = mean_i [sum_{r > r_diss} |psi_i|^2 dr + absorbed_i],
+The reference for the hand-written adjoint.  The differentiated run is the
+coupled step of Eqs. (1)-(5) as in oracle.coupled; the objective is the
+dissociated population studied in the paper's application section on
+collective dissociation near plasmonic interfaces, at the end of the run, Y = mean_i [sum_{r > r_diss} |psi_i|^2 dr + absorbed_i],
 and its derivative along a direction of the incident-field samples,
 dY = sum_n (dY/dsrc[n]) dsrc[n], propagated forward alongside the state.
 
