@@ -157,6 +157,14 @@ def stencil_bytes_per_cell(prec):
     return 18 * w + 3
 
 
+def stencil_min_bytes_per_cell(prec):
+    """The least a whole field step must move per cell: E and H each read
+    once and written once (12 words) and the material ids (3 B), as a single
+    fused H + E sweep would; the two-kernel split moves 18 words."""
+    w = 8 if prec == "fp64" else 4
+    return 12 * w + 3
+
+
 def run_coupled(cfg, prec, steps, warmup, n0, mol_every=1):
     """Time `steps` coupled steps (after `warmup` untimed ones) with HIP
     events on the stream the steps are launched on."""
@@ -615,7 +623,10 @@ def main():
                     "algorithmic_bytes_per_launch": unit_bytes * cfg.n_mol},
         },
         "stencil": {"ms_per_step": sten_ms, "cell_updates_per_s": cells / (sten_ms / 1e3),
-                    "achieved_GBs": sten_gbs, "frac": sten_gbs / HBM_PEAK_GBS},
+                    "achieved_GBs": sten_gbs, "frac": sten_gbs / HBM_PEAK_GBS,
+                    "bytes_per_cell": stencil_bytes_per_cell("mixed"),
+                    "frac_vs_fused_minimum": stencil_min_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
+                    / HBM_PEAK_GBS},
         "fp64": None if fp64 is None else {
             "value": fp64["n_mol"] * K / (fp64["ms"] / 1e3), "ms_per_step": fp64["ms"] / K,
             "mol_kernel_ms": mol64_ms},
