@@ -77,12 +77,23 @@ typedef struct {
   int32_t basis;          /* MSQD_BASIS_M0: J lines with m = 0, the field
                              along the quantisation axis (E_mol, d_mol: one
                              value per molecule); MSQD_BASIS_JM: all
-                             (j, m) with j <= j_max <= 1, all three field
-                             components (E_mol, d_mol: [n_mol][3] = x, y, z),
-                             psi lines ordered b = j^2 + m + j             */
+                             (j, m) with j <= j_max, 1 <= j_max <= 5, all
+                             three field components (E_mol, d_mol:
+                             [n_mol][3] = x, y, z), psi lines ordered
+                             b = j^2 + m + j.  One workgroup holds a
+                             molecule: 2 (j_max+1)^2 lines of n_r/R1 lanes
+                             (R1 = 32 for complex64 at n_r >= 256, 16 for
+                             complex128 at n_r = 256 and for n_r = 128, 8 at
+                             n_r = 64) must stay within 1024 threads and
+                             160 KB of LDS, else MSQD_EUNSUP (e.g. complex128
+                             at n_r = 256 takes j_max <= 3)                 */
 } qd_desc;
 
-/* Bytes of device workspace (tables and a status word) for qd_* calls. */
+/* Bytes of device workspace (tables and a status word) for qd_* calls; 0
+ * (with the message) for an invalid or unsupported descriptor.  With
+ * basis = MSQD_BASIS_JM and j_max >= 2 it includes the tables of the
+ * general coupling (the Wigner-rotation eigenvectors of J_x, the per-m'
+ * eigen-decompositions of cos(theta) and the dipole matrix elements). */
 size_t qd_workspace_bytes(const qd_desc* d);
 
 /* Build the split-operator tables (Eq. (5) phases on the grid, the
@@ -104,8 +115,11 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
  * NULL.
  * With basis = MSQD_BASIS_JM: E_mol is [n_mol][3] (E_x, E_y, E_z) and d_mol
  * [n_mol][3], the dipole <mu12 d_c sigma_x> along x, y, z; the coupling is
- * exp(i mu12 dt sigma_x (x) sum_c E_c D_c) on the j <= 1 basis, D_c the
- * direction cosines of the molecular axis (Eq. (3) with all m). */
+ * exp(i mu12 dt sigma_x (x) sum_c E_c D_c), exact on the truncated basis,
+ * D_c the direction cosines of the molecular axis (Eq. (3) with all m):
+ * a closed form for j_max = 1; for j_max >= 2 the rotation of the field
+ * direction onto z, per-m' Gauss transforms of cos(theta), the 2x2 rotation
+ * of each eigenvector's (g, e) pair and the way back. */
 int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
             double* absorbed, double* d_mol, int32_t n_steps, void* stream);
 

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libmsqd.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "host_tables.cpp", "fdtd.hip", "mol_fp64.hip", "mol_fp32.hip",
-           "mol_mixed.hip", "adjoint.hip", "bloch.hip", "readout.hip", "mol_jm.hip"]
+           "mol_mixed.hip", "adjoint.hip", "bloch.hip", "readout.hip", "mol_jm.hip",
+           "mol_jmg_fp32.hip", "mol_jmg_fp64.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

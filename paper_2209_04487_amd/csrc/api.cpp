@@ -12,6 +12,7 @@
 #include "fdtd.h"
 #include "host_tables.h"
 #include "mol.h"
+#include "mol_jmg.h"
 
 namespace msqd {
 
@@ -149,8 +150,16 @@ static int check_qd(const qd_desc* d) {
     return fail(MSQD_EPREC, "unknown precision");
   if (!(d->r_max > d->r_min) || !(d->r_min > 0.0)) return fail(MSQD_EINVAL, "need 0 < r_min < r_max");
   if (d->basis != MSQD_BASIS_M0 && d->basis != MSQD_BASIS_JM) return fail(MSQD_EINVAL, "unknown basis");
-  if (d->basis == MSQD_BASIS_JM && d->j_max != 1)
-    return fail(MSQD_EUNSUP, "the (j, m) basis is provided for j_max = 1");
+  if (d->basis == MSQD_BASIS_JM) {
+    if (d->j_max < 1 || d->j_max > kJmgMax)
+      return fail(MSQD_EUNSUP, "the (j, m) basis is provided for 1 <= j_max <= " + std::to_string(kJmgMax));
+    size_t lds = 0;
+    if (d->j_max >= 2 && !jmg_supported(d->n_r, d->prec != MSQD_FP64, d->j_max, &lds))
+      return fail(MSQD_EUNSUP, "(j, m) basis: n_r x (j_max+1)^2 too large for one workgroup in this precision (" +
+                                   std::to_string(lds) + " bytes of LDS, " +
+                                   std::to_string(qd_lines(d) * (d->n_r / fft_r1(d->n_r, d->prec == MSQD_FP64 ? 8 : 4))) +
+                                   " threads)");
+  }
   if (!(d->mass_au > 0.0) || !(d->dt_au > 0.0)) return fail(MSQD_EINVAL, "mass and dt must be > 0");
   if (d->absorb_width_au < 0.0 || d->absorb_width_au > d->r_max - d->r_min)
     return fail(MSQD_EINVAL, "absorber width outside the box");
@@ -268,7 +277,8 @@ static int launch_mol(const qd_desc* d, const MolArgs& a, hipStream_t s) {
   int e = 0;
   if (a.n_mol == 0) return MSQD_OK;
   if (d->basis == MSQD_BASIS_JM) {
-    e = launch_mol_jm(a, d->n_r, d->prec != MSQD_FP64, s);
+    e = d->j_max == 1 ? launch_mol_jm(a, d->n_r, d->prec != MSQD_FP64, s)
+                      : launch_mol_jmg(a, d->n_r, d->prec != MSQD_FP64, d->j_max, s);
     if (e != 0) return check_hip(static_cast<hipError_t>(e), "(j, m) molecule step launch");
     return MSQD_OK;
   }
@@ -311,9 +321,14 @@ extern "C" {
 const char* msqd_last_error(void) { return g_err.c_str(); }
 int msqd_version(void) { return 100; }
 
+// bytes of the general (j, m) coupling tables after the common ones
+static size_t qd_jmg_bytes(const qd_desc* d) {
+  return (d->basis == MSQD_BASIS_JM && d->j_max >= 2) ? 8 * static_cast<size_t>(jmg_tab(d->j_max).n) : 0;
+}
+
 size_t qd_workspace_bytes(const qd_desc* d) {
   if (check_qd(d) != MSQD_OK) return 0;
-  return qd_layout(d->n_r, d->j_max + 1).total;
+  return qd_layout(d->n_r, d->j_max + 1).total + qd_jmg_bytes(d);
 }
 
 int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double* mu12,
@@ -324,7 +339,8 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   if (!U_g || !U_e || !mu12 || !psi0) return fail(MSQD_EINVAL, "host table pointer is NULL");
   if (!ws || !aligned16(ws)) return fail(MSQD_EINVAL, "workspace NULL or misaligned");
   const QdLayout L = qd_layout(d->n_r, d->j_max + 1);
-  if (ws_bytes < L.total) return fail(MSQD_ESHAPE, "workspace too small");
+  const size_t ws_need = L.total + qd_jmg_bytes(d);
+  if (ws_bytes < ws_need) return fail(MSQD_ESHAPE, "workspace too small");
   if (d->n_mol > 0 && (!psi || !aligned16(psi) || !absorbed))
     return fail(MSQD_EINVAL, "psi / absorbed NULL or misaligned");
   for (int k = 0; k < d->n_r; ++k)
@@ -333,9 +349,11 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   const MolTablesHost t = build_mol_tables(*d, U_g, U_e, mu12);
-  std::vector<unsigned char> host(L.total, 0);
+  std::vector<unsigned char> host(ws_need, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) { std::memcpy(host.data() + off, src, bytes); };
   const int nr = d->n_r, nj = d->j_max + 1;
+  if (qd_jmg_bytes(d) > 0 && !fill_jmg_tables(d->j_max, reinterpret_cast<double*>(host.data() + L.total)))
+    return fail(MSQD_EDEVICE, "(j, m) coupling tables: eigen-decomposition did not converge");
   put(L.psi0, psi0, 8 * nr);
   put(L.kin_d, t.kin.data(), 16 * nr);
   put(L.tw_d, t.tw.data(), 16 * t.tw.size());
@@ -385,7 +403,7 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
       }
   }
 
-  MSQD_HIP(hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s));
+  MSQD_HIP(hipMemcpyAsync(ws, host.data(), ws_need, hipMemcpyHostToDevice, s));
   if (d->n_mol > 0) {
     const int lines = qd_lines(d);
     const size_t total = static_cast<size_t>(lines) * nr * d->n_mol;

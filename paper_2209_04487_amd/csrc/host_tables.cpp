@@ -2,6 +2,8 @@
 // maps.  Everything here runs once per init call.
 #include "host_tables.h"
 
+#include "mol_jmg.h"
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -191,6 +193,108 @@ int32_t build_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, in
   }
   occ_ptr[n_occ] = n_mol;
   return n_occ;
+}
+
+// ------------------------------------------------------ (j, m), j_max >= 2
+// Eigen-decomposition of a small symmetric matrix a [n x n] (row-major,
+// destroyed) by cyclic Jacobi rotations: w ascending, v[i * n + k] the i-th
+// component of the k-th eigenvector.  Returns false without convergence.
+static bool sym_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v) {
+  v.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
+  bool done = false;
+  double prev = HUGE_VAL;
+  for (int sweep = 0; sweep < 100 && !done; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) (i == k ? diag : off) += a[i * n + k] * a[i * n + k];
+    // converged, or stalled at the rounding floor of the sweep
+    if (off <= 1e-30 * (diag + 1e-300) || (off >= prev && off <= 1e-24 * (diag + 1e-300))) {
+      done = true;
+      break;
+    }
+    prev = off;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        // rotation angle that zeroes a[p][q]
+        const double th = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[k * n + p], vkq = v[k * n + q];
+          v[k * n + p] = c * vkp - s * vkq;
+          v[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  if (!done) return false;
+  // sort ascending
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a[x * n + x] < a[y * n + y]; });
+  std::vector<double> vs(static_cast<size_t>(n) * n);
+  w.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    w[k] = a[ord[k] * n + ord[k]];
+    for (int i = 0; i < n; ++i) vs[i * n + k] = v[i * n + ord[k]];
+  }
+  v.swap(vs);
+  return true;
+}
+
+bool fill_jmg_tables(int jm, double* out) {
+  const JmgTab tb = jmg_tab(jm);
+  std::vector<double> a, w, v;
+  // J_x on the block j: <m+1|J_x|m> = sqrt(j(j+1) - m(m+1)) / 2
+  for (int j = 0; j <= jm; ++j) {
+    const int n = 2 * j + 1;
+    a.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) {
+      const double m = i - j;
+      a[i * n + i + 1] = a[(i + 1) * n + i] = 0.5 * std::sqrt(j * (j + 1.0) - m * (m + 1.0));
+    }
+    if (!sym_eig(n, a, w, v)) return false;
+    for (int k = 0; k < n; ++k)
+      if (std::fabs(w[k] - (k - j)) > 1e-9) return false;   // the spectrum is -j..j
+    std::copy(v.begin(), v.end(), out + tb.jx + jmg_jx_off(j));
+  }
+  // cos(theta) on the block m' = a: <j+1,a|cos|j,a> = sqrt(((j+1)^2 - a^2) / ((2j+1)(2j+3)))
+  for (int am = 0; am <= jm; ++am) {
+    const int n = jm + 1 - am;
+    a.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) {
+      const double j = am + i;
+      a[i * n + i + 1] = a[(i + 1) * n + i] =
+          std::sqrt(((j + 1.0) * (j + 1.0) - am * am) / ((2.0 * j + 1.0) * (2.0 * j + 3.0)));
+    }
+    if (!sym_eig(n, a, w, v)) return false;
+    std::copy(v.begin(), v.end(), out + tb.q + jmg_q_off(jm, am));
+    std::copy(w.begin(), w.end(), out + tb.x + jmg_x_off(jm, am));
+  }
+  // dipole matrix elements (Condon-Shortley phases)
+  for (int j = 0; j <= jm; ++j)
+    for (int m = -j; m <= j; ++m) {
+      double* e = out + tb.dip + 3 * (j * j + m + j);
+      const double jj = j, mm = m;
+      e[0] = j < jm ? std::sqrt(((jj + 1.0) * (jj + 1.0) - mm * mm) / ((2.0 * jj + 1.0) * (2.0 * jj + 3.0))) : 0.0;
+      e[1] = j < jm ? -std::sqrt((jj + mm + 1.0) * (jj + mm + 2.0) / ((2.0 * jj + 1.0) * (2.0 * jj + 3.0))) : 0.0;
+      e[2] = (j >= 1 && m + 1 <= j - 1)
+                 ? std::sqrt((jj - mm) * (jj - mm - 1.0) / ((2.0 * jj - 1.0) * (2.0 * jj + 1.0)))
+                 : 0.0;
+    }
+  return true;
 }
 
 }  // namespace msqd

@@ -1,0 +1,516 @@
+// The molecular step in the rotational basis |j, m>, 2 <= j_max <= 5, with
+// all three field components: one workgroup per molecule, (j_max + 1)^2
+// lines per electronic state.  The coupling is the exact exponential on the
+// truncated basis, applied as a rotation to the field frame, per-m' Gauss
+// transforms of cos(theta), the 2x2 rotation of every eigenvector's (g, e)
+// pair, and the way back (the construction and the tables are described in
+// mol_jmg.h).
+//
+// Work decomposition: the line layout and the kinetic half-steps are those
+// of the m = 0 step (R2 lanes per line, R1 values per lane, in-wave
+// four-step FFT).  The lines go through LDS in SP rounds of radial points;
+// in each round the coupling runs as three stages over the LDS rows:
+//   A: per (state, j, r): y_m' = sum_m d^j_{m m'}(beta) e^{i m alpha} psi_m,
+//   B: per (m', r): chi = Q^T y for both states, the increment of the
+//      rotation, back with Q (the increments replace y in LDS),
+//   C: per (state, j, r): dpsi_m = e^{-i m alpha} sum_m' d^j_{m m'} dy_m',
+// and every lane adds the increments to the values it kept in registers
+// (the increment form: rounding errors scale with the change, not with psi).
+#pragma once
+
+#include "mol_impl.h"
+#include "mol_jmg.h"
+
+namespace msqd {
+
+template <typename T, int NR, int JM>
+struct JmgShape {
+  static constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  static constexpr int NB = (JM + 1) * (JM + 1), L = 2 * NB, threads = L * R2;
+  static constexpr int SP = fwd_split<NR, T>(), NRH = NR / SP;
+  typedef StagedTables<NR, T, true, false> TBL;
+  static constexpr JmgTab tab = jmg_tab(JM);
+  static constexpr size_t a16(size_t b) { return (b + 15) / 16 * 16; }
+  static constexpr size_t rows_bytes =
+      a16(sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))));
+  static constexpr size_t ph_bytes = a16(sizeof(cx<T>) * (2 * JM + 1));
+  static constexpr size_t mt_bytes = a16(sizeof(T) * static_cast<size_t>(tab.n_jx + tab.n_q + tab.n_x));
+  static constexpr size_t red_bytes = 6 * 16 * sizeof(double);
+  static constexpr size_t bytes = TBL::bytes + rows_bytes + ph_bytes + mt_bytes + red_bytes;
+  static constexpr bool fits = threads <= 1024 && bytes <= 160 * 1024;
+};
+
+// ---------------------------------------------------------------- stages
+// Rotation of the j block of state s at radial point rl: to the field frame
+// (BACK = false) or back (BACK = true).  dm holds d^j(beta) row-major
+// [m + j][m' + j] at jmg_jx_off(j); ph[m + JM] = e^{i m alpha}.
+template <typename T, int NR, int JM, int J, bool BACK>
+__device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dm, const cx<T>* ph, int s, int rl) {
+  constexpr int N = 2 * J + 1, NB = (JM + 1) * (JM + 1);
+  const T* d = dm + jmg_jx_off(J);
+  cx<T>* row0 = sh + rl;
+  const int l0 = s * NB + J * J;
+  // the inputs stay in registers; each output goes to LDS as it is formed
+  // (in place: the inputs were read before the first store)
+  cx<T> u[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = row0[lds_row<NR, T>(l0 + i)];
+  if constexpr (!BACK) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = cmul(ph[JM - J + i], u[i]);
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+      cx<T> acc = cscale(u[0], d[k]);
+#pragma unroll
+      for (int i = 1; i < N; ++i) acc = acc + cscale(u[i], d[i * N + k]);
+      row0[lds_row<NR, T>(l0 + k)] = acc;
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < N; ++i) {
+      cx<T> acc = cscale(u[0], d[i * N]);
+#pragma unroll
+      for (int k = 1; k < N; ++k) acc = acc + cscale(u[k], d[i * N + k]);
+      row0[lds_row<NR, T>(l0 + i)] = cmul_conj(acc, ph[JM - J + i]);
+    }
+  }
+}
+
+template <typename T, int NR, int JM, int J, bool BACK>
+__device__ __forceinline__ void jmg_rot_dispatch(int j, cx<T>* sh, const T* dm, const cx<T>* ph, int s, int rl) {
+  if (j == J)
+    jmg_rot_block<T, NR, JM, J, BACK>(sh, dm, ph, s, rl);
+  else if constexpr (J > 1)
+    jmg_rot_dispatch<T, NR, JM, J - 1, BACK>(j, sh, dm, ph, s, rl);
+}
+
+// All (state, j >= 1, r) tasks of a round; the j = 0 block is unchanged by
+// the rotation.  Tasks are ordered by decreasing j so that the heavy blocks
+// spread over the workgroup.
+template <typename T, int NR, int JM, bool BACK>
+__device__ __forceinline__ void jmg_rotate(cx<T>* sh, const T* dm, const cx<T>* ph, int tid, int nthr) {
+  constexpr int NRH = JmgShape<T, NR, JM>::NRH;
+  constexpr int NT = 2 * JM * NRH;
+  for (int t = tid; t < NT; t += nthr) {
+    const int jr = t / (2 * NRH);
+    const int rem = t - jr * 2 * NRH;
+    const int s = rem / NRH;
+    jmg_rot_dispatch<T, NR, JM, JM, BACK>(JM - jr, sh, dm, ph, s, rem - s * NRH);
+  }
+}
+
+// Stage B on the block m' (|m'| = A) at radial point rl: the states
+// j = A..JM of both electronic states.  The block |m'| = JM has the single
+// state j = JM, on which cos(theta) vanishes: its increment is zero.
+template <typename T, int NR, int JM, int A>
+__device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T* xe, int mp, T md, int rl) {
+  constexpr int N = JM + 1 - A, NB = (JM + 1) * (JM + 1);
+  if constexpr (A == JM) {
+    const int b = JM * JM + mp + JM;
+    sh[lds_row<NR, T>(b) + rl] = {T(0), T(0)};
+    sh[lds_row<NR, T>(NB + b) + rl] = {T(0), T(0)};
+  } else {
+    const T* Q = qm + jmg_q_off(JM, A);
+    const T* x = xe + jmg_x_off(JM, A);
+    cx<T> g[N], e[N], cg[N], ce[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int j = A + i, b = j * j + mp + j;
+      g[i] = sh[lds_row<NR, T>(b) + rl];
+      e[i] = sh[lds_row<NR, T>(NB + b) + rl];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      cx<T> ag = cscale(g[0], Q[k]), ae = cscale(e[0], Q[k]);
+#pragma unroll
+      for (int i = 1; i < N; ++i) {
+        ag = ag + cscale(g[i], Q[i * N + k]);
+        ae = ae + cscale(e[i], Q[i * N + k]);
+      }
+      // exp(i th sigma_x) - 1 on (g, e): (-vers g + i sin e, i sin g - vers e)
+      T sn, vs;
+      sin_vers(md * x[k], &sn, &vs);
+      cg[k] = {-vs * ag.x - sn * ae.y, -vs * ag.y + sn * ae.x};
+      ce[k] = {-vs * ae.x - sn * ag.y, -vs * ae.y + sn * ag.x};
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      cx<T> ag = cscale(cg[0], Q[i * N]), ae = cscale(ce[0], Q[i * N]);
+#pragma unroll
+      for (int k = 1; k < N; ++k) {
+        ag = ag + cscale(cg[k], Q[i * N + k]);
+        ae = ae + cscale(ce[k], Q[i * N + k]);
+      }
+      const int j = A + i, b = j * j + mp + j;
+      sh[lds_row<NR, T>(b) + rl] = ag;
+      sh[lds_row<NR, T>(NB + b) + rl] = ae;
+    }
+  }
+}
+
+template <typename T, int NR, int JM, int A>
+__device__ __forceinline__ void jmg_couple_dispatch(int a, cx<T>* sh, const T* qm, const T* xe, int mp, T md,
+                                                    int rl) {
+  if (a == A)
+    jmg_couple_block<T, NR, JM, A>(sh, qm, xe, mp, md, rl);
+  else if constexpr (A > 0)
+    jmg_couple_dispatch<T, NR, JM, A - 1>(a, sh, qm, xe, mp, md, rl);
+}
+
+// All (m', r) tasks of a round, m' in the order 0, 1, -1, 2, -2, ...
+template <typename T, int NR, int JM>
+__device__ __forceinline__ void jmg_couple(cx<T>* sh, const T* qm, const T* xe, const T* mudt_h, int tid,
+                                           int nthr) {
+  constexpr int NRH = JmgShape<T, NR, JM>::NRH;
+  constexpr int NT = (2 * JM + 1) * NRH;
+  for (int t = tid; t < NT; t += nthr) {
+    const int u = t / NRH;
+    const int rl = t - u * NRH;
+    const int a = (u + 1) >> 1;
+    const int mp = (u & 1) ? a : -a;
+    jmg_couple_dispatch<T, NR, JM, JM>(a, sh, qm, xe, mp, mudt_h[rl], rl);
+  }
+}
+
+// Dipole vector at radial point rl (FP64): Re<g|D_z|e>, and P = <g|D_+|e>,
+// P' = <e|D_+|g> with D_+ = D_x + i D_y, from which Re<g|D_x|e> =
+// (Re P + Re P') / 2 and Re<g|D_y|e> = (Im P + Im P') / 2.
+template <typename T, int NR, int JM>
+__device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* dip, int rl, double* tx,
+                                                 double* ty, double* tz) {
+  constexpr int NB = (JM + 1) * (JM + 1);
+  auto ld = [&](int line) {
+    const cx<T> v = sh[lds_row<NR, T>(line) + rl];
+    return cx<double>{static_cast<double>(v.x), static_cast<double>(v.y)};
+  };
+  double z = 0.0, pr = 0.0, pi = 0.0;
+#pragma unroll 1
+  for (int j = 0; j <= JM; ++j) {
+#pragma unroll 1
+    for (int m = -j; m <= j; ++m) {
+      const int b = j * j + m + j;
+      const cx<double> gb = ld(b), eb = ld(NB + b);
+      if (j < JM) {
+        const int bz = (j + 1) * (j + 1) + m + j + 1;        // (j+1, m)
+        const int bp = bz + 1;                               // (j+1, m+1)
+        const cx<double> gz = ld(bz), ez = ld(NB + bz);
+        z += dip[3 * b] * ((gz.x * eb.x + gz.y * eb.y) + (gb.x * ez.x + gb.y * ez.y));
+        const cx<double> gp = ld(bp), ep = ld(NB + bp);
+        const double c = dip[3 * b + 1];
+        // conj(g_p) e_b + conj(e_p) g_b
+        pr += c * ((gp.x * eb.x + gp.y * eb.y) + (ep.x * gb.x + ep.y * gb.y));
+        pi += c * ((gp.x * eb.y - gp.y * eb.x) + (ep.x * gb.y - ep.y * gb.x));
+      }
+      if (m + 1 <= j - 1) {
+        const int bm = (j - 1) * (j - 1) + m + 1 + j - 1;    // (j-1, m+1)
+        const cx<double> gm = ld(bm), em = ld(NB + bm);
+        const double c = dip[3 * b + 2];
+        pr += c * ((gm.x * eb.x + gm.y * eb.y) + (em.x * gb.x + em.y * gb.y));
+        pi += c * ((gm.x * eb.y - gm.y * eb.x) + (em.x * gb.y - em.y * gb.x));
+      }
+    }
+  }
+  *tx = 0.5 * pr;
+  *ty = 0.5 * pi;
+  *tz = z;
+}
+
+// ---------------------------------------------------------------- kernel
+// Waves per SIMD the register allocation targets (complex64): three where
+// that fits more workgroups on a CU than two does.  A seven-wave workgroup
+// (j_max = 4 at R2 = 8) gets one workgroup per CU either way, so it keeps
+// two waves per SIMD and the registers that come with them.
+template <typename T, int NR, int JM>
+struct JmgOcc {
+  static constexpr int wg_waves = (JmgShape<T, NR, JM>::threads + 63) / 64;
+  static constexpr int waves = sizeof(T) == 8 ? 1 : ((12 / wg_waves) > (8 / wg_waves) ? 3 : 2);
+};
+
+template <typename T, int NR, int JM, bool ONE>
+__global__ __launch_bounds__((JmgShape<T, NR, JM>::threads)) __attribute__((amdgpu_waves_per_eu(JmgOcc<T, NR, JM>::waves)))
+void mol_jmg_kernel(MolArgs a) {
+  typedef JmgShape<T, NR, JM> S;
+  constexpr int R1 = S::R1, R2 = S::R2, NB = S::NB, SP = S::SP, PH = R1 / SP, NRH = S::NRH;
+  constexpr JmgTab TB = S::tab;
+  typedef typename S::TBL TBL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tw_s = kin_s + NR;
+  T* mask_s = reinterpret_cast<T*>(tw_s + TBL::tw_elems);
+  cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TBL::bytes);
+  cx<T>* ph = reinterpret_cast<cx<T>*>(smem + TBL::bytes + S::rows_bytes);
+  T* dm = reinterpret_cast<T*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes);
+  T* qm = dm + TB.n_jx;
+  T* xe = qm + TB.n_q;
+  double* red = reinterpret_cast<double*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes + S::mt_bytes);
+
+  const int mol = blockIdx.x;
+  const int tid = threadIdx.x;
+  constexpr int nthr = S::threads;
+  const int line = tid / R2;
+  const int q = tid - line * R2;
+  const int st = line / NB, b = line - st * NB;
+  int jl = 0;
+  while ((jl + 1) * (jl + 1) <= b) ++jl;
+
+  const char* ws = a.ws;
+  const bool dbl = sizeof(T) == 8;
+  const cx<T>* kin_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.kin_d : a.lay.kin_f));
+  const cx<T>* tw_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.tw_d : a.lay.tw_f));
+  const cx<T>* vph_g = reinterpret_cast<const cx<T>*>(ws + (dbl ? a.lay.vph_d : a.lay.vph_f));
+  const T* mudt = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mudt_d : a.lay.mudt_f));
+  const T* mask_g = reinterpret_cast<const T*>(ws + (dbl ? a.lay.mask_d : a.lay.mask_f));
+  const double* mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
+  const double* tg = reinterpret_cast<const double*>(ws + a.lay.total);
+
+  // field at the molecule (each component at its own edge of the cell)
+  double E3[3];
+  if (a.Ex != nullptr) {
+    const int c = a.cell_of_mol[mol];
+    const void* f3[3] = {a.Ex, a.Ey, a.Ez};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      E3[k] = (a.ex_is_float ? static_cast<double>(static_cast<const float*>(f3[k])[c])
+                             : static_cast<const double*>(f3[k])[c]) * a.inv_eau;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) E3[k] = a.E_mol[3 * mol + k];
+  }
+  if (a.E_out != nullptr && tid == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.E_out[3 * mol + k] = E3[k];
+  }
+
+  cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * S::L * NR;
+  cx<T>* slot = sh + lds_row<NR, T>(line);
+  const int loff = line * NR + q;
+  const int voff = (st * a.nj + jl) * NR + q;   // potential phases depend on (state, j)
+  cx<T> vv[R1];
+#pragma unroll
+  for (int p = 0; p < R1; ++p) vv[p] = psi[loff + R2 * p];
+
+  // per-molecule coupling tables: the field frame (alpha, beta) and |E|
+  {
+    const double en = sqrt(E3[0] * E3[0] + E3[1] * E3[1] + E3[2] * E3[2]);
+    const double rho = sqrt(E3[0] * E3[0] + E3[1] * E3[1]);
+    const double ca = rho > 0.0 ? E3[0] / rho : 1.0, sa = rho > 0.0 ? E3[1] / rho : 0.0;
+    const double cb = en > 0.0 ? E3[2] / en : 1.0, sb = en > 0.0 ? rho / en : 0.0;
+    if (tid < 2 * JM + 1) {
+      const int m = tid - JM, am = m < 0 ? -m : m;
+      double px = 1.0, py = 0.0;
+      for (int k = 0; k < am; ++k) {
+        const double nx = px * ca - py * sa;
+        py = px * sa + py * ca;
+        px = nx;
+      }
+      ph[tid] = {static_cast<T>(px), static_cast<T>(m < 0 ? -py : py)};
+    }
+    for (int t = tid; t < TB.n_jx; t += nthr) {
+      int j = 0;
+      while (t >= jmg_jx_off(j + 1)) ++j;
+      const int n = 2 * j + 1, o = t - jmg_jx_off(j), ra = o / n, rc = o - ra * n;
+      const double* O = tg + TB.jx + jmg_jx_off(j);
+      // cos(pi/2 (m' - m) - beta mu) = cA cos(mu beta) + sA sin(mu beta)
+      const int dq = (rc - ra) & 3;
+      const double cA = dq == 0 ? 1.0 : (dq == 2 ? -1.0 : 0.0);
+      const double sA = dq == 1 ? 1.0 : (dq == 3 ? -1.0 : 0.0);
+      double acc = O[ra * n + j] * O[rc * n + j] * cA;
+      double wc = 1.0, wsn = 0.0;   // cos(mu beta), sin(mu beta)
+      for (int mu_ = 1; mu_ <= j; ++mu_) {
+        const double nc = wc * cb - wsn * sb;
+        wsn = wc * sb + wsn * cb;
+        wc = nc;
+        acc += O[ra * n + j + mu_] * O[rc * n + j + mu_] * (cA * wc + sA * wsn) +
+               O[ra * n + j - mu_] * O[rc * n + j - mu_] * (cA * wc - sA * wsn);
+      }
+      dm[t] = static_cast<T>(acc);
+    }
+    for (int t = tid; t < TB.n_q; t += nthr) qm[t] = static_cast<T>(tg[TB.q + t]);
+    for (int t = tid; t < TB.n_x; t += nthr) xe[t] = static_cast<T>(en * tg[TB.x + t]);
+  }
+  if constexpr (stage_tables<NR, T>()) stage_tables_to_lds<NR, T, true>(kin_s, tw_s, mask_s, kin_g, tw_g, mask_g);
+  __syncthreads();
+
+  double ab = 0.0;
+  const int n_steps = ONE ? 1 : a.n_steps;
+  for (int step = 0; step < n_steps; ++step) {
+    const cx<T>* kin;
+    const cx<T>* tw;
+    const T* mask;
+    if constexpr (stage_tables<NR, T>()) {
+      kin = kin_s;
+      tw = tw_s;
+      mask = mask_s;
+    } else {
+      kin = opaque(kin_g);
+      tw = opaque(tw_g);
+      mask = opaque(mask_g);
+    }
+    const cx<T>* vph = opaque(vph_g);
+    kinetic_half<T, NR, false, SP, TBL::TWC>(vv, slot, q, kin, tw);
+#pragma unroll
+    for (int h = 0; h < SP; ++h) {
+#pragma unroll
+      for (int pp = 0; pp < PH; ++pp) {
+        const int p = h * PH + pp;
+        vv[p] = phase_mul(vv[p], vph[voff + R2 * p]);
+        slot[q + R2 * pp] = vv[p];
+      }
+      __syncthreads();
+      jmg_rotate<T, NR, JM, false>(sh, dm, ph, tid, nthr);
+      __syncthreads();
+      jmg_couple<T, NR, JM>(sh, qm, xe, mudt + h * NRH, tid, nthr);
+      __syncthreads();
+      jmg_rotate<T, NR, JM, true>(sh, dm, ph, tid, nthr);
+      __syncthreads();
+#pragma unroll
+      for (int pp = 0; pp < PH; ++pp) {
+        const int p = h * PH + pp;
+        vv[p] = phase_mul(vv[p] + slot[q + R2 * pp], vph[voff + R2 * p]);
+      }
+    }
+    kinetic_half<T, NR, false, SP, TBL::TWC>(vv, slot, q, kin, tw);
+    constexpr int P0 = (3 * R1) / 4;
+    if (a.kmask >= R2 * P0) {
+#pragma unroll
+      for (int p = P0; p < R1; ++p) absorb_point_nb(vv[p], mask[q + R2 * p], ab);
+    } else {
+#pragma unroll
+      for (int p = 0; p < R1; ++p) absorb_point(vv[p], mask[q + R2 * p], ab);
+    }
+  }
+
+  // readouts: norm, yield, and the dipole vector (in the same rounds)
+  double nrm = 0.0, yld = 0.0;
+#pragma unroll
+  for (int p = 0; p < R1; ++p) {
+    const double n2 = static_cast<double>(norm2(vv[p]));
+    nrm += n2;
+    if (q + R2 * p >= a.kdiss) yld += n2;
+  }
+  double dc[3] = {0.0, 0.0, 0.0};
+  if (a.want_d && a.d_mol) {
+    const double* dip = tg + TB.dip;
+#pragma unroll
+    for (int h = 0; h < SP; ++h) {
+      __syncthreads();   // the previous users of the slots are done
+#pragma unroll
+      for (int pp = 0; pp < PH; ++pp) slot[q + R2 * pp] = vv[h * PH + pp];
+      __syncthreads();
+      for (int rl = tid; rl < NRH; rl += nthr) {
+        double tx, ty, tz;
+        jmg_dipole_point<T, NR, JM>(sh, dip, rl, &tx, &ty, &tz);
+        const double m = mu[h * NRH + rl];
+        dc[0] += m * tx;
+        dc[1] += m * ty;
+        dc[2] += m * tz;
+      }
+    }
+  }
+  // workgroup sums of (ab, nrm, yld, dx, dy, dz) in a fixed order
+  double vals[6] = {ab, nrm, yld, dc[0], dc[1], dc[2]};
+  const int lane = tid & 63, wid = tid >> 6;
+  constexpr int nw = (nthr + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) vals[k] = wave_sum(vals[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[wid * 6 + k] = vals[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sm[6];
+    for (int k = 0; k < 6; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w * 6 + k];
+      sm[k] = t;
+    }
+    const double dr = a.dr;
+    const double absorbed = a.absorbed[mol] + sm[0] * dr;
+    if (n_steps > 0) a.absorbed[mol] = absorbed;
+    if (a.want_d && a.d_mol) {
+      for (int k = 0; k < 3; ++k) a.d_mol[3 * mol + k] = 2.0 * dr * sm[3 + k];
+    }
+    if (a.want_norm && a.norm_mol) a.norm_mol[mol] = sm[1] * dr;
+    if (a.want_yield && a.yield_mol) a.yield_mol[mol] = sm[2] * dr + absorbed;
+    if (!isfinite(sm[1]) || !isfinite(sm[3]) || !isfinite(sm[4]) || !isfinite(sm[5]) || !isfinite(absorbed))
+      atomicOr(a.status, 1);
+  }
+  if (n_steps > 0) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) psi[loff + R2 * p] = vv[p];
+  }
+}
+
+template <typename T, int NR, int JM, bool ONE>
+int launch_jmg_t1(const MolArgs& a, hipStream_t s) {
+  typedef JmgShape<T, NR, JM> S;
+  if constexpr (!S::fits) {
+    return static_cast<int>(hipErrorInvalidValue);
+  } else {
+    const size_t shm = S::bytes;
+    if (shm > mol_lds_limit()) return static_cast<int>(hipErrorInvalidValue);
+    static std::atomic<unsigned long long> lds_set{0};
+    if (shm > 64 * 1024) {
+      const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_jmg_kernel<T, NR, JM, ONE>), lds_set);
+      if (e != hipSuccess) return static_cast<int>(e);
+    }
+    hipLaunchKernelGGL((mol_jmg_kernel<T, NR, JM, ONE>), dim3(a.n_mol), dim3(S::threads), shm, s, a);
+    return static_cast<int>(hipGetLastError());
+  }
+}
+
+template <typename T, int NR, int JM>
+int launch_jmg_t(const MolArgs& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.n_steps == 1) return launch_jmg_t1<T, NR, JM, true>(a, s);
+  }
+  return launch_jmg_t1<T, NR, JM, false>(a, s);
+}
+
+template <typename T, int JM>
+int launch_jmg_nr(const MolArgs& a, int n_r, hipStream_t s) {
+  switch (n_r) {
+    case 64: return launch_jmg_t<T, 64, JM>(a, s);
+    case 128: return launch_jmg_t<T, 128, JM>(a, s);
+    case 256: return launch_jmg_t<T, 256, JM>(a, s);
+    case 512: return launch_jmg_t<T, 512, JM>(a, s);
+    default: return static_cast<int>(hipErrorInvalidValue);
+  }
+}
+
+template <typename T>
+int launch_jmg_prec(const MolArgs& a, int n_r, int jm, hipStream_t s) {
+  switch (jm) {
+    case 2: return launch_jmg_nr<T, 2>(a, n_r, s);
+    case 3: return launch_jmg_nr<T, 3>(a, n_r, s);
+    case 4: return launch_jmg_nr<T, 4>(a, n_r, s);
+    case 5: return launch_jmg_nr<T, 5>(a, n_r, s);
+    default: return static_cast<int>(hipErrorInvalidValue);
+  }
+}
+
+template <typename T, int JM>
+bool jmg_fits_nr(int n_r, size_t* lds) {
+  switch (n_r) {
+    case 64: *lds = JmgShape<T, 64, JM>::bytes; return JmgShape<T, 64, JM>::fits;
+    case 128: *lds = JmgShape<T, 128, JM>::bytes; return JmgShape<T, 128, JM>::fits;
+    case 256: *lds = JmgShape<T, 256, JM>::bytes; return JmgShape<T, 256, JM>::fits;
+    case 512: *lds = JmgShape<T, 512, JM>::bytes; return JmgShape<T, 512, JM>::fits;
+    default: *lds = 0; return false;
+  }
+}
+
+template <typename T>
+bool jmg_fits(int n_r, int jm, size_t* lds) {
+  switch (jm) {
+    case 2: return jmg_fits_nr<T, 2>(n_r, lds);
+    case 3: return jmg_fits_nr<T, 3>(n_r, lds);
+    case 4: return jmg_fits_nr<T, 4>(n_r, lds);
+    case 5: return jmg_fits_nr<T, 5>(n_r, lds);
+    default: *lds = 0; return false;
+  }
+}
+
+}  // namespace msqd

@@ -146,12 +146,28 @@ def test_bloch_validation(msqd):
 
 
 def test_jm_basis_validation(msqd):
-    """The (j, m) basis is provided for j_max = 1; an unknown basis value is
-    rejected before anything touches a device."""
-    d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_JM)
-    assert msqd.lib.qd_workspace_bytes(C.byref(d)) > 0
-    d = msqd.qd_desc(4, 128, 2, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_JM)
-    assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0
-    assert "j_max = 1" in msqd.last_error()
+    """The (j, m) basis is provided for 1 <= j_max <= 5, within one
+    workgroup's threads and LDS; its workspace carries the coupling tables
+    for j_max >= 2; an unknown basis value is rejected before anything
+    touches a device."""
+    def ws(n_r, j_max, prec=msqd.FP64):
+        d = msqd.qd_desc(4, n_r, j_max, prec, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_JM)
+        return msqd.lib.qd_workspace_bytes(C.byref(d))
+
+    assert ws(128, 1) > 0
+    base = {jm: ws(128, jm, msqd.FP32) for jm in range(1, 6)}
+    # the general tables: sum (2j+1)^2 + sum (j_max+1-a)^2 + (j_max+1)(j_max+2)/2 + 3 (j_max+1)^2 doubles
+    for jm in range(2, 6):
+        n = sum((2 * j + 1) ** 2 for j in range(jm + 1)) + sum((jm + 1 - a) ** 2 for a in range(jm + 1)) \
+            + (jm + 1) * (jm + 2) // 2 + 3 * (jm + 1) ** 2
+        d0 = msqd.qd_desc(4, 128, jm, msqd.FP32, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_M0)
+        assert base[jm] == msqd.lib.qd_workspace_bytes(C.byref(d0)) + 8 * n
+    assert ws(256, 5, msqd.MIXED) > 0
+    for n_r, jm, prec in [(128, 0, msqd.FP64), (128, 6, msqd.FP32)]:
+        assert ws(n_r, jm, prec) == 0
+        assert "1 <= j_max <= 5" in msqd.last_error()
+    # complex128 at n_r = 256: 32 lanes x 36 lines exceed one workgroup
+    assert ws(256, 5) == 0
+    assert "too large for one workgroup" in msqd.last_error()
     d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 7)
     assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0

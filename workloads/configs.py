@@ -64,7 +64,7 @@ class Config:
     r_min: float = 1.0
     r_max: float = 12.0
     j_max: int = 4
-    basis: str = "m0"              # m0: J lines, field along the axis | jm: all (j, m), j <= 1
+    basis: str = "m0"              # m0: J lines, field along the axis | jm: all (j, m), 1 <= j_max <= 5
     mass: float = 1.0e4
     morse_d: float = 0.17
     morse_a: float = 1.0
