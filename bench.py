@@ -99,8 +99,37 @@ def jm_bytes_per_step(n_r):
     return 2 * 8 * n_r * 8 + 3 * 8 + 3 * 8 + 16
 
 
-def jm_config(cfg, n_mol=691_200, n_r=256):
-    return cfg.replace(n_mol=n_mol, j_max=1, basis="jm", n_r=n_r)
+def jmg_flops_per_step(n_r, j_max):
+    """Algorithmic vector flops of one molecule-step in the (j, m) basis with
+    2 <= j_max <= 5 ((j_max+1)^2 lines per state): four N_r-point complex
+    FFTs per line, the kinetic and the two potential phase multiplies (6
+    flops per point each), and at every (state, r) the rotation to the field
+    frame and back (per block j >= 1: 2j+1 phase products, 6 flops, and the
+    (2j+1)^2 real-by-complex products of d^j, 4 flops each); at every r the
+    per-m' transforms of cos(theta) for both states, there and back (4 n^2
+    real-by-complex products, n = j_max + 1 - |m'|) and the 2x2 rotation of
+    each eigenvector's pair (12 flops plus 2 for the angle); and the norm and
+    dipole-vector readouts (3 and about 50 flops per line and point)."""
+    nb = (j_max + 1) ** 2
+    lines = 2 * nb
+    fft = 5 * n_r * int(np.log2(n_r))
+    per_line = 4 * fft + 2 * 6 * n_r + 2 * 6 * n_r
+    rot = 2 * 2 * n_r * (6 * (nb - 1) + 4 * sum((2 * j + 1) ** 2 for j in range(1, j_max + 1)))
+    blocks = [j_max + 1 - abs(mp) for mp in range(-j_max, j_max + 1) if abs(mp) < j_max]
+    couple = n_r * sum(16 * n * n + 14 * n for n in blocks)
+    readout = 2 * nb * n_r * 3 + 50 * nb * n_r
+    return lines * per_line + rot + couple + readout
+
+
+def jmg_bytes_per_step(n_r, j_max):
+    """Algorithmic HBM bytes of one (j, m) molecule-step: the 2 (j_max+1)^2
+    lines read and written once (complex64), the three field components, the
+    dipole vector and the absorbed accumulator (read + write)."""
+    return 2 * 2 * (j_max + 1) ** 2 * n_r * 8 + 3 * 8 + 3 * 8 + 16
+
+
+def jm_config(cfg, n_mol=691_200, n_r=256, j_max=1):
+    return cfg.replace(n_mol=n_mol, j_max=j_max, basis="jm", n_r=n_r)
 
 
 def mol_mfma_flops_per_step(cfg):
@@ -260,22 +289,28 @@ def run_bloch(cfg, steps, warmup, n0, n_emitters):
     return out
 
 
-def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256):
-    """The paper's own molecular model: all (j, m) with j <= 1 and all three
-    field components, 691,200 molecules in the SRR slab (the paper's count),
-    precision form, one molecular step per field step."""
-    c = jm_config(cfg, n_mol, n_r)
+def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256, j_max=1):
+    """The paper's own molecular model: all (j, m) with j <= j_max and all
+    three field components, 691,200 molecules in the SRR slab (the paper's
+    count), precision form, one molecular step per field step.  j_max = 1 is
+    the truncation of the paper's ensemble results (closed-form coupling);
+    j_max = 5 the largest basis of its scaling test (general coupling)."""
+    c = jm_config(cfg, n_mol, n_r, j_max)
     out = run_coupled(c, "fp32", steps, warmup, n0)
     rate = out["n_mol"] * steps / (out["ms"] / 1e3)
-    kms = time_mol_kernel(c, "fp32", 10)
-    kt = jm_flops_per_step(n_r) * n_mol / (kms / 1e3) / 1e12
-    kb = jm_bytes_per_step(n_r) * n_mol / (kms / 1e3) / 1e9
-    return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= 1, N_r={n_r}, FP32",
+    kms = time_mol_kernel(c, "fp32", 10 if j_max == 1 else 5)
+    fl = jm_flops_per_step(n_r) if j_max == 1 else jmg_flops_per_step(n_r, j_max)
+    by = jm_bytes_per_step(n_r) if j_max == 1 else jmg_bytes_per_step(n_r, j_max)
+    kt = fl * n_mol / (kms / 1e3) / 1e12
+    kb = by * n_mol / (kms / 1e3) / 1e9
+    name = "mol_jm_kernel<float,256,single-step>" if j_max == 1 else \
+        f"mol_jmg_kernel<float,256,{j_max},single-step>"
+    return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= {j_max}, N_r={n_r}, FP32",
             "ms_per_step": out["ms"] / steps, "molecule_steps_per_s": rate,
-            "flops_per_molecule_step": jm_flops_per_step(n_r),
-            "coupled_step_TFLOPs": rate * jm_flops_per_step(n_r) / 1e12,
-            "coupled_step_frac_of_vector_peak": rate * jm_flops_per_step(n_r) / 1e12 / VALU_F32_PEAK_TFLOPS,
-            "kernel": "mol_jm_kernel<float,256,single-step>", "kernel_ms": kms,
+            "flops_per_molecule_step": fl, "bytes_per_molecule_step": by,
+            "coupled_step_TFLOPs": rate * fl / 1e12,
+            "coupled_step_frac_of_vector_peak": rate * fl / 1e12 / VALU_F32_PEAK_TFLOPS,
+            "kernel": name, "kernel_ms": kms,
             "kernel_TFLOPs": kt, "kernel_frac_of_vector_peak": kt / VALU_F32_PEAK_TFLOPS,
             "kernel_GBs": kb, "kernel_frac_of_hbm": kb / HBM_PEAK_GBS}
 
@@ -473,7 +508,7 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload (400 forward + reverse steps) and its "
                          "forward-only timing, for a kernel trace of the adjoint")
-    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm"], default=None,
+    ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm", "jm5"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
     args = ap.parse_args()
@@ -516,6 +551,15 @@ def main():
                           "TFLOPs": jm_flops_per_step(c.n_r) * c.n_mol / (ms / 1e3) / 1e12,
                           "calibration_copy_bytes": 1 << 30}))
         return
+    if args.kernel == "jm5":
+        c = jm_config(cfg, j_max=5)
+        ms = time_mol_kernel(c, "fp32", K)
+        calibration_copy()
+        print(json.dumps({"kernel": "jm5", "launches": K, "ms": ms, "n_mol": c.n_mol,
+                          "GBs": jmg_bytes_per_step(c.n_r, 5) * c.n_mol / (ms / 1e3) / 1e9,
+                          "TFLOPs": jmg_flops_per_step(c.n_r, 5) * c.n_mol / (ms / 1e3) / 1e12,
+                          "calibration_copy_bytes": 1 << 30}))
+        return
     if args.kernel:
         c = cfg if args.kernel != "fp64" else cfg64
         ms = time_mol_kernel(c, args.kernel, K)
@@ -556,6 +600,8 @@ def main():
 
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 1")
     jm = run_jm(cfg, 20, 2, n0)
+    log("(j, m)-basis coupled run: 691,200 molecules, j <= 5")
+    jm["j_max_5"] = run_jm(cfg, 5, 1, n0, j_max=5)
     log("Bloch-emitter coupled run: 691,200 emitters")
     bloch = run_bloch(cfg, K, W, n0, 691_200)
 

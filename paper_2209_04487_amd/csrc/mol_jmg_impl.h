@@ -110,40 +110,48 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
     sh[lds_row<NR, T>(b) + rl] = {T(0), T(0)};
     sh[lds_row<NR, T>(NB + b) + rl] = {T(0), T(0)};
   } else {
-    const T* Q = qm + jmg_q_off(JM, A);
+    // one eigenvector k at a time: chi_k = sum_i Q[i][k] y_i for both states,
+    // its rotation increment, and dy_i += Q[i][k] dchi_k; qm holds Q
+    // column-major, so column k is contiguous
+    const T* Qc = qm + jmg_q_off(JM, A);
     const T* x = xe + jmg_x_off(JM, A);
-    cx<T> g[N], e[N], cg[N], ce[N];
+    // the rotation angles' sine and versine first, while little else is
+    // live (the large-angle path is an out-of-line call)
+    T sn[N], vs[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) sin_vers(md * x[k], &sn[k], &vs[k]);
+    cx<T> g[N], e[N], og[N], oe[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const int j = A + i, b = j * j + mp + j;
       g[i] = sh[lds_row<NR, T>(b) + rl];
       e[i] = sh[lds_row<NR, T>(NB + b) + rl];
+      og[i] = {T(0), T(0)};
+      oe[i] = {T(0), T(0)};
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      cx<T> ag = cscale(g[0], Q[k]), ae = cscale(e[0], Q[k]);
+      const T* qk = Qc + k * N;
+      cx<T> ag = cscale(g[0], qk[0]), ae = cscale(e[0], qk[0]);
 #pragma unroll
       for (int i = 1; i < N; ++i) {
-        ag = ag + cscale(g[i], Q[i * N + k]);
-        ae = ae + cscale(e[i], Q[i * N + k]);
+        ag = ag + cscale(g[i], qk[i]);
+        ae = ae + cscale(e[i], qk[i]);
       }
       // exp(i th sigma_x) - 1 on (g, e): (-vers g + i sin e, i sin g - vers e)
-      T sn, vs;
-      sin_vers(md * x[k], &sn, &vs);
-      cg[k] = {-vs * ag.x - sn * ae.y, -vs * ag.y + sn * ae.x};
-      ce[k] = {-vs * ae.x - sn * ag.y, -vs * ae.y + sn * ag.x};
+      const cx<T> dg = {-vs[k] * ag.x - sn[k] * ae.y, -vs[k] * ag.y + sn[k] * ae.x};
+      const cx<T> de = {-vs[k] * ae.x - sn[k] * ag.y, -vs[k] * ae.y + sn[k] * ag.x};
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        og[i] = og[i] + cscale(dg, qk[i]);
+        oe[i] = oe[i] + cscale(de, qk[i]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      cx<T> ag = cscale(cg[0], Q[i * N]), ae = cscale(ce[0], Q[i * N]);
-#pragma unroll
-      for (int k = 1; k < N; ++k) {
-        ag = ag + cscale(cg[k], Q[i * N + k]);
-        ae = ae + cscale(ce[k], Q[i * N + k]);
-      }
       const int j = A + i, b = j * j + mp + j;
-      sh[lds_row<NR, T>(b) + rl] = ag;
-      sh[lds_row<NR, T>(NB + b) + rl] = ae;
+      sh[lds_row<NR, T>(b) + rl] = og[i];
+      sh[lds_row<NR, T>(NB + b) + rl] = oe[i];
     }
   }
 }
@@ -172,11 +180,12 @@ __device__ __forceinline__ void jmg_couple(cx<T>* sh, const T* qm, const T* xe, 
   }
 }
 
-// Dipole vector at radial point rl (FP64): Re<g|D_z|e>, and P = <g|D_+|e>,
-// P' = <e|D_+|g> with D_+ = D_x + i D_y, from which Re<g|D_x|e> =
-// (Re P + Re P') / 2 and Re<g|D_y|e> = (Im P + Im P') / 2.
+// The terms of the dipole vector at radial point rl from the basis states of
+// one j (FP64): Re<g|D_z|e>, and P = <g|D_+|e>, P' = <e|D_+|g> with
+// D_+ = D_x + i D_y, from which Re<g|D_x|e> = (Re P + Re P') / 2 and
+// Re<g|D_y|e> = (Im P + Im P') / 2.  Summed over j they give the dipole.
 template <typename T, int NR, int JM>
-__device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* dip, int rl, double* tx,
+__device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* dip, int j, int rl, double* tx,
                                                  double* ty, double* tz) {
   constexpr int NB = (JM + 1) * (JM + 1);
   auto ld = [&](int line) {
@@ -184,8 +193,7 @@ __device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* 
     return cx<double>{static_cast<double>(v.x), static_cast<double>(v.y)};
   };
   double z = 0.0, pr = 0.0, pi = 0.0;
-#pragma unroll 1
-  for (int j = 0; j <= JM; ++j) {
+  {
 #pragma unroll 1
     for (int m = -j; m <= j; ++m) {
       const int b = j * j + m + j;
@@ -325,7 +333,13 @@ void mol_jmg_kernel(MolArgs a) {
       }
       dm[t] = static_cast<T>(acc);
     }
-    for (int t = tid; t < TB.n_q; t += nthr) qm[t] = static_cast<T>(tg[TB.q + t]);
+    // Q^(a) column-major in LDS (the workspace holds it row-major)
+    for (int t = tid; t < TB.n_q; t += nthr) {
+      int am = 0;
+      while (t >= jmg_q_off(JM, am + 1)) ++am;
+      const int n = JM + 1 - am, o = t - jmg_q_off(JM, am), i = o / n, k = o - i * n;
+      qm[jmg_q_off(JM, am) + k * n + i] = static_cast<T>(tg[TB.q + t]);
+    }
     for (int t = tid; t < TB.n_x; t += nthr) xe[t] = static_cast<T>(en * tg[TB.x + t]);
   }
   if constexpr (stage_tables<NR, T>()) stage_tables_to_lds<NR, T, true>(kin_s, tw_s, mask_s, kin_g, tw_g, mask_g);
@@ -397,9 +411,10 @@ void mol_jmg_kernel(MolArgs a) {
 #pragma unroll
       for (int pp = 0; pp < PH; ++pp) slot[q + R2 * pp] = vv[h * PH + pp];
       __syncthreads();
-      for (int rl = tid; rl < NRH; rl += nthr) {
+      for (int t = tid; t < NRH * (JM + 1); t += nthr) {
+        const int j = t / NRH, rl = t - j * NRH;
         double tx, ty, tz;
-        jmg_dipole_point<T, NR, JM>(sh, dip, rl, &tx, &ty, &tz);
+        jmg_dipole_point<T, NR, JM>(sh, dip, j, rl, &tx, &ty, &tz);
         const double m = mu[h * NRH + rl];
         dc[0] += m * tx;
         dc[1] += m * ty;
