@@ -110,9 +110,12 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
     sh[lds_row<NR, T>(b) + rl] = {T(0), T(0)};
     sh[lds_row<NR, T>(NB + b) + rl] = {T(0), T(0)};
   } else {
-    // one eigenvector k at a time: chi_k = sum_i Q[i][k] y_i for both states,
-    // its rotation increment, and dy_i += Q[i][k] dchi_k; qm holds Q
-    // column-major, so column k is contiguous
+    // Two passes, so that inputs and outputs are never live together.
+    // (1) per eigenvector k: chi_k = sum_i Q[i][k] y_i for both states and
+    //     its rotation increment dchi_k, stored at once over the block's LDS
+    //     slots (all inputs are in registers by then; qm holds Q
+    //     column-major, so column k is contiguous);
+    // (2) per row i: dy_i = sum_k Q[i][k] dchi_k, read back from those slots.
     const T* Qc = qm + jmg_q_off(JM, A);
     const T* x = xe + jmg_x_off(JM, A);
     // the rotation angles' sine and versine first, while little else is
@@ -120,14 +123,12 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
     T sn[N], vs[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) sin_vers(md * x[k], &sn[k], &vs[k]);
-    cx<T> g[N], e[N], og[N], oe[N];
+    cx<T> g[N], e[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const int j = A + i, b = j * j + mp + j;
       g[i] = sh[lds_row<NR, T>(b) + rl];
       e[i] = sh[lds_row<NR, T>(NB + b) + rl];
-      og[i] = {T(0), T(0)};
-      oe[i] = {T(0), T(0)};
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -139,19 +140,27 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
         ae = ae + cscale(e[i], qk[i]);
       }
       // exp(i th sigma_x) - 1 on (g, e): (-vers g + i sin e, i sin g - vers e)
-      const cx<T> dg = {-vs[k] * ag.x - sn[k] * ae.y, -vs[k] * ag.y + sn[k] * ae.x};
-      const cx<T> de = {-vs[k] * ae.x - sn[k] * ag.y, -vs[k] * ae.y + sn[k] * ag.x};
+      const int j = A + k, b = j * j + mp + j;   // slot k of the block
+      sh[lds_row<NR, T>(b) + rl] = {-vs[k] * ag.x - sn[k] * ae.y, -vs[k] * ag.y + sn[k] * ae.x};
+      sh[lds_row<NR, T>(NB + b) + rl] = {-vs[k] * ae.x - sn[k] * ag.y, -vs[k] * ae.y + sn[k] * ag.x};
+    }
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        og[i] = og[i] + cscale(dg, qk[i]);
-        oe[i] = oe[i] + cscale(de, qk[i]);
-      }
+    for (int k = 0; k < N; ++k) {
+      const int j = A + k, b = j * j + mp + j;
+      g[k] = sh[lds_row<NR, T>(b) + rl];
+      e[k] = sh[lds_row<NR, T>(NB + b) + rl];
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
+      cx<T> ag = cscale(g[0], Qc[i]), ae = cscale(e[0], Qc[i]);
+#pragma unroll
+      for (int k = 1; k < N; ++k) {
+        ag = ag + cscale(g[k], Qc[k * N + i]);
+        ae = ae + cscale(e[k], Qc[k * N + i]);
+      }
       const int j = A + i, b = j * j + mp + j;
-      sh[lds_row<NR, T>(b) + rl] = og[i];
-      sh[lds_row<NR, T>(NB + b) + rl] = oe[i];
+      sh[lds_row<NR, T>(b) + rl] = ag;
+      sh[lds_row<NR, T>(NB + b) + rl] = ae;
     }
   }
 }
