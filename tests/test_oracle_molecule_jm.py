@@ -30,7 +30,7 @@ def _models(j_max=1, n_r=64, dt=0.5, mass=1.0e4, absorb=0.0):
     return jm, m0
 
 
-@pytest.mark.parametrize("j_max", [1, 2, 3])
+@pytest.mark.parametrize("j_max", [1, 2, 3, 5])
 def test_direction_cosine_matrices(j_max):
     D = direction_cosines(j_max)
     basis = jm_basis(j_max)
@@ -89,11 +89,12 @@ def test_isotropy_of_the_induced_dipole():
     assert np.abs(across).max() < 1e-10 * np.abs(along).max()
 
 
-def test_coupling_is_the_dense_exponential_and_conserves_norm():
-    jm, _ = _models(j_max=1, n_r=32)
+@pytest.mark.parametrize("j_max,E", [(1, [0.03, -0.07, 0.05]), (3, [0.3, -0.2, 0.25]), (5, [-0.1, 0.4, -0.3])])
+def test_coupling_is_the_dense_exponential_and_conserves_norm(j_max, E):
+    jm, _ = _models(j_max=j_max, n_r=32)
     rng = np.random.default_rng(5)
     psi = rng.standard_normal((1, 2, jm.n_b, jm.n_r)) + 1j * rng.standard_normal((1, 2, jm.n_b, jm.n_r))
-    E3 = np.array([[0.03, -0.07, 0.05]])
+    E3 = np.array([E])
     out = jm.coupling(psi, E3)
     A = np.einsum("c,cab->ab", E3[0], jm.D)
     sx = np.array([[0, 1], [1, 0]])
