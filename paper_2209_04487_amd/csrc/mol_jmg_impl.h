@@ -34,20 +34,58 @@ struct JmgShape {
   static constexpr size_t rows_bytes =
       a16(sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))));
   static constexpr size_t ph_bytes = a16(sizeof(cx<T>) * (2 * JM + 1));
-  static constexpr size_t mt_bytes = a16(sizeof(T) * static_cast<size_t>(tab.n_jx + tab.n_q + tab.n_x));
+  // d^j(beta) twice (row-major and transposed), rows padded to 16 bytes
+  static constexpr int PADE = 16 / static_cast<int>(sizeof(T));
+  static constexpr int prow(int j) { return (2 * j + 1 + PADE - 1) / PADE * PADE; }
+  static constexpr int poff(int j) { return j == 0 ? 0 : poff(j - 1) + (2 * j - 1) * prow(j - 1); }
+  static constexpr int n_pad = poff(JM + 1);
+  static constexpr size_t mt_bytes = a16(sizeof(T) * static_cast<size_t>(2 * n_pad + tab.n_q + tab.n_x));
   static constexpr size_t red_bytes = 6 * 16 * sizeof(double);
   static constexpr size_t bytes = TBL::bytes + rows_bytes + ph_bytes + mt_bytes + red_bytes;
   static constexpr bool fits = threads <= 1024 && bytes <= 160 * 1024;
 };
 
 // ---------------------------------------------------------------- stages
+// Task t of pass p for thread tid: the passes alternate direction, so that
+// with tasks ordered from the heaviest down, a thread that drew a heavy task
+// in one pass draws a light one in the next.  Only for workgroups of whole
+// wavefronts: otherwise the reversed passes would split the tasks of one
+// block over two wavefronts.
+template <int NTHR>
+__device__ __forceinline__ int zigzag_task(int pass, int tid) {
+  return pass * NTHR + ((NTHR % 64 == 0 && (pass & 1)) ? NTHR - 1 - tid : tid);
+}
+
 // Rotation of the j block of state s at radial point rl: to the field frame
-// (BACK = false) or back (BACK = true).  dm holds d^j(beta) row-major
-// [m + j][m' + j] at jmg_jx_off(j); ph[m + JM] = e^{i m alpha}.
+// (BACK = false) or back (BACK = true).  dmr holds d^j(beta) row-major
+// [m + j][m' + j] and dmt its transpose, each row padded to 16 bytes at
+// JmgShape::poff(j), so that a row is read with 16-byte loads;
+// ph[m + JM] = e^{i m alpha}.
+template <typename T>
+__device__ __forceinline__ void load_row16(T* dst, const T* src, int n) {
+  if constexpr (sizeof(T) == 4) {
+    for (int c = 0; c < n; c += 4) {
+      const float4 w = *reinterpret_cast<const float4*>(src + c);
+      dst[c] = w.x;
+      dst[c + 1] = w.y;
+      dst[c + 2] = w.z;
+      dst[c + 3] = w.w;
+    }
+  } else {
+    for (int c = 0; c < n; c += 2) {
+      const double2 w = *reinterpret_cast<const double2*>(src + c);
+      dst[c] = w.x;
+      dst[c + 1] = w.y;
+    }
+  }
+}
+
 template <typename T, int NR, int JM, int J, bool BACK>
-__device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dm, const cx<T>* ph, int s, int rl) {
-  constexpr int N = 2 * J + 1, NB = (JM + 1) * (JM + 1);
-  const T* d = dm + jmg_jx_off(J);
+__device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dmr, const T* dmt, const cx<T>* ph, int s,
+                                              int rl) {
+  typedef JmgShape<T, NR, JM> S;
+  constexpr int N = 2 * J + 1, NB = (JM + 1) * (JM + 1), P = S::prow(J);
+  const T* d = (BACK ? dmr : dmt) + S::poff(J);
   cx<T>* row0 = sh + rl;
   const int l0 = s * NB + J * J;
   // the inputs stay in registers; each output goes to LDS as it is formed
@@ -58,44 +96,46 @@ __device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dm, const cx<T
   if constexpr (!BACK) {
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = cmul(ph[JM - J + i], u[i]);
+  }
 #pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-      cx<T> acc = cscale(u[0], d[k]);
+  for (int o = 0; o < N; ++o) {
+    // y_o = sum_i d[i][o] u_i (to the field frame, row o of the transpose)
+    // or sum_i d[o][i] u_i (back, row o)
+    T dv[P];
 #pragma unroll
-      for (int i = 1; i < N; ++i) acc = acc + cscale(u[i], d[i * N + k]);
-      row0[lds_row<NR, T>(l0 + k)] = acc;
-    }
-  } else {
-#pragma unroll 1
-    for (int i = 0; i < N; ++i) {
-      cx<T> acc = cscale(u[0], d[i * N]);
+    for (int c = 0; c < P; c += S::PADE) load_row16(dv + c, d + o * P + c, S::PADE);
+    cx<T> acc = cscale(u[0], dv[0]);
 #pragma unroll
-      for (int k = 1; k < N; ++k) acc = acc + cscale(u[k], d[i * N + k]);
-      row0[lds_row<NR, T>(l0 + i)] = cmul_conj(acc, ph[JM - J + i]);
-    }
+    for (int i = 1; i < N; ++i) acc = acc + cscale(u[i], dv[i]);
+    if constexpr (BACK) acc = cmul_conj(acc, ph[JM - J + o]);
+    row0[lds_row<NR, T>(l0 + o)] = acc;
   }
 }
 
 template <typename T, int NR, int JM, int J, bool BACK>
-__device__ __forceinline__ void jmg_rot_dispatch(int j, cx<T>* sh, const T* dm, const cx<T>* ph, int s, int rl) {
+__device__ __forceinline__ void jmg_rot_dispatch(int j, cx<T>* sh, const T* dmr, const T* dmt, const cx<T>* ph,
+                                                 int s, int rl) {
   if (j == J)
-    jmg_rot_block<T, NR, JM, J, BACK>(sh, dm, ph, s, rl);
+    jmg_rot_block<T, NR, JM, J, BACK>(sh, dmr, dmt, ph, s, rl);
   else if constexpr (J > 1)
-    jmg_rot_dispatch<T, NR, JM, J - 1, BACK>(j, sh, dm, ph, s, rl);
+    jmg_rot_dispatch<T, NR, JM, J - 1, BACK>(j, sh, dmr, dmt, ph, s, rl);
 }
 
 // All (state, j >= 1, r) tasks of a round; the j = 0 block is unchanged by
 // the rotation.  Tasks are ordered by decreasing j so that the heavy blocks
 // spread over the workgroup.
 template <typename T, int NR, int JM, bool BACK>
-__device__ __forceinline__ void jmg_rotate(cx<T>* sh, const T* dm, const cx<T>* ph, int tid, int nthr) {
+__device__ __forceinline__ void jmg_rotate(cx<T>* sh, const T* dmr, const T* dmt, const cx<T>* ph, int tid,
+                                           int nthr) {
   constexpr int NRH = JmgShape<T, NR, JM>::NRH;
   constexpr int NT = 2 * JM * NRH;
-  for (int t = tid; t < NT; t += nthr) {
+  for (int pass = 0; pass * nthr < NT; ++pass) {
+    const int t = zigzag_task<JmgShape<T, NR, JM>::threads>(pass, tid);
+    if (t >= NT) continue;
     const int jr = t / (2 * NRH);
     const int rem = t - jr * 2 * NRH;
     const int s = rem / NRH;
-    jmg_rot_dispatch<T, NR, JM, JM, BACK>(JM - jr, sh, dm, ph, s, rem - s * NRH);
+    jmg_rot_dispatch<T, NR, JM, JM, BACK>(JM - jr, sh, dmr, dmt, ph, s, rem - s * NRH);
   }
 }
 
@@ -180,7 +220,9 @@ __device__ __forceinline__ void jmg_couple(cx<T>* sh, const T* qm, const T* xe, 
                                            int nthr) {
   constexpr int NRH = JmgShape<T, NR, JM>::NRH;
   constexpr int NT = (2 * JM + 1) * NRH;
-  for (int t = tid; t < NT; t += nthr) {
+  for (int pass = 0; pass * nthr < NT; ++pass) {
+    const int t = zigzag_task<JmgShape<T, NR, JM>::threads>(pass, tid);
+    if (t >= NT) continue;
     const int u = t / NRH;
     const int rl = t - u * NRH;
     const int a = (u + 1) >> 1;
@@ -256,8 +298,9 @@ void mol_jmg_kernel(MolArgs a) {
   T* mask_s = reinterpret_cast<T*>(tw_s + TBL::tw_elems);
   cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TBL::bytes);
   cx<T>* ph = reinterpret_cast<cx<T>*>(smem + TBL::bytes + S::rows_bytes);
-  T* dm = reinterpret_cast<T*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes);
-  T* qm = dm + TB.n_jx;
+  T* dmr = reinterpret_cast<T*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes);
+  T* dmt = dmr + S::n_pad;
+  T* qm = dmt + S::n_pad;
   T* xe = qm + TB.n_q;
   double* red = reinterpret_cast<double*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes + S::mt_bytes);
 
@@ -322,10 +365,10 @@ void mol_jmg_kernel(MolArgs a) {
       }
       ph[tid] = {static_cast<T>(px), static_cast<T>(m < 0 ? -py : py)};
     }
-    for (int t = tid; t < TB.n_jx; t += nthr) {
-      int j = 0;
-      while (t >= jmg_jx_off(j + 1)) ++j;
-      const int n = 2 * j + 1, o = t - jmg_jx_off(j), ra = o / n, rc = o - ra * n;
+    // d^j_{m m'}(beta) = sum_k O_{m k} O_{m' k} cos(pi/2 (m' - m) - beta mu_k),
+    // mu_k = k - j: ra, rc are the rows of m and m' in O
+    auto wigner_d = [&](int j, int ra, int rc) {
+      const int n = 2 * j + 1;
       const double* O = tg + TB.jx + jmg_jx_off(j);
       // cos(pi/2 (m' - m) - beta mu) = cA cos(mu beta) + sA sin(mu beta)
       const int dq = (rc - ra) & 3;
@@ -340,7 +383,17 @@ void mol_jmg_kernel(MolArgs a) {
         acc += O[ra * n + j + mu_] * O[rc * n + j + mu_] * (cA * wc + sA * wsn) +
                O[ra * n + j - mu_] * O[rc * n + j - mu_] * (cA * wc - sA * wsn);
       }
-      dm[t] = static_cast<T>(acc);
+      return acc;
+    };
+    // both padded layouts: entry (row r, column c) of block j is d[r][c]
+    // in dmr and d[c][r] in dmt; the padding columns are zero
+    for (int t = tid; t < S::n_pad; t += nthr) {
+      int j = 0;
+      while (t >= S::poff(j + 1)) ++j;
+      const int P = S::prow(j), o = t - S::poff(j), r = o / P, c = o - r * P;
+      const bool in = c < 2 * j + 1;
+      dmr[t] = in ? static_cast<T>(wigner_d(j, r, c)) : T(0);
+      dmt[t] = in ? static_cast<T>(wigner_d(j, c, r)) : T(0);
     }
     // Q^(a) column-major in LDS (the workspace holds it row-major)
     for (int t = tid; t < TB.n_q; t += nthr) {
@@ -380,11 +433,11 @@ void mol_jmg_kernel(MolArgs a) {
         slot[q + R2 * pp] = vv[p];
       }
       __syncthreads();
-      jmg_rotate<T, NR, JM, false>(sh, dm, ph, tid, nthr);
+      jmg_rotate<T, NR, JM, false>(sh, dmr, dmt, ph, tid, nthr);
       __syncthreads();
       jmg_couple<T, NR, JM>(sh, qm, xe, mudt + h * NRH, tid, nthr);
       __syncthreads();
-      jmg_rotate<T, NR, JM, true>(sh, dm, ph, tid, nthr);
+      jmg_rotate<T, NR, JM, true>(sh, dmr, dmt, ph, tid, nthr);
       __syncthreads();
 #pragma unroll
       for (int pp = 0; pp < PH; ++pp) {
@@ -420,8 +473,10 @@ void mol_jmg_kernel(MolArgs a) {
 #pragma unroll
       for (int pp = 0; pp < PH; ++pp) slot[q + R2 * pp] = vv[h * PH + pp];
       __syncthreads();
-      for (int t = tid; t < NRH * (JM + 1); t += nthr) {
-        const int j = t / NRH, rl = t - j * NRH;
+      for (int pass = 0; pass * nthr < NRH * (JM + 1); ++pass) {
+        const int t = zigzag_task<JmgShape<T, NR, JM>::threads>(pass, tid);
+        if (t >= NRH * (JM + 1)) continue;
+        const int j = JM - t / NRH, rl = t - (JM - j) * NRH;   // heaviest j first
         double tx, ty, tz;
         jmg_dipole_point<T, NR, JM>(sh, dip, j, rl, &tx, &ty, &tz);
         const double m = mu[h * NRH + rl];
