@@ -14,7 +14,9 @@ times.
   at any size (norm + absorbed = 1, the gathered field equals E_x at the
   molecule's edge, each cell's polarisation equals its molecules' dipole sum);
 - the molecule -> cell maps of the 100,000- and 700,000-molecule workloads,
-  bit for bit against the oracle.
+  bit for bit against the oracle;
+- the (j, m) basis at j_max = 5 over 691,200 molecules (FP32): a seeded
+  sample of planted random states against the oracle.
 """
 
 import numpy as np
@@ -65,6 +67,43 @@ def test_full_batch_sampled_molecules(name, prec):
     # it is round-off of the far tail, ~eps^2 of the working precision
     ab_gpu = mols.absorbed.cpu().numpy()[sample]
     np.testing.assert_allclose(ab_gpu, ab, rtol=10 * TOL[prec], atol=1e-24 if prec == "fp64" else 1e-10)
+
+
+def test_full_jm_general_sampled_molecules():
+    """The (j, m) basis at j_max = 5 over the paper's 691,200 molecules
+    (N_r = 256, FP32, one single-step launch as in the coupled step): seeded
+    random states planted in a sample of molecules (the last workgroup
+    included), seeded fields of all directions, element by element against
+    the oracle."""
+    from gpu_helpers import random_state
+    from oracle.molecule_jm import jm_model_from_config
+    from paper_2209_04487_amd import msqd
+    torch.cuda.empty_cache()
+    cfg = get_config("cfg2").replace(n_mol=691_200, j_max=5, basis="jm", n_r=256)
+    nb = 36
+    banner(f"full batch (j, m) j_max=5 fp32: {cfg.n_mol} molecules, 1 step")
+    rng = np.random.default_rng(23)
+    E3 = rng.uniform(-2e-3, 2e-3, (cfg.n_mol, 3))
+    sample = np.sort(rng.choice(cfg.n_mol, 12, replace=False))
+    sample[-1] = cfg.n_mol - 1                      # the last workgroup
+    E3[sample[0]] = [0.3, -0.2, 0.25]               # a strong field (large-angle branch)
+    E3[sample[1]] = [0.0, 0.0, -1e-3]               # along -z
+    mols = msqd.Molecules.from_config(cfg, prec="fp32")
+    dr = (cfg.r_max - cfg.r_min) / cfg.n_r
+    psi = random_state(29, len(sample), nb, cfg.n_r, dr).astype(np.complex64)
+    idx = torch.as_tensor(sample, device="cuda")
+    mols.psi[idx] = torch.as_tensor(psi, device="cuda")
+    mols.step(torch.as_tensor(E3, device="cuda"))
+    torch.cuda.synchronize()
+    ug, ue, mu = potentials(cfg)
+    om = jm_model_from_config(cfg, ug, ue, mu)
+    p, ab = om.step(psi.astype(np.complex128), E3[sample], np.zeros(len(sample)))
+    got = mols.psi[idx].to(torch.complex128).cpu().numpy()
+    assert rel_err(got, p) < TOL["fp32"]
+    assert rel_err(mols.d[idx].cpu().numpy(), om.dipole(p)) < 10 * TOL["fp32"]
+    np.testing.assert_allclose(mols.absorbed[idx].cpu().numpy(), ab, rtol=10 * TOL["fp32"], atol=1e-10)
+    del mols
+    torch.cuda.empty_cache()
 
 
 def test_full_grid_fields_fp64():
