@@ -244,29 +244,27 @@ __device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* 
     return cx<double>{static_cast<double>(v.x), static_cast<double>(v.y)};
   };
   double z = 0.0, pr = 0.0, pi = 0.0;
-  {
 #pragma unroll 1
-    for (int m = -j; m <= j; ++m) {
-      const int b = j * j + m + j;
-      const cx<double> gb = ld(b), eb = ld(NB + b);
-      if (j < JM) {
-        const int bz = (j + 1) * (j + 1) + m + j + 1;        // (j+1, m)
-        const int bp = bz + 1;                               // (j+1, m+1)
-        const cx<double> gz = ld(bz), ez = ld(NB + bz);
-        z += dip[3 * b] * ((gz.x * eb.x + gz.y * eb.y) + (gb.x * ez.x + gb.y * ez.y));
-        const cx<double> gp = ld(bp), ep = ld(NB + bp);
-        const double c = dip[3 * b + 1];
-        // conj(g_p) e_b + conj(e_p) g_b
-        pr += c * ((gp.x * eb.x + gp.y * eb.y) + (ep.x * gb.x + ep.y * gb.y));
-        pi += c * ((gp.x * eb.y - gp.y * eb.x) + (ep.x * gb.y - ep.y * gb.x));
-      }
-      if (m + 1 <= j - 1) {
-        const int bm = (j - 1) * (j - 1) + m + 1 + j - 1;    // (j-1, m+1)
-        const cx<double> gm = ld(bm), em = ld(NB + bm);
-        const double c = dip[3 * b + 2];
-        pr += c * ((gm.x * eb.x + gm.y * eb.y) + (em.x * gb.x + em.y * gb.y));
-        pi += c * ((gm.x * eb.y - gm.y * eb.x) + (em.x * gb.y - em.y * gb.x));
-      }
+  for (int m = -j; m <= j; ++m) {
+    const int b = j * j + m + j;
+    const cx<double> gb = ld(b), eb = ld(NB + b);
+    if (j < JM) {
+      const int bz = (j + 1) * (j + 1) + m + j + 1;        // (j+1, m)
+      const int bp = bz + 1;                               // (j+1, m+1)
+      const cx<double> gz = ld(bz), ez = ld(NB + bz);
+      z += dip[3 * b] * ((gz.x * eb.x + gz.y * eb.y) + (gb.x * ez.x + gb.y * ez.y));
+      const cx<double> gp = ld(bp), ep = ld(NB + bp);
+      const double c = dip[3 * b + 1];
+      // conj(g_p) e_b + conj(e_p) g_b
+      pr += c * ((gp.x * eb.x + gp.y * eb.y) + (ep.x * gb.x + ep.y * gb.y));
+      pi += c * ((gp.x * eb.y - gp.y * eb.x) + (ep.x * gb.y - ep.y * gb.x));
+    }
+    if (m + 1 <= j - 1) {
+      const int bm = (j - 1) * (j - 1) + m + 1 + j - 1;    // (j-1, m+1)
+      const cx<double> gm = ld(bm), em = ld(NB + bm);
+      const double c = dip[3 * b + 2];
+      pr += c * ((gm.x * eb.x + gm.y * eb.y) + (em.x * gb.x + em.y * gb.y));
+      pi += c * ((gm.x * eb.y - gm.y * eb.x) + (em.x * gb.y - em.y * gb.x));
     }
   }
   *tx = 0.5 * pr;
