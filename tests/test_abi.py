@@ -166,8 +166,12 @@ def test_jm_basis_validation(msqd):
     for n_r, jm, prec in [(128, 0, msqd.FP64), (128, 6, msqd.FP32)]:
         assert ws(n_r, jm, prec) == 0
         assert "1 <= j_max <= 5" in msqd.last_error()
-    # complex128 at n_r = 256: 32 lanes x 36 lines exceed one workgroup
-    assert ws(256, 5) == 0
-    assert "too large for one workgroup" in msqd.last_error()
+    # complex128 at n_r = 256 (16 lanes x 72 lines) and complex64 at n_r = 512
+    # (16 lanes x 72 lines) exceed one workgroup; complex128 at n_r = 256 with
+    # j_max = 4 exceeds its LDS
+    for n_r, jm, prec in [(256, 5, msqd.FP64), (512, 5, msqd.FP32), (256, 4, msqd.FP64)]:
+        assert ws(n_r, jm, prec) == 0
+        assert "too large for one workgroup" in msqd.last_error()
+    assert ws(512, 4, msqd.FP32) > 0 and ws(512, 2, msqd.FP64) > 0 and ws(256, 3, msqd.FP64) > 0
     d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 7)
     assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0

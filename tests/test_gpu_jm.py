@@ -60,7 +60,8 @@ def test_jm_step_matches_oracle(prec, n_r, n_mol, n_steps):
                                                           ("fp64", 256, 3, 5, 2), ("fp64", 64, 4, 6, 1),
                                                           ("fp32", 256, 5, 6, 1), ("fp32", 256, 5, 6, 2),
                                                           ("fp32", 256, 2, 6, 1), ("mixed", 128, 4, 6, 1),
-                                                          ("fp32", 512, 3, 6, 1), ("fp32", 64, 3, 6, 3)])
+                                                          ("fp32", 512, 3, 6, 1), ("fp32", 64, 3, 6, 3),
+                                                          ("fp64", 512, 2, 5, 1), ("fp32", 512, 4, 5, 1)])
 def test_jm_general_step_matches_oracle(prec, n_r, j_max, n_mol, n_steps):
     from paper_2209_04487_amd import msqd
     cfg = get_config("cfg0", n_r=n_r, j_max=j_max, basis="jm", n_mol=n_mol)
