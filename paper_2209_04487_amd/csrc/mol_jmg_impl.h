@@ -23,27 +23,58 @@
 
 namespace msqd {
 
-template <typename T, int NR, int JM>
-struct JmgShape {
-  static constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
-  static constexpr int NB = (JM + 1) * (JM + 1), L = 2 * NB, threads = L * R2;
-  static constexpr int SP = fwd_split<NR, T>(), NRH = NR / SP;
-  typedef StagedTables<NR, T, true, false> TBL;
-  static constexpr JmgTab tab = jmg_tab(JM);
+// LDS of the per-molecule coupling tables: the phases e^{i m alpha}; d^j(beta)
+// twice (row-major and transposed, rows padded to 16 bytes); Q and the
+// scaled nodes; and the workgroup reduction scratch.
+template <typename T, int JM>
+struct JmgTabShape {
   static constexpr size_t a16(size_t b) { return (b + 15) / 16 * 16; }
-  static constexpr size_t rows_bytes =
-      a16(sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))));
-  static constexpr size_t ph_bytes = a16(sizeof(cx<T>) * (2 * JM + 1));
-  // d^j(beta) twice (row-major and transposed), rows padded to 16 bytes
+  static constexpr JmgTab tab = jmg_tab(JM);
   static constexpr int PADE = 16 / static_cast<int>(sizeof(T));
   static constexpr int prow(int j) { return (2 * j + 1 + PADE - 1) / PADE * PADE; }
   static constexpr int poff(int j) { return j == 0 ? 0 : poff(j - 1) + (2 * j - 1) * prow(j - 1); }
   static constexpr int n_pad = poff(JM + 1);
+  static constexpr size_t ph_bytes = a16(sizeof(cx<T>) * (2 * JM + 1));
   static constexpr size_t mt_bytes = a16(sizeof(T) * static_cast<size_t>(2 * n_pad + tab.n_q + tab.n_x));
   static constexpr size_t red_bytes = 6 * 16 * sizeof(double);
-  static constexpr size_t bytes = TBL::bytes + rows_bytes + ph_bytes + mt_bytes + red_bytes;
+  static constexpr size_t bytes = ph_bytes + mt_bytes + red_bytes;
+};
+
+// Radial rounds of the line exchange.  Complex64 workgroups for j_max >= 4
+// hold one molecule per CU whatever their LDS (their registers exclude a
+// second), so they exchange all radial points in one round when the LDS
+// allows it: half the barriers per step and twice the tasks per stage.  The
+// others use the rounds of the m = 0 step, which keep the LDS of a
+// workgroup small enough for several per CU.
+template <typename T, int NR, int JM>
+struct JmgSplit {
+  static constexpr int R2 = FftShape<NR, T>::R2, L = 2 * (JM + 1) * (JM + 1);
+  static constexpr size_t one_round = StagedTables<NR, T, true, false>::bytes +
+                                      JmgTabShape<T, JM>::a16(sizeof(cx<T>) * static_cast<size_t>(lds_line_start(
+                                                                                   L, NR + R2, sizeof(cx<T>)))) +
+                                      JmgTabShape<T, JM>::bytes;
+  static constexpr int value = (sizeof(T) == 4 && JM >= 4 && one_round <= 160 * 1024) ? 1 : fwd_split<NR, T>();
+};
+
+template <typename T, int NR, int JM>
+struct JmgShape : JmgTabShape<T, JM> {
+  typedef JmgTabShape<T, JM> TS;
+  static constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
+  static constexpr int NB = (JM + 1) * (JM + 1), L = 2 * NB, threads = L * R2;
+  static constexpr int SP = JmgSplit<T, NR, JM>::value, NRH = NR / SP;
+  static constexpr int LS = NRH + R2;   // line stride (elements) of the LDS rows
+  typedef StagedTables<NR, T, true, false> TBL;
+  static constexpr size_t rows_bytes =
+      TS::a16(sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, LS, sizeof(cx<T>))));
+  static constexpr size_t bytes = TBL::bytes + rows_bytes + TS::bytes;
   static constexpr bool fits = threads <= 1024 && bytes <= 160 * 1024;
 };
+
+// Start (elements) of line `line` in the LDS rows.
+template <typename T, int NR, int JM>
+__device__ __forceinline__ int jmg_row(int line) {
+  return lds_line_start(line, JmgShape<T, NR, JM>::LS, static_cast<int>(sizeof(cx<T>)));
+}
 
 // ---------------------------------------------------------------- stages
 // Task t of pass p for thread tid: the passes alternate direction, so that
@@ -92,7 +123,7 @@ __device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dmr, const T* 
   // (in place: the inputs were read before the first store)
   cx<T> u[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) u[i] = row0[lds_row<NR, T>(l0 + i)];
+  for (int i = 0; i < N; ++i) u[i] = row0[jmg_row<T, NR, JM>(l0 + i)];
   if constexpr (!BACK) {
 #pragma unroll
     for (int i = 0; i < N; ++i) u[i] = cmul(ph[JM - J + i], u[i]);
@@ -108,7 +139,7 @@ __device__ __forceinline__ void jmg_rot_block(cx<T>* sh, const T* dmr, const T* 
 #pragma unroll
     for (int i = 1; i < N; ++i) acc = acc + cscale(u[i], dv[i]);
     if constexpr (BACK) acc = cmul_conj(acc, ph[JM - J + o]);
-    row0[lds_row<NR, T>(l0 + o)] = acc;
+    row0[jmg_row<T, NR, JM>(l0 + o)] = acc;
   }
 }
 
@@ -147,8 +178,8 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
   constexpr int N = JM + 1 - A, NB = (JM + 1) * (JM + 1);
   if constexpr (A == JM) {
     const int b = JM * JM + mp + JM;
-    sh[lds_row<NR, T>(b) + rl] = {T(0), T(0)};
-    sh[lds_row<NR, T>(NB + b) + rl] = {T(0), T(0)};
+    sh[jmg_row<T, NR, JM>(b) + rl] = {T(0), T(0)};
+    sh[jmg_row<T, NR, JM>(NB + b) + rl] = {T(0), T(0)};
   } else {
     // Two passes, so that inputs and outputs are never live together.
     // (1) per eigenvector k: chi_k = sum_i Q[i][k] y_i for both states and
@@ -167,8 +198,8 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const int j = A + i, b = j * j + mp + j;
-      g[i] = sh[lds_row<NR, T>(b) + rl];
-      e[i] = sh[lds_row<NR, T>(NB + b) + rl];
+      g[i] = sh[jmg_row<T, NR, JM>(b) + rl];
+      e[i] = sh[jmg_row<T, NR, JM>(NB + b) + rl];
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -181,14 +212,14 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
       }
       // exp(i th sigma_x) - 1 on (g, e): (-vers g + i sin e, i sin g - vers e)
       const int j = A + k, b = j * j + mp + j;   // slot k of the block
-      sh[lds_row<NR, T>(b) + rl] = {-vs[k] * ag.x - sn[k] * ae.y, -vs[k] * ag.y + sn[k] * ae.x};
-      sh[lds_row<NR, T>(NB + b) + rl] = {-vs[k] * ae.x - sn[k] * ag.y, -vs[k] * ae.y + sn[k] * ag.x};
+      sh[jmg_row<T, NR, JM>(b) + rl] = {-vs[k] * ag.x - sn[k] * ae.y, -vs[k] * ag.y + sn[k] * ae.x};
+      sh[jmg_row<T, NR, JM>(NB + b) + rl] = {-vs[k] * ae.x - sn[k] * ag.y, -vs[k] * ae.y + sn[k] * ag.x};
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const int j = A + k, b = j * j + mp + j;
-      g[k] = sh[lds_row<NR, T>(b) + rl];
-      e[k] = sh[lds_row<NR, T>(NB + b) + rl];
+      g[k] = sh[jmg_row<T, NR, JM>(b) + rl];
+      e[k] = sh[jmg_row<T, NR, JM>(NB + b) + rl];
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -199,8 +230,8 @@ __device__ __forceinline__ void jmg_couple_block(cx<T>* sh, const T* qm, const T
         ae = ae + cscale(e[k], Qc[k * N + i]);
       }
       const int j = A + i, b = j * j + mp + j;
-      sh[lds_row<NR, T>(b) + rl] = ag;
-      sh[lds_row<NR, T>(NB + b) + rl] = ae;
+      sh[jmg_row<T, NR, JM>(b) + rl] = ag;
+      sh[jmg_row<T, NR, JM>(NB + b) + rl] = ae;
     }
   }
 }
@@ -240,7 +271,7 @@ __device__ __forceinline__ void jmg_dipole_point(const cx<T>* sh, const double* 
                                                  double* ty, double* tz) {
   constexpr int NB = (JM + 1) * (JM + 1);
   auto ld = [&](int line) {
-    const cx<T> v = sh[lds_row<NR, T>(line) + rl];
+    const cx<T> v = sh[jmg_row<T, NR, JM>(line) + rl];
     return cx<double>{static_cast<double>(v.x), static_cast<double>(v.y)};
   };
   double z = 0.0, pr = 0.0, pi = 0.0;
@@ -340,7 +371,7 @@ void mol_jmg_kernel(MolArgs a) {
   }
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * S::L * NR;
-  cx<T>* slot = sh + lds_row<NR, T>(line);
+  cx<T>* slot = sh + jmg_row<T, NR, JM>(line);
   const int loff = line * NR + q;
   const int voff = (st * a.nj + jl) * NR + q;   // potential phases depend on (state, j)
   cx<T> vv[R1];
