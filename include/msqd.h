@@ -107,6 +107,25 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
             const double* psi0, void* ws, size_t ws_bytes, void* psi, double* absorbed,
             void* stream);
 
+/* Host only (no device, no stream): the tables of the general (j, m)
+ * coupling (2 <= j_max <= 5) that qd_init places in the workspace, as
+ * doubles, for inspection and host-side checks.  Layout, in order:
+ *   O^(j), j = 0..j_max: eigenvectors of J_x on the block j, (2j+1)^2 each,
+ *     row m + j, column k for the eigenvalue k - j (the Wigner matrices
+ *     follow as d^j_{m m'}(beta) = sum_k O_{mk} O_{m'k} cos(pi/2 (m'-m) - beta (k-j)));
+ *   Q^(a), a = |m'| = 0..j_max: eigenvectors of cos(theta) on the states
+ *     j = a..j_max of one m', (j_max+1-a)^2 each, row j - a, column k;
+ *   x^(a): the matching eigenvalues, ascending, j_max+1-a each;
+ *   per basis state b = j^2 + m + j: <j+1,m|cos th|j,m>,
+ *     <j+1,m+1|sin th e^{i ph}|j,m>, <j-1,m+1|sin th e^{i ph}|j,m> (0 where
+ *     the target state lies outside the basis).
+ * qd_jm_tables_size: the number of doubles (0 if j_max is outside 2..5).
+ * Errors: MSQD_EUNSUP (j_max), MSQD_EINVAL (NULL), MSQD_ESHAPE (n_out too
+ * small), MSQD_EDEVICE (an eigen-decomposition failed to converge; not
+ * expected for these sizes). */
+size_t qd_jm_tables_size(int32_t j_max);
+int qd_jm_tables(int32_t j_max, double* out, size_t n_out);
+
 /* Advance every molecule n_steps split-operator steps (K/2 V/2 C(E) V/2 K/2,
  * then the absorber) under a field held constant over the call.
  * E_mol: device [n_mol] float64 field along the quantisation axis (au).

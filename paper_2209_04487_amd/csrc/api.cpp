@@ -331,6 +331,20 @@ size_t qd_workspace_bytes(const qd_desc* d) {
   return qd_layout(d->n_r, d->j_max + 1).total + qd_jmg_bytes(d);
 }
 
+size_t qd_jm_tables_size(int32_t j_max) {
+  return (j_max >= 2 && j_max <= kJmgMax) ? static_cast<size_t>(jmg_tab(j_max).n) : 0;
+}
+
+int qd_jm_tables(int32_t j_max, double* out, size_t n_out) {
+  if (j_max < 2 || j_max > kJmgMax)
+    return fail(MSQD_EUNSUP, "the general (j, m) tables exist for 2 <= j_max <= " + std::to_string(kJmgMax));
+  if (!out) return fail(MSQD_EINVAL, "output pointer is NULL");
+  const size_t need = qd_jm_tables_size(j_max);
+  if (n_out < need) return fail(MSQD_ESHAPE, "output holds fewer than " + std::to_string(need) + " doubles");
+  if (!fill_jmg_tables(j_max, out)) return fail(MSQD_EDEVICE, "eigen-decomposition did not converge");
+  return MSQD_OK;
+}
+
 int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double* mu12,
             const double* psi0, void* ws, size_t ws_bytes, void* psi, double* absorbed,
             void* stream) {

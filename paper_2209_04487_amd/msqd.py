@@ -36,7 +36,8 @@ EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
-           "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout"]
+           "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
+           "qd_jm_tables"]
 
 
 class MsqdError(RuntimeError):
@@ -121,6 +122,8 @@ _sigs = {
     "qd_step": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]),
     "dipole_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "msqd_check_status": (C.c_int, [_vp, _vp]),
+    "qd_jm_tables_size": (C.c_size_t, [C.c_int32]),
+    "qd_jm_tables": (C.c_int, [C.c_int32, _dp, C.c_size_t]),
     "fdtd_workspace_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_psi_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_dft_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
@@ -203,6 +206,16 @@ def qd_step(d, ws, psi, E_mol, absorbed, d_mol=None, n_steps=1, stream=None):
 def dipole_readout(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=None, stream=None):
     return _check(lib.dipole_readout(C.byref(d), _ptr(ws), _ptr(psi), _ptr(absorbed), _ptr(d_mol),
                                      _ptr(norm_mol), _ptr(yield_mol), stream or current_stream()))
+
+
+def jm_tables(j_max):
+    """The host-built tables of the general (j, m) coupling (2 <= j_max <= 5)
+    as a float64 array, in the layout include/msqd.h documents for
+    qd_jm_tables."""
+    n = lib.qd_jm_tables_size(int(j_max))
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    _check(lib.qd_jm_tables(int(j_max), out.ctypes.data_as(_dp), n))
+    return out[:n]
 
 
 def check_status(ws, stream=None):
@@ -622,5 +635,5 @@ def version():
 
 
 __all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "CarrierBatch", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
-           "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status",
+           "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status", "jm_tables",
            "MsqdError", "lib", "LIB_PATH", "EXPORTS"]
