@@ -9,12 +9,20 @@
   along z or along (1, 1, 1)/sqrt(3) induces the same dipole along the field
   and none across it;
 - the coupling factor equals a dense matrix exponential; without absorber the
-  norm is conserved.
+  norm is conserved;
+- rotational covariance: rotating the initial state (the rotation's matrix
+  on each j block taken by quadrature of the spherical harmonics at rotated
+  points, not from the direction cosines) and the field by the same rotation
+  rotates the stepped state, and the dipole turns as a vector.
 """
 
 import numpy as np
 import pytest
 from scipy.linalg import expm
+
+from numpy.polynomial.legendre import leggauss
+from scipy.spatial.transform import Rotation
+from scipy.special import sph_harm_y
 
 from oracle.molecule import MoleculeModel, coupling_cj
 from oracle.molecule_jm import MoleculeJM, direction_cosines, jm_basis
@@ -147,3 +155,46 @@ def test_coupled_jm_energy_balance_with_transverse_field():
         imb.append(((f1 + m1) - (f0 + m0)) / (m1 - m0))
     assert abs(imb[0]) < 0.25, imb
     assert 1.6 < imb[0] / imb[1] < 2.4, imb
+
+
+def _rotation_matrix_on_basis(j_max, R):
+    """U[(j, m'), (j, m)] = int conj(Y_jm') (Y_jm o R^-1) dOmega by a product
+    quadrature exact for these degrees: the action f -> f(R^-1 r) of the
+    rotation R on the truncated basis."""
+    basis = jm_basis(j_max)
+    n_t = n_p = 2 * j_max + 4
+    x, w = leggauss(n_t)
+    th = np.arccos(x)
+    ph = 2.0 * np.pi * np.arange(n_p) / n_p
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    W = w[:, None] * (2.0 * np.pi / n_p)
+    pts = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], axis=-1)
+    back = pts @ R            # rows are R^T r = R^-1 r
+    th2 = np.arccos(np.clip(back[..., 2], -1.0, 1.0))
+    ph2 = np.arctan2(back[..., 1], back[..., 0])
+    U = np.zeros((len(basis), len(basis)), complex)
+    for a, (j1, m1) in enumerate(basis):
+        y1 = np.conj(sph_harm_y(j1, m1, TH, PH))
+        for b, (j2, m2) in enumerate(basis):
+            if j1 == j2:
+                U[a, b] = np.sum(W * y1 * sph_harm_y(j2, m2, th2, ph2))
+    return U
+
+
+@pytest.mark.parametrize("j_max", [1, 3])
+def test_rotational_covariance(j_max):
+    jm, _ = _models(j_max=j_max, n_r=32)
+    rng = np.random.default_rng(11 + j_max)
+    R = Rotation.random(random_state=rng.integers(1 << 31)).as_matrix()
+    U = _rotation_matrix_on_basis(j_max, R)
+    assert np.abs(U.conj().T @ U - np.eye(jm.n_b)).max() < 1e-12
+    psi = rng.standard_normal((1, 2, jm.n_b, jm.n_r)) + 1j * rng.standard_normal((1, 2, jm.n_b, jm.n_r))
+    E = np.array([[0.05, -0.08, 0.03]])
+    p1, _ = jm.step(psi, E, np.zeros(1))
+    psi_r = np.einsum("ab,msbr->msar", U, psi)
+    p2, _ = jm.step(psi_r, E @ R.T, np.zeros(1))
+    np.testing.assert_allclose(p2, np.einsum("ab,msbr->msar", U, p1), atol=1e-11)
+    np.testing.assert_allclose(jm.dipole(p2)[0], R @ jm.dipole(p1)[0], atol=1e-11)
+    # and a field that is not a rotation of the first one gives a different state
+    p3, _ = jm.step(psi_r, E, np.zeros(1))
+    assert np.abs(p3 - p2).max() > 1e-4
