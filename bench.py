@@ -624,6 +624,17 @@ def main():
     sten_ms = time_stencil(cfg, "mixed", launches)
     cells = cfg.nx * cfg.ny * cfg.nz
     sten_gbs = stencil_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
+    # cell-updates/s of the other grids: the differentiation cell (FP32), the
+    # nanohole film (precision form) and the SRR grid in FP64
+    sten_grids = {}
+    for name, pr in (("cfg3", "fp32"), ("cfg4", "mixed"), ("cfg1", "fp64")):
+        c = get_config(name)
+        ms_g = time_stencil(c, pr, launches)
+        n_c = c.nx * c.ny * c.nz
+        gbs = stencil_bytes_per_cell(pr) * n_c / (ms_g / 1e3) / 1e9
+        sten_grids[name] = {"grid": f"{c.nx}x{c.ny}x{c.nz}", "prec": pr, "ms_per_step": ms_g,
+                            "cell_updates_per_s": n_c / (ms_g / 1e3), "achieved_GBs": gbs,
+                            "frac": gbs / HBM_PEAK_GBS, "bytes_per_cell": stencil_bytes_per_cell(pr)}
     mol64_ms = time_mol_kernel(cfg64, "fp64", max(5, launches // 4)) if not args.no_fp64 else None
 
     cpu = None
@@ -672,7 +683,8 @@ def main():
                     "achieved_GBs": sten_gbs, "frac": sten_gbs / HBM_PEAK_GBS,
                     "bytes_per_cell": stencil_bytes_per_cell("mixed"),
                     "frac_vs_fused_minimum": stencil_min_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
-                    / HBM_PEAK_GBS},
+                    / HBM_PEAK_GBS,
+                    "other_grids": sten_grids},
         "fp64": None if fp64 is None else {
             "value": fp64["n_mol"] * K / (fp64["ms"] / 1e3), "ms_per_step": fp64["ms"] / K,
             "mol_kernel_ms": mol64_ms},
