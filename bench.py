@@ -605,6 +605,19 @@ def main():
     log("Bloch-emitter coupled run: 691,200 emitters")
     bloch = run_bloch(cfg, K, W, n0, 691_200)
 
+    # coupled-step rates of the other two workloads: the tiny parity case
+    # (64 molecules, FP64; launch-latency bound) and the differentiation
+    # cell's forward step (20,000 molecules, FP32)
+    other = {}
+    for name, pr in (("cfg0", "fp64"), ("cfg3", "fp32")):
+        c = get_config(name)
+        o = run_coupled(c, pr, max(K, 50), W, default_first_step(c))
+        other[name] = {"workload": f"{c.nx}x{c.ny}x{c.nz} cells, {c.n_mol} molecules, N_r={c.n_r}, "
+                                   f"J<={c.j_max}, {pr}",
+                       "ms_per_step": o["ms"] / max(K, 50),
+                       "molecule_steps_per_s": o["n_mol"] * max(K, 50) / (o["ms"] / 1e3),
+                       "cell_updates_per_s": c.nx * c.ny * c.nz * max(K, 50) / (o["ms"] / 1e3)}
+
     scale = None
     adjoint = None
     if not args.no_scale:
@@ -693,6 +706,7 @@ def main():
         "multirate": multirate,
         "jm_basis": jm,
         "bloch_emitters": bloch,
+        "other_workloads": other,
         "scale": scale,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
