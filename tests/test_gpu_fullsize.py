@@ -109,22 +109,28 @@ def test_full_jm_general_sampled_molecules():
 def test_full_grid_fields_fp64():
     """The field solver on the full grid until the pulse has crossed the
     split rings, the molecule slab and the lower CPML: every E and H component
-    against the oracle after 40, 120 and 240 steps."""
+    against the oracle after 40, 120 and 240 steps; and the transmission
+    monitor as the benchmark runs it (32 frequencies on the 192 x 192
+    detection plane, every 4 steps): its four accumulator planes and the flux
+    spectrum at the end."""
+    from oracle.fdtd import FluxMonitor
     from paper_2209_04487_amd import msqd
     cfg = get_config("cfg1", t0_steps=30.0, t0_fs=None, fwhm_fs=1.0)
     checks = [40, 120, 240]
     nsteps = checks[-1]
-    banner(f"full grid fields cfg1 fp64: {cfg.nx}x{cfg.ny}x{cfg.nz}, {nsteps} steps")
+    banner(f"full grid fields cfg1 fp64: {cfg.nx}x{cfg.ny}x{cfg.nz}, {nsteps} steps, monitor {len(cfg.freqs)} freqs")
     mat = material_map(cfg)
     src = source_values(cfg, 0, nsteps)
-    fl = msqd.Fields(msqd.fdtd_desc_from_config(cfg, "fp64", n_freq=0), mat, [])
+    fl = msqd.Fields(msqd.fdtd_desc_from_config(cfg, "fp64"), mat, cfg.freqs)
     yee = yee_from_config(cfg, mat, eps_table(cfg))
+    mon = FluxMonitor(cfg.ny, cfg.nx, cfg.mon_k, cfg.freqs, cfg.dt, cfg.mon_every)
     n = 0
     for stop in checks:
         for m in range(n, stop):
             fl.step(m, src[m])
             yee.update_H()
             yee.update_E(src[m], cfg.src_k)
+            mon.sample(yee, m)
         n = stop
         torch.cuda.synchronize()
         emax = max(np.abs(e).max() for e in yee.E)
@@ -133,6 +139,12 @@ def test_full_grid_fields_fp64():
             assert np.abs(getattr(fl, nm).cpu().numpy() - yee.E[c]).max() < 1e-11 * emax, (stop, nm)
         for c, nm in enumerate(["Hx", "Hy", "Hz"]):
             assert np.abs(getattr(fl, nm).cpu().numpy() - yee.H[c]).max() < 1e-11 * hmax, (stop, nm)
+    assert len(cfg.freqs) == 32 and cfg.mon_every == 4
+    dft = fl.dft_planes().cpu().numpy()
+    for c, ref in enumerate([mon.Ex, mon.Ey, mon.Hx, mon.Hy]):
+        assert np.abs(ref).max() > 0
+        assert rel_err(dft[c], ref) < 1e-10, c
+    assert rel_err(fl.flux().cpu().numpy(), mon.flux()) < 1e-9
 
 
 def test_decoupled_replay_full_workload_fp64():
