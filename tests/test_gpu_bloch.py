@@ -2,7 +2,9 @@
 oracle: bloch_step element by element on seeded fields (FP64 1e-12 of the
 state scale, FP32 2e-6), a ragged emitter count that spans several blocks;
 the coupled step with Bloch emitters on the tiny workload (FP64, 1e-10 on the
-dipole trace, fields and polarisation)."""
+dipole trace, fields and polarisation); and the benchmark's 691,200 emitters
+in FP32, one step per launch as in the coupled step, every emitter against
+the oracle."""
 
 import numpy as np
 import pytest
@@ -37,6 +39,29 @@ def test_bloch_step_matches_oracle(prec, tol):
     assert np.abs(got - y).max() < tol * max(np.abs(y).max(), 1e-3)
     assert rel_err(em.d.cpu().numpy(), m.dipole(y)) < 10 * tol
     assert np.abs(y[0]).max() > 1e-3          # a real excitation
+
+
+def test_bloch_full_count_fp32():
+    from paper_2209_04487_amd import msqd
+    n, launches = 691_200, 20
+    banner(f"bloch_step fp32: {n} emitters, {launches} single-step launches")
+    rng = np.random.default_rng(41)
+    E = rng.uniform(-0.05, 0.05, n)
+    E[n - 1] = 0.05                               # the last block
+    w0, mu, dt = 0.3, 0.8, 0.05
+    em = msqd.Bloch(n, w0, mu, dt, "fp32")
+    Et = torch.as_tensor(E, device="cuda")
+    for _ in range(launches):
+        em.step(Et)
+    torch.cuda.synchronize()
+    m = BlochModel(w0, mu, dt, 0.0, 0.0)
+    y = BlochModel.ground(n)
+    for _ in range(launches):
+        y = m.step(y, E)
+    got = em.state.double().cpu().numpy()
+    assert np.abs(got - y).max() < 2e-6 * np.abs(y).max()
+    assert rel_err(em.d.cpu().numpy(), m.dipole(y)) < 2e-5
+    assert np.abs(y[0]).max() > 1e-3
 
 
 def test_bloch_zero_steps_and_empty():
