@@ -16,7 +16,10 @@ times.
 - the molecule -> cell maps of the 100,000- and 700,000-molecule workloads,
   bit for bit against the oracle;
 - the (j, m) basis at j_max = 5 over 691,200 molecules (FP32): a seeded
-  sample of planted random states against the oracle.
+  sample of planted random states against the oracle;
+- multi-rate coupling at M = 40 on the full workload: the held current,
+  the cell polarisation and the gathered field at an update step, and
+  nothing moving in between.
 """
 
 import numpy as np
@@ -214,6 +217,46 @@ def test_full_coupled_invariants_mixed():
     sums = np.add.reduceat(dd[perm], ptr[:-1]) * pfac
     np.testing.assert_allclose(P, sums, rtol=1e-12, atol=1e-30)
     assert np.abs(dd).max() > 0
+    msqd.check_status(sysm.mol.ws)
+
+
+def test_full_multirate_invariants_mixed():
+    """Multi-rate coupling as the benchmark runs it (molecules every 40 field
+    steps, precision form, 100,000 molecules): at an update step the field
+    each molecule saw is E_x^n at its edge, the held current is
+    J_mol = (P_new - P_old) / (40 dt) and P_c is the sum of the cell's
+    dipoles; over the next 39 steps the current, P_c and the dipoles stay
+    bit for bit."""
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg2")
+    M, n0 = 40, 5480
+    banner(f"full coupled cfg2 mixed multi-rate M={M}: {cfg.n_mol} molecules, steps {n0 - M}..{n0 + M}")
+    sysm = msqd.Coupled(cfg, prec="mixed", mol_every=M)
+    sysm.n = n0 - M
+    src = source_values(cfg, n0 - M, 2 * M)
+    sysm.step(src[:M])
+    P_old = sysm.P_c.double().cpu().numpy().copy()
+    ex_before = sysm.fields.Ex.reshape(-1).double().cpu().numpy()
+    sysm.step(src[M:M + 1])                      # the update step n0
+    torch.cuda.synchronize()
+    cells = sysm.cell_of_mol.cpu().numpy()
+    np.testing.assert_array_equal(sysm.E_mol.cpu().numpy(), ex_before[cells] * (1.0 / E_AU))
+    occ = sysm.occ_cell.cpu().numpy()
+    P_new = sysm.P_c.double().cpu().numpy()
+    J = sysm.J_mol.double().cpu().numpy()
+    n_occ = len(occ)
+    np.testing.assert_allclose(J[:n_occ], (P_new[:n_occ] - P_old[:n_occ]) / (M * cfg.dt), rtol=1e-12, atol=1e-300)
+    assert np.abs(J[:n_occ]).max() > 0
+    dd = sysm.mol.d.cpu().numpy()
+    perm = sysm.mol_perm.cpu().numpy()
+    ptr = sysm.occ_ptr.cpu().numpy()
+    pfac = cfg.mol_weight * EA0 / cfg.dx ** 3
+    np.testing.assert_allclose(P_new[:n_occ], np.add.reduceat(dd[perm], ptr[:-1]) * pfac, rtol=1e-12, atol=1e-30)
+    sysm.step(src[M + 1:])                       # 39 apply-only steps
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sysm.J_mol.double().cpu().numpy(), J)
+    np.testing.assert_array_equal(sysm.P_c.double().cpu().numpy(), P_new)
+    np.testing.assert_array_equal(sysm.mol.d.cpu().numpy(), dd)
     msqd.check_status(sysm.mol.ws)
 
 
