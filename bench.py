@@ -601,7 +601,11 @@ def main():
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 1")
     jm = run_jm(cfg, 20, 2, n0)
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 5")
-    jm["j_max_5"] = run_jm(cfg, 5, 1, n0, j_max=5)
+    try:
+        jm["j_max_5"] = run_jm(cfg, 5, 1, n0, j_max=5)
+    except torch.cuda.OutOfMemoryError as e:       # 102 GB of wavepackets: report, do not lose the line
+        torch.cuda.empty_cache()
+        jm["j_max_5"] = {"error": f"out of device memory: {e}".splitlines()[0]}
     log("Bloch-emitter coupled run: 691,200 emitters")
     bloch = run_bloch(cfg, K, W, n0, 691_200)
 
