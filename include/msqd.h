@@ -86,7 +86,9 @@ typedef struct {
                              complex128 at n_r = 256 and for n_r = 128, 8 at
                              n_r = 64) must stay within 1024 threads and
                              160 KB of LDS, else MSQD_EUNSUP (e.g. complex128
-                             at n_r = 256 takes j_max <= 3)                 */
+                             at n_r = 256 takes j_max <= 3).  This basis has
+                             no J<->angle contraction: MSQD_FP32 and
+                             MSQD_MIXED run the same complex64 kernel.       */
 } qd_desc;
 
 /* Bytes of device workspace (tables and a status word) for qd_* calls; 0
