@@ -303,8 +303,8 @@ def run_jm(cfg, steps, warmup, n0, n_mol=691_200, n_r=256, j_max=1):
     by = jm_bytes_per_step(n_r) if j_max == 1 else jmg_bytes_per_step(n_r, j_max)
     kt = fl * n_mol / (kms / 1e3) / 1e12
     kb = by * n_mol / (kms / 1e3) / 1e9
-    name = "mol_jm_kernel<float,256,single-step>" if j_max == 1 else \
-        f"mol_jmg_kernel<float,256,{j_max},single-step>"
+    name = f"mol_jm_kernel<float,{n_r},single-step>" if j_max == 1 else \
+        f"mol_jmg_kernel<float,{n_r},{j_max},single-step>"
     return {"workload": f"SRR array, {n_mol} molecules, (j, m) basis j <= {j_max}, N_r={n_r}, FP32",
             "ms_per_step": out["ms"] / steps, "molecule_steps_per_s": rate,
             "flops_per_molecule_step": fl, "bytes_per_molecule_step": by,
@@ -600,6 +600,8 @@ def main():
 
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 1")
     jm = run_jm(cfg, 20, 2, n0)
+    log("(j, m)-basis coupled run: 691,200 molecules, j <= 1, N_r = 512 (the paper's radial grid size)")
+    jm["n_r_512"] = run_jm(cfg, 10, 1, n0, n_r=512)
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 5")
     try:
         jm["j_max_5"] = run_jm(cfg, 5, 1, n0, j_max=5)
