@@ -180,3 +180,40 @@ def test_gradient_matches_central_differences():
     h = 1e-4 * cfg.omega
     fd = (Yof(kn, cfg.omega + h) - Yof(kn, cfg.omega - h)) / (2 * h)
     assert abs(fd - dw) <= 1e-3 * abs(dw), (fd, dw)
+
+
+def test_full_size_gradient_fp64_fd_and_fp32():
+    """The differentiation workload at its full size and launch shape (one
+    SRR cell 96 x 96 x 80, 20,000 molecules, N_r = 128, J <= 6, a checkpoint
+    every 200 steps) in the dissociating regime (lighter nuclei, carrier at
+    the vertical gap, r_diss = 4 a0, 600 steps, so that the yield, about
+    3e-5, is far above the FP32 round-off floor): the FP64 gradient against
+    central differences of the FP64 forward (relative step 1e-4) on two knots
+    and the carrier, and the FP32 yield and gradient against FP64, each to
+    1e-3."""
+    from paper_2209_04487_amd.grad import CoupledYield, yield_and_gradient
+    cfg = get_config("cfg3", mass=500.0, r_diss=4.0, omega_h=0.45, n_steps=600, ckpt_every=200)
+    banner(f"full-size adjoint cfg3: {cfg.n_mol} molecules, {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.n_steps} steps")
+    kn = knot_values(cfg) * 10.0
+    Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp64")
+    assert Y > 1e-6
+
+    def Yof(knots, omega):
+        k = torch.as_tensor(knots)
+        w = torch.as_tensor(float(omega), dtype=torch.float64)
+        return float(CoupledYield.apply(k, w, cfg, "fp64", None))
+
+    for j in [int(np.argmax(np.abs(dk))), 20]:
+        h = 1e-4 * kn[j]
+        kp, km = kn.copy(), kn.copy()
+        kp[j] += h
+        km[j] -= h
+        fd = (Yof(kp, cfg.omega) - Yof(km, cfg.omega)) / (2 * h)
+        assert abs(fd - dk[j]) <= 1e-3 * abs(dk[j]), (j, fd, dk[j])
+    h = 1e-4 * cfg.omega
+    fd = (Yof(kn, cfg.omega + h) - Yof(kn, cfg.omega - h)) / (2 * h)
+    assert abs(fd - dw) <= 1e-3 * abs(dw), (fd, dw)
+    Y32, dk32, dw32 = yield_and_gradient(cfg, kn, cfg.omega, prec="fp32")
+    assert abs(Y32 - Y) <= 1e-3 * abs(Y)
+    assert np.abs(dk32 - dk).max() <= 1e-3 * np.abs(dk).max()
+    assert abs(dw32 - dw) <= 1e-3 * abs(dw)
