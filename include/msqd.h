@@ -349,7 +349,10 @@ int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* s, const 
  * dissociated population Y = mean_i [sum_{r > r_diss} |psi_i|^2 dr +
  * absorbed_i] with respect to the incident-field samples.
  * For complex psi the adjoint is dY/dRe(psi) + i dY/dIm(psi).
- * Supported in the MSQD_FP64 and MSQD_FP32 forms with mol_every <= 1.
+ * Supported in the MSQD_FP64 and MSQD_FP32 forms, for any mol_every (with
+ * mol_every > 1 the molecules step only at n % mol_every == 0, and the held
+ * current's adjoint lJ carries the field sensitivity of the held steps back
+ * to the update that set the current).
  * ---------------------------------------------------------------------- */
 typedef struct {
   void* lpsi;        /* adjoint of psi, same layout and type              */
@@ -359,6 +362,9 @@ typedef struct {
   double* lE;        /* [n_mol] scratch: adjoint of the gathered fields   */
   fdtd_fields lf;    /* adjoint fields (E, H, J_D, CPML psi); mat, dft unused */
   void* scratch;     /* adjoint_scratch_bytes() of device memory          */
+  double* lJ;        /* [n_occ] adjoint of the held molecular current;
+                        needed with mol_every > 1 (zeroed by
+                        adjoint_init_yield), ignored otherwise (may be NULL) */
 } cpl_adj;
 
 size_t adjoint_scratch_bytes(const cpl_desc* d);
@@ -371,8 +377,10 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* s, cpl_adj* adj, void
 /* One reverse step n: with adj holding dY/d(state after step n), overwrite
  * it with dY/d(state before step n) and write g_src[0] = dY/dsrc_value[n]
  * (device float64).  psi_n and E_mol_n are the wavepackets before step n
- * and the field it gathered (recorded by a forward recompute); s supplies the
- * maps, tables and material map of the forward system. */
+ * and the field it gathered (recorded by a forward recompute; with
+ * mol_every > 1 they are read only at the update steps n % mol_every == 0);
+ * s supplies the maps, tables and material map of the forward system.
+ * Errors: MSQD_EINVAL also for n < 0. */
 int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, const double* E_mol_n,
                  cpl_adj* adj, int64_t n, double* g_src, void* stream);
 

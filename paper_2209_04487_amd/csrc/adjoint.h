@@ -42,6 +42,13 @@ struct CplAdjArgs {
   double* ld;
   const double* lE;
   void* lEx;
+  // multi-rate coupling (molecules every M field steps): the adjoint of the
+  // held current per occupied cell, accumulated over the held steps; NULL
+  // for M = 1.  update: this step recomputes P_c and the current;
+  // inv_mdt = 1 / (M dt).
+  double* lJ;
+  int update;
+  double inv_mdt;
 };
 int launch_deposit_adj(const CplAdjArgs& a, bool f32, hipStream_t s);
 int launch_gather_adj(const CplAdjArgs& a, bool f32, hipStream_t s);

@@ -544,8 +544,25 @@ __global__ __launch_bounds__(256) void deposit_adj_kernel(CplAdjArgs a) {
   const int cell = a.occ_cell[c];
   const double ce = a.ce[a.mat[cell] & 3];
   const double lex = static_cast<double>(static_cast<const T*>(a.lEx)[cell]);
-  const double lp_new = a.lP[c] - ce * a.inv_dt * lex;
-  a.lP[c] = ce * a.inv_dt * lex;
+  double lp_new;
+  if (a.lJ == nullptr) {
+    // one molecular step per field step: J = (P_new - P_old) / dt
+    lp_new = a.lP[c] - ce * a.inv_dt * lex;
+    a.lP[c] = ce * a.inv_dt * lex;
+  } else {
+    // multi-rate: E_x -= ce J at every step with J held between updates, so
+    // the current's adjoint accumulates -ce lambda_Ex over the held steps;
+    // at the update J = (P_new - P_old) / (M dt) hands it to both P's, and
+    // the current before the update has no further influence
+    const double lj = a.lJ[c] - ce * lex;
+    if (!a.update) {
+      a.lJ[c] = lj;
+      return;
+    }
+    lp_new = a.lP[c] + a.inv_mdt * lj;
+    a.lP[c] = -a.inv_mdt * lj;
+    a.lJ[c] = 0.0;
+  }
   const double ldv = a.pfac * lp_new;
   for (int t = a.occ_ptr[c]; t < a.occ_ptr[c + 1]; ++t) a.ld[a.mol_perm[t]] = ldv;
 }

@@ -902,7 +902,6 @@ static int check_adj(const cpl_desc* d, const cpl_state* st, const cpl_adj* adj)
   if (rc) return rc;
   if (d->qd.prec == MSQD_MIXED || d->fd.prec == MSQD_MIXED)
     return fail(MSQD_EUNSUP, "the adjoint is provided for the FP64 and FP32 forms");
-  if (d->mol_every > 1) return fail(MSQD_EUNSUP, "the adjoint is provided for mol_every <= 1");
   if (d->qd.basis != MSQD_BASIS_M0) return fail(MSQD_EUNSUP, "the adjoint is provided for the m = 0 basis");
   if (d->qd.prec != d->fd.prec) return fail(MSQD_EPREC, "molecule and field precision differ");
   const fdtd_fields& f = adj->lf;
@@ -911,6 +910,8 @@ static int check_adj(const cpl_desc* d, const cpl_state* st, const cpl_adj* adj)
     if (!p || !aligned16(p)) return fail(MSQD_EINVAL, "adjoint field pointer NULL or misaligned");
   if (d->qd.n_mol > 0 && (!adj->lpsi || !adj->labs || !adj->ld || !adj->lE))
     return fail(MSQD_EINVAL, "adjoint molecule pointer NULL");
+  if (d->mol_every > 1 && d->qd.n_mol > 0 && d->n_occ > 0 && !adj->lJ)
+    return fail(MSQD_EINVAL, "adjoint of the held current (lJ) NULL with mol_every > 1");
   if (d->n_occ > 0 && !adj->lP) return fail(MSQD_EINVAL, "adjoint polarisation pointer NULL");
   if (!st->f.mat || !st->fd_ws) return fail(MSQD_EINVAL, "forward material map or workspace NULL");
   const size_t need = mol_adj_lds_bytes(d->qd.n_r, d->qd.j_max + 1, d->qd.prec != MSQD_FP64);
@@ -937,6 +938,10 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* st, cpl_adj* adj, voi
   if (d->n_occ > 0) {
     e = launch_fill_zero(adj->lP, sizeof(double) * d->n_occ, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "adjoint polarisation zero fill");
+    if (d->mol_every > 1 && adj->lJ) {
+      e = launch_fill_zero(adj->lJ, sizeof(double) * d->n_occ, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "adjoint current zero fill");
+    }
   }
   if (d->qd.n_mol > 0) {
     const MolArgs ma = make_mol_args(&d->qd, st->qd_ws);
@@ -953,7 +958,10 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, cons
   if (rc) return rc;
   if (!g_src) return fail(MSQD_EINVAL, "g_src NULL");
   if (d->qd.n_mol > 0 && (!psi_n || !E_mol_n)) return fail(MSQD_EINVAL, "recorded state NULL");
-  (void)n;
+  if (n < 0) return fail(MSQD_EINVAL, "step index < 0");
+  // multi-rate coupling: the molecules stepped (by M dt) only at n % M == 0
+  const int M = d->mol_every > 1 ? d->mol_every : 1;
+  const bool update = (n % M) == 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool f32 = d->fd.prec != MSQD_FP64;
   FdArgs lam = make_fd_args(&d->fd, &adj->lf, st->fd_ws);
@@ -973,6 +981,9 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, cons
   ca.ld = adj->ld;
   ca.lE = adj->lE;
   ca.lEx = adj->lf.Ex;
+  ca.lJ = M > 1 ? adj->lJ : nullptr;
+  ca.update = update ? 1 : 0;
+  ca.inv_mdt = 1.0 / (M * d->fd.dt);
   // reverse order of the forward step: deposit, E update, molecules, gather, H update
   int e = launch_src_grad(lam, 2.0 / (kEta0 * d->fd.dx), g_src, f32, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "source gradient launch");
@@ -982,7 +993,7 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, cons
   }
   e = launch_yee_e_adj(fa, f32, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "E adjoint launch");
-  if (d->qd.n_mol > 0) {
+  if (d->qd.n_mol > 0 && update) {
     if (d->n_occ == 0) {
       e = launch_fill_zero(adj->ld, sizeof(double) * d->qd.n_mol, s);
       if (e) return check_hip(static_cast<hipError_t>(e), "dipole adjoint zero fill");

@@ -22,14 +22,14 @@ from . import msqd
 
 class CoupledYield(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, knots, omega, cfg, prec="fp32", ckpt_every=None):
+    def forward(ctx, knots, omega, cfg, prec="fp32", ckpt_every=None, mol_every=1):
         from workloads.pulses import source_values
         K = int(ckpt_every or cfg.ckpt_every)
         n_steps = cfg.n_steps
         kn = knots.detach().cpu().numpy().astype(np.float64)
         w = float(omega.detach().cpu())
         src = source_values(cfg, 0, n_steps, knots=kn, omega=w)
-        sysm = msqd.Coupled(cfg, prec=prec)
+        sysm = msqd.Coupled(cfg, prec=prec, mol_every=mol_every)
         ckpts = []
         for s0 in range(0, n_steps, K):
             ckpts.append(sysm.snapshot())
@@ -48,7 +48,7 @@ class CoupledYield(torch.autograd.Function):
         scale = float(gY)
         dk = torch.as_tensor(dp[:-1] * scale, dtype=torch.float64)
         dw = torch.as_tensor(dp[-1] * scale, dtype=torch.float64)
-        return dk, dw, None, None, None
+        return dk, dw, None, None, None, None
 
 
 def source_gradient(sysm, ckpts, src, K):
@@ -79,10 +79,11 @@ def source_gradient(sysm, ckpts, src, K):
     return g
 
 
-def yield_and_gradient(cfg, knots, omega, prec="fp32", ckpt_every=None):
-    """(Y, dY/dknots, dY/domega) for a run of cfg."""
+def yield_and_gradient(cfg, knots, omega, prec="fp32", ckpt_every=None, mol_every=1):
+    """(Y, dY/dknots, dY/domega) for a run of cfg, with the molecules
+    stepped every mol_every field steps."""
     k = torch.as_tensor(np.asarray(knots, np.float64)).requires_grad_(True)
     w = torch.as_tensor(float(omega), dtype=torch.float64).requires_grad_(True)
-    Y = CoupledYield.apply(k, w, cfg, prec, ckpt_every)
+    Y = CoupledYield.apply(k, w, cfg, prec, ckpt_every, mol_every)
     Y.backward()
     return float(Y.detach()), k.grad.numpy().copy(), float(w.grad)

@@ -110,7 +110,7 @@ class cpl_bloch_state(C.Structure):
 
 class cpl_adj(C.Structure):
     _fields_ = [("lpsi", C.c_void_p), ("labs", C.c_void_p), ("lP", C.c_void_p), ("ld", C.c_void_p),
-                ("lE", C.c_void_p), ("lf", fdtd_fields), ("scratch", C.c_void_p)]
+                ("lE", C.c_void_p), ("lf", fdtd_fields), ("scratch", C.c_void_p), ("lJ", C.c_void_p)]
 
 
 _vp, _dp, _i32p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
@@ -518,6 +518,7 @@ class Coupled:
         t["ld"] = torch.zeros(nm, dtype=torch.float64, device=dev)
         t["lE"] = torch.zeros(nm, dtype=torch.float64, device=dev)
         t["lP"] = torch.zeros(max(self.desc.n_occ, 1), dtype=torch.float64, device=dev)
+        t["lJ"] = torch.zeros(max(self.desc.n_occ, 1), dtype=torch.float64, device=dev)
         nbytes = lib.adjoint_scratch_bytes(C.byref(self.desc))
         t["scratch"] = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=dev)
         lf = fdtd_fields(*[C.c_void_p(t[n].data_ptr()) for n in ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz",
@@ -525,7 +526,8 @@ class Coupled:
                          None, None)
         adj = cpl_adj(C.c_void_p(t["lpsi"].data_ptr()), C.c_void_p(t["labs"].data_ptr()),
                       C.c_void_p(t["lP"].data_ptr()), C.c_void_p(t["ld"].data_ptr()),
-                      C.c_void_p(t["lE"].data_ptr()), lf, C.c_void_p(t["scratch"].data_ptr()))
+                      C.c_void_p(t["lE"].data_ptr()), lf, C.c_void_p(t["scratch"].data_ptr()),
+                      C.c_void_p(t["lJ"].data_ptr()))
         return adj, t
 
 

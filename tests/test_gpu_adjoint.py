@@ -217,3 +217,38 @@ def test_full_size_gradient_fp64_fd_and_fp32():
     assert abs(Y32 - Y) <= 1e-3 * abs(Y)
     assert np.abs(dk32 - dk).max() <= 1e-3 * np.abs(dk).max()
     assert abs(dw32 - dw) <= 1e-3 * abs(dw)
+
+
+def test_multirate_gradient_matches_central_differences():
+    """Multi-rate coupling (molecules by 4 dt every 4 field steps, the current
+    held in between): the FP64 gradient against central differences of the
+    FP64 forward on two knots and the carrier, and FP32 against FP64, each
+    to 1e-3, over 250 steps (Y ~ 1e-4).  Checkpoints every 70 steps, so that
+    segments restart in the middle of a held interval."""
+    from paper_2209_04487_amd.grad import CoupledYield, yield_and_gradient
+    M = 4
+    cfg = _cfg_dissociating(n_steps=250, ckpt=70)
+    banner(f"adjoint gradient multi-rate M={M} vs GPU central differences fp64")
+    kn = knot_values(cfg) * 10.0
+    Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp64", mol_every=M)
+    assert Y > 1e-5
+
+    def Yof(knots, omega):
+        k = torch.as_tensor(knots)
+        w = torch.as_tensor(float(omega), dtype=torch.float64)
+        return float(CoupledYield.apply(k, w, cfg, "fp64", None, M))
+
+    for j in [int(np.argmax(np.abs(dk))), 20]:
+        h = 1e-4 * kn[j]
+        kp, km = kn.copy(), kn.copy()
+        kp[j] += h
+        km[j] -= h
+        fd = (Yof(kp, cfg.omega) - Yof(km, cfg.omega)) / (2 * h)
+        assert abs(fd - dk[j]) <= 1e-3 * abs(dk[j]), (j, fd, dk[j])
+    h = 1e-4 * cfg.omega
+    fd = (Yof(kn, cfg.omega + h) - Yof(kn, cfg.omega - h)) / (2 * h)
+    assert abs(fd - dw) <= 1e-3 * abs(dw), (fd, dw)
+    Y32, dk32, dw32 = yield_and_gradient(cfg, kn, cfg.omega, prec="fp32", mol_every=M)
+    assert abs(Y32 - Y) <= 1e-3 * abs(Y)
+    assert np.abs(dk32 - dk).max() <= 1e-3 * np.abs(dk).max()
+    assert abs(dw32 - dw) <= 1e-3 * abs(dw)
