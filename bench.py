@@ -506,7 +506,7 @@ def main():
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the 700,000-molecule and adjoint measurements")
     ap.add_argument("--adjoint-only", action="store_true",
-                    help="only run the differentiation workload (400 forward + reverse steps) and its "
+                    help="only run the differentiation workload (4,000 forward + reverse steps) and its "
                          "forward-only timing, for a kernel trace of the adjoint")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm", "jm5"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
@@ -527,7 +527,7 @@ def main():
     K, W = args.steps, args.warmup
     n0 = default_first_step(cfg) if args.n0 is None else args.n0
     if args.adjoint_only:
-        adj = run_adjoint(400)
+        adj = run_adjoint(4000)
         cfg3 = get_config("cfg3")
         fwd = run_coupled(cfg3, "fp32", 200, 20, default_first_step(cfg3))
         adj["forward_ms_per_step"] = fwd["ms"] / 200
@@ -629,8 +629,8 @@ def main():
     if not args.no_scale:
         log("scale workload: 700,000 molecules, one run and a 3-carrier batch")
         scale = run_scale(10)
-        log("adjoint: differentiation workload, 400 steps")
-        adjoint = run_adjoint(400)
+        log("adjoint: differentiation workload, 4,000 steps")
+        adjoint = run_adjoint(4000)
 
     log("kernel timing")
     launches = max(10, min(K, 100))
