@@ -61,6 +61,19 @@ const char* msqd_last_error(void);
 /* Library version (major*10000 + minor*100 + patch). */
 int msqd_version(void);
 
+/* Instrumentation of the molecular step inside coupled_step (host only, per
+ * calling thread; not needed for any computation).  msqd_mol_timing_begin
+ * creates max_launches pairs of HIP timing events (1 <= max_launches <=
+ * 2^20); until msqd_mol_timing_end, every coupled_step call on this thread
+ * records one pair around each of its molecular-step launches, on the
+ * call's stream, for the first max_launches launches.
+ * msqd_mol_timing_end waits for the recorded events, writes the summed
+ * duration of the recorded launches (ms) and their number, and destroys the
+ * events.  Errors: MSQD_EINVAL (bad count, NULL output, end without begin),
+ * MSQD_EDEVICE (event creation or query failed). */
+int msqd_mol_timing_begin(int32_t max_launches);
+int msqd_mol_timing_end(double* total_ms, int32_t* n_launches);
+
 /* ------------------------------------------------------------------------
  * Molecules: two-state ro-vibrational wavepackets, Eqs. (3)-(5).
  * ---------------------------------------------------------------------- */
@@ -91,11 +104,14 @@ typedef struct {
                              MSQD_MIXED run the same complex64 kernel.       */
 } qd_desc;
 
-/* Bytes of device workspace (tables and a status word) for qd_* calls; 0
- * (with the message) for an invalid or unsupported descriptor.  With
- * basis = MSQD_BASIS_JM and j_max >= 2 it includes the tables of the
- * general coupling (the Wigner-rotation eigenvectors of J_x, the per-m'
- * eigen-decompositions of cos(theta) and the dipole matrix elements). */
+/* Bytes of device workspace (tables, a status word, and the partial sums of
+ * dipole_readout's ensemble sums: 8 (nc + 2) ceil(n_mol / 1024) bytes, nc =
+ * 1 or 3 dipole components) for qd_* calls; 0 (with the message) for an
+ * invalid or unsupported descriptor.  With basis = MSQD_BASIS_JM and
+ * j_max >= 2 it includes the tables of the general coupling (the
+ * Wigner-rotation eigenvectors of J_x, the per-m' eigen-decompositions of
+ * cos(theta) and the dipole matrix elements).  qd_init rejects a smaller
+ * ws_bytes with MSQD_ESHAPE. */
 size_t qd_workspace_bytes(const qd_desc* d);
 
 /* Build the split-operator tables (Eq. (5) phases on the grid, the
@@ -144,18 +160,34 @@ int qd_jm_tables(int32_t j_max, double* out, size_t n_out);
 int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
             double* absorbed, double* d_mol, int32_t n_steps, void* stream);
 
-/* Per-molecule readouts of the current state (float64, device):
- * d_mol (e a0), norm_mol (sum |psi|^2 dr), yield_mol (norm beyond r_diss
- * plus absorbed).  Any output may be NULL.  The state is not modified. */
+/* Per-molecule readouts of the current state (float64, device) and their
+ * ensemble sums.  The dipole is the expectation of mu12(r) cos(theta)
+ * sigma_x, the quantity whose density is the mean-field polarisation that
+ * returns to Ampere's law (section on the coupled equations, Eqs. (1), (4));
+ * the yield is the dissociated population (norm beyond r_diss plus the
+ * absorbed norm) of the section on collective dissociation dynamics.
+ *   d_mol     [n_mol] (e a0), or [n_mol][3] in the (j, m) basis;
+ *   norm_mol  [n_mol] sum |psi|^2 dr;
+ *   yield_mol [n_mol] norm beyond r_diss plus absorbed;
+ *   sums      [nc + 2] FP64 = (sum d (nc = 1, or the x, y, z sums: nc = 3),
+ *             sum norm, sum yield) over all molecules, in a fixed two-stage
+ *             order (blocks of 1024 consecutive molecules, then the block
+ *             partials), bit-reproducible for a given n_mol; or NULL.  The
+ *             stage-one partials use the tail of ws (qd_workspace_bytes).
+ * Per-molecule outputs may be NULL when sums is NULL; sums needs all three
+ * (it reduces them): MSQD_EINVAL otherwise.  With n_mol = 0 only sums is
+ * written (zeros).  The state is not modified. */
 int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
-                   double* d_mol, double* norm_mol, double* yield_mol, void* stream);
+                   double* d_mol, double* norm_mol, double* yield_mol, double* sums, void* stream);
 
 /* Excited-state internuclear distance, Eq. (8): per molecule (float64,
  * device) r_num = <chi_e|R|chi_e> = sum_{J,k} r_k |psi_e,J(r_k)|^2 dr and
  * pop = <chi_e|chi_e>; the ratio is the molecule's <R>_e.  sums: device
- * float64 [2] = (sum r_num, sum pop) over all molecules in a fixed order (the
- * ensemble <R>_e is their ratio), or NULL.  ws is unused but validated like
- * the other readouts.  Errors: MSQD_EINVAL for NULL outputs. */
+ * float64 [3] = (sum r_num, sum pop, their ratio: the ensemble <R>_e, each
+ * molecule weighted by its excited population; NaN while that population is
+ * exactly zero) over all molecules in a fixed order, or NULL.  With
+ * n_mol = 0 nothing is written.  ws is unused but validated like the other
+ * readouts.  Errors: MSQD_EINVAL for NULL outputs. */
 int excited_r_readout(const qd_desc* d, const void* ws, const void* psi, double* r_num, double* pop,
                       double* sums, void* stream);
 
@@ -224,6 +256,18 @@ int fdtd_step(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t 
  * S_ref: T = S(mon_k)/S_ref, R = 1 - S(mon_k2)/S_ref, A = 1 - T - R (the
  * short-pulse spectra of the section on 3D domain decomposition, Fig. 6a). */
 int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* stream);
+
+/* Transmission, reflection and absorption spectra of the short-pulse runs
+ * (section on 3D domain decomposition, Fig. 6a), per monitor frequency:
+ *   T = S_trans / S_ref,  R = (S_ref - S_inc) / S_ref,  A = (S_inc - S_trans) / S_ref = 1 - T - R,
+ * with flux the device float64 [2][n_freq] readout of a run with both
+ * detection planes (S_trans on mon_k beyond the structure, S_inc on mon_k2
+ * on the incident side, where the net flux is the incident minus the
+ * reflected one) and flux_ref a device float64 [n_freq] incident-side flux of
+ * a reference run without the structure.  tra: device float64 [3][n_freq] =
+ * T, R, A.  Errors: MSQD_EINVAL for NULL pointers, no monitor, or no
+ * second plane (d->mon_k2 = 0). */
+int spectra_readout(const fdtd_desc* d, const double* flux, const double* flux_ref, double* tra, void* stream);
 
 /* ------------------------------------------------------------------------
  * Coupling: molecules <-> cells, the self-consistent step.

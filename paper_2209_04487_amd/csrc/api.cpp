@@ -18,6 +18,22 @@ namespace msqd {
 
 static thread_local std::string g_err;
 
+// Molecular-launch timing of the calling thread (msqd_mol_timing_begin/end):
+// event pairs recorded around the molecular-step launches of coupled_step
+struct MolTiming {
+  std::vector<hipEvent_t> b, e;
+  int n_rec = 0;
+  bool armed = false;
+};
+static thread_local MolTiming g_timing;
+
+static void timing_mark(bool before, hipStream_t s) {
+  MolTiming& t = g_timing;
+  if (!t.armed || t.n_rec >= static_cast<int>(t.b.size())) return;
+  (void)hipEventRecord(before ? t.b[t.n_rec] : t.e[t.n_rec], s);
+  if (!before) ++t.n_rec;
+}
+
 void set_error(const std::string& msg) { g_err = msg; }
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -319,16 +335,73 @@ using namespace msqd;
 extern "C" {
 
 const char* msqd_last_error(void) { return g_err.c_str(); }
-int msqd_version(void) { return 100; }
+int msqd_version(void) { return 200; }
+
+static void timing_release() {
+  for (hipEvent_t ev : g_timing.b) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : g_timing.e) (void)hipEventDestroy(ev);
+  g_timing = MolTiming{};
+}
+
+int msqd_mol_timing_begin(int32_t max_launches) {
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(MSQD_EINVAL, "max_launches outside [1, 2^20]");
+  timing_release();
+  g_timing.b.resize(max_launches);
+  g_timing.e.resize(max_launches);
+  for (int i = 0; i < max_launches; ++i) {
+    hipError_t e1 = hipEventCreate(&g_timing.b[i]);
+    hipError_t e2 = e1 == hipSuccess ? hipEventCreate(&g_timing.e[i]) : e1;
+    if (e2 != hipSuccess) {
+      g_timing.b.resize(e1 == hipSuccess ? i + 1 : i);
+      g_timing.e.resize(i);
+      timing_release();
+      return check_hip(e2, "hipEventCreate");
+    }
+  }
+  g_timing.armed = true;
+  return MSQD_OK;
+}
+
+int msqd_mol_timing_end(double* total_ms, int32_t* n_launches) {
+  if (!total_ms || !n_launches) return fail(MSQD_EINVAL, "NULL output");
+  *total_ms = 0.0;
+  *n_launches = 0;
+  if (!g_timing.armed) return fail(MSQD_EINVAL, "molecular timing was not started on this thread");
+  double sum = 0.0;
+  for (int i = 0; i < g_timing.n_rec; ++i) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(g_timing.e[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_timing.b[i], g_timing.e[i]);
+    if (e != hipSuccess) {
+      timing_release();
+      return check_hip(e, "molecular launch timing");
+    }
+    sum += ms;
+  }
+  *total_ms = sum;
+  *n_launches = g_timing.n_rec;
+  timing_release();
+  return MSQD_OK;
+}
 
 // bytes of the general (j, m) coupling tables after the common ones
 static size_t qd_jmg_bytes(const qd_desc* d) {
   return (d->basis == MSQD_BASIS_JM && d->j_max >= 2) ? 8 * static_cast<size_t>(jmg_tab(d->j_max).n) : 0;
 }
 
+// dipole_readout's ensemble sums: the dipole (one component, or x, y, z in
+// the (j, m) basis), the norm and the yield; their stage-one partials sit at
+// the end of the workspace, after the tables
+static int qd_sum_vecs(const qd_desc* d) { return (d->basis == MSQD_BASIS_JM ? 3 : 1) + 2; }
+static size_t qd_tables_bytes(const qd_desc* d) { return qd_layout(d->n_r, d->j_max + 1).total + qd_jmg_bytes(d); }
+static size_t qd_partials_offset(const qd_desc* d) { return align256(qd_tables_bytes(d)); }
+static size_t qd_partials_bytes(const qd_desc* d) {
+  return sizeof(double) * qd_sum_vecs(d) * static_cast<size_t>(sum_blocks(d->n_mol));
+}
+
 size_t qd_workspace_bytes(const qd_desc* d) {
   if (check_qd(d) != MSQD_OK) return 0;
-  return qd_layout(d->n_r, d->j_max + 1).total + qd_jmg_bytes(d);
+  return qd_partials_offset(d) + qd_partials_bytes(d);
 }
 
 size_t qd_jm_tables_size(int32_t j_max) {
@@ -353,8 +426,8 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   if (!U_g || !U_e || !mu12 || !psi0) return fail(MSQD_EINVAL, "host table pointer is NULL");
   if (!ws || !aligned16(ws)) return fail(MSQD_EINVAL, "workspace NULL or misaligned");
   const QdLayout L = qd_layout(d->n_r, d->j_max + 1);
-  const size_t ws_need = L.total + qd_jmg_bytes(d);
-  if (ws_bytes < ws_need) return fail(MSQD_ESHAPE, "workspace too small");
+  const size_t ws_need = qd_tables_bytes(d);
+  if (ws_bytes < qd_partials_offset(d) + qd_partials_bytes(d)) return fail(MSQD_ESHAPE, "workspace too small");
   if (d->n_mol > 0 && (!psi || !aligned16(psi) || !absorbed))
     return fail(MSQD_EINVAL, "psi / absorbed NULL or misaligned");
   for (int k = 0; k < d->n_r; ++k)
@@ -451,25 +524,58 @@ int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol, do
   return launch_mol(d, a, static_cast<hipStream_t>(stream));
 }
 
+// per-molecule readouts, then (sums != NULL) their fixed-order ensemble sums
+// with the stage-one partials in `partial`
+static int readout_impl(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
+                        double* d_mol, double* norm_mol, double* yield_mol, double* sums, double* partial,
+                        hipStream_t s) {
+  if (sums && (!d_mol || !norm_mol || !yield_mol))
+    return fail(MSQD_EINVAL, "sums need the per-molecule d_mol, norm_mol and yield_mol they reduce");
+  if (d->n_mol > 0) {
+    if (!ws || !psi || !absorbed) return fail(MSQD_EINVAL, "NULL device pointer");
+    if (!aligned16(ws) || !aligned16(psi)) return fail(MSQD_EINVAL, "misaligned device pointer");
+    MolArgs a = make_mol_args(d, ws);
+    a.n_steps = 0;
+    a.psi = const_cast<void*>(psi);
+    a.E_mol = absorbed;  // unused with n_steps = 0 (any valid pointer)
+    a.absorbed = const_cast<double*>(absorbed);
+    a.d_mol = d_mol;
+    a.norm_mol = norm_mol;
+    a.yield_mol = yield_mol;
+    a.want_d = d_mol != nullptr;
+    a.want_norm = norm_mol != nullptr;
+    a.want_yield = yield_mol != nullptr;
+    const int rc = launch_mol(d, a, s);
+    if (rc) return rc;
+  }
+  if (!sums) return MSQD_OK;
+  SumArgs sa{};
+  const int nc = qd_sum_vecs(d) - 2;
+  for (int c = 0; c < nc; ++c) {
+    sa.src[c] = d_mol + c;
+    sa.stride[c] = nc;
+  }
+  sa.src[nc] = norm_mol;
+  sa.src[nc + 1] = yield_mol;
+  sa.stride[nc] = sa.stride[nc + 1] = 1;
+  sa.nv = nc + 2;
+  sa.n = d->n_mol;
+  sa.partial = partial;
+  sa.out = sums;
+  const int e = launch_ensemble_sums(sa, s);
+  return e ? check_hip(static_cast<hipError_t>(e), "ensemble sums launch") : MSQD_OK;
+}
+
 int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
-                   double* d_mol, double* norm_mol, double* yield_mol, void* stream) {
+                   double* d_mol, double* norm_mol, double* yield_mol, double* sums, void* stream) {
   int rc = check_qd(d);
   if (rc) return rc;
-  if (d->n_mol == 0) return MSQD_OK;
-  if (!ws || !psi || !absorbed) return fail(MSQD_EINVAL, "NULL device pointer");
-  if (!aligned16(ws) || !aligned16(psi)) return fail(MSQD_EINVAL, "misaligned device pointer");
-  MolArgs a = make_mol_args(d, ws);
-  a.n_steps = 0;
-  a.psi = const_cast<void*>(psi);
-  a.E_mol = absorbed;  // unused with n_steps = 0 (any valid pointer)
-  a.absorbed = const_cast<double*>(absorbed);
-  a.d_mol = d_mol;
-  a.norm_mol = norm_mol;
-  a.yield_mol = yield_mol;
-  a.want_d = d_mol != nullptr;
-  a.want_norm = norm_mol != nullptr;
-  a.want_yield = yield_mol != nullptr;
-  return launch_mol(d, a, static_cast<hipStream_t>(stream));
+  if (sums && d->n_mol > 0 && !ws) return fail(MSQD_EINVAL, "NULL workspace");
+  double* partial = (sums && d->n_mol > 0)
+                        ? reinterpret_cast<double*>(static_cast<char*>(const_cast<void*>(ws)) + qd_partials_offset(d))
+                        : nullptr;
+  return readout_impl(d, ws, psi, absorbed, d_mol, norm_mol, yield_mol, sums, partial,
+                      static_cast<hipStream_t>(stream));
 }
 
 int excited_r_readout(const qd_desc* d, const void* ws, const void* psi, double* r_num, double* pop,
@@ -663,6 +769,16 @@ int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* s
   return MSQD_OK;
 }
 
+int spectra_readout(const fdtd_desc* d, const double* flux, const double* flux_ref, double* tra, void* stream) {
+  int rc = check_fd(d);
+  if (rc) return rc;
+  if (d->n_freq <= 0) return fail(MSQD_EINVAL, "no monitor frequencies");
+  if (fd_planes(d) != 2) return fail(MSQD_EINVAL, "spectra need the second detection plane (mon_k2)");
+  if (!flux || !flux_ref || !tra) return fail(MSQD_EINVAL, "NULL pointer");
+  const int e = launch_spectra(flux, flux + d->n_freq, flux_ref, d->n_freq, tra, static_cast<hipStream_t>(stream));
+  return e ? check_hip(static_cast<hipError_t>(e), "spectra launch") : MSQD_OK;
+}
+
 // --------------------------------------------------------------- coupling
 int map_build(int32_t n_mol, int32_t nx, int32_t ny, int32_t nz, uint64_t seed, int32_t slab_k0,
               int32_t slab_nk, int32_t* cell_of_mol, int32_t* occ_cell, int32_t* occ_ptr,
@@ -758,8 +874,10 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
     const bool mol_now = (n % M) == 0;
     if (mol_now) {
+      timing_mark(true, s);
       rc = launch_mol(&d->qd, ma, s);
       if (rc) return rc;
+      timing_mark(false, s);
     }
     e = launch_yee_e(fa, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");

@@ -34,7 +34,9 @@ class CoupledYield(torch.autograd.Function):
         for s0 in range(0, n_steps, K):
             ckpts.append(sysm.snapshot())
             sysm.step(src[s0:min(s0 + K, n_steps)])
-        Y = sysm.yield_mean().detach().clone()
+        # the objective: the mean over molecules of the library's FP64 sum of
+        # the per-molecule dissociated populations (dipole_readout)
+        Y = sysm.ensemble_sums()[-1].detach().clone() / sysm.mol.desc.n_mol
         ctx.sysm, ctx.ckpts, ctx.src, ctx.K = sysm, ckpts, src, K
         ctx.cfg, ctx.kn, ctx.w = cfg, kn, w
         return Y

@@ -3,8 +3,10 @@
 Argument marshalling only: every step of the path runs in the HIP library.
 torch provides device memory and the stream.  The entry points keep the C
 names (qd_init, qd_step, dipole_readout, fdtd_init, fdtd_step, flux_readout,
-map_build, coupled_step); the classes below only allocate the buffers the C
-calls expect and hold the descriptors.
+spectra_readout, map_build, coupled_step, adjoint_step, ...); the classes
+below only allocate the buffers the C calls expect and hold the descriptors.
+Every number a caller reads back (dipoles, ensemble sums, <R>_e, spectra)
+is computed by the library; this module does no arithmetic on them.
 
 The library is loaded from this package directory; if it is missing the import
 fails loudly (there is no fallback implementation).
@@ -37,7 +39,7 @@ EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
            "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
-           "qd_jm_tables"]
+           "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end"]
 
 
 class MsqdError(RuntimeError):
@@ -117,10 +119,12 @@ _vp, _dp, _i32p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
 _sigs = {
     "msqd_last_error": (C.c_char_p, []),
     "msqd_version": (C.c_int, []),
+    "msqd_mol_timing_begin": (C.c_int, [C.c_int32]),
+    "msqd_mol_timing_end": (C.c_int, [_dp, _i32p]),
     "qd_workspace_bytes": (C.c_size_t, [C.POINTER(qd_desc)]),
     "qd_init": (C.c_int, [C.POINTER(qd_desc), _dp, _dp, _dp, _dp, _vp, C.c_size_t, _vp, _vp, _vp]),
     "qd_step": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]),
-    "dipole_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "dipole_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "msqd_check_status": (C.c_int, [_vp, _vp]),
     "qd_jm_tables_size": (C.c_size_t, [C.c_int32]),
     "qd_jm_tables": (C.c_int, [C.c_int32, _dp, C.c_size_t]),
@@ -132,6 +136,7 @@ _sigs = {
     "fdtd_step": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, C.c_int64,
                             C.c_double, _vp]),
     "flux_readout": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, _vp]),
+    "spectra_readout": (C.c_int, [C.POINTER(fdtd_desc), _vp, _vp, _vp, _vp]),
     "map_build": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32,
                             C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
     "map_csr": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
@@ -203,9 +208,11 @@ def qd_step(d, ws, psi, E_mol, absorbed, d_mol=None, n_steps=1, stream=None):
                               _ptr(d_mol), int(n_steps), stream or current_stream()))
 
 
-def dipole_readout(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=None, stream=None):
+def dipole_readout(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=None, sums=None,
+                   stream=None):
     return _check(lib.dipole_readout(C.byref(d), _ptr(ws), _ptr(psi), _ptr(absorbed), _ptr(d_mol),
-                                     _ptr(norm_mol), _ptr(yield_mol), stream or current_stream()))
+                                     _ptr(norm_mol), _ptr(yield_mol), _ptr(sums),
+                                     stream or current_stream()))
 
 
 def jm_tables(j_max):
@@ -216,6 +223,21 @@ def jm_tables(j_max):
     out = np.zeros(max(n, 1), dtype=np.float64)
     _check(lib.qd_jm_tables(int(j_max), out.ctypes.data_as(_dp), n))
     return out[:n]
+
+
+def mol_timing_begin(max_launches):
+    """Start recording HIP events around the molecular-step launches of
+    coupled_step on this thread (instrumentation only)."""
+    return _check(lib.msqd_mol_timing_begin(int(max_launches)))
+
+
+def mol_timing_end():
+    """(summed ms, launches) of the molecular-step launches recorded since
+    mol_timing_begin; waits for their events."""
+    ms = C.c_double(0.0)
+    n = C.c_int32(0)
+    _check(lib.msqd_mol_timing_end(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def check_status(ws, stream=None):
@@ -237,6 +259,11 @@ def fdtd_step(d, f, ws, n, src_value, stream=None):
 
 def flux_readout(d, f, flux, stream=None):
     return _check(lib.flux_readout(C.byref(d), C.byref(f), _ptr(flux), stream or current_stream()))
+
+
+def spectra_readout(d, flux, flux_ref, tra, stream=None):
+    return _check(lib.spectra_readout(C.byref(d), _ptr(flux), _ptr(flux_ref), _ptr(tra),
+                                      stream or current_stream()))
 
 
 def map_build(n_mol, nx, ny, nz, seed, slab_k0, slab_nk):
@@ -320,42 +347,64 @@ class Molecules:
         qd_step(self.desc, self.ws, self.psi, E_mol, self.absorbed, self.d if want_d else None,
                 n_steps)
 
-    def readout(self):
+    @property
+    def n_sums(self):
+        """Entries of dipole_readout's ensemble sums: the dipole components
+        (1, or x, y, z in the (j, m) basis), then the norm and the yield."""
+        return (3 if self.basis == BASIS_JM else 1) + 2
+
+    def readout(self, sums=None):
+        """Per-molecule (d, norm, yield) of the current state; with `sums` (a
+        device float64 tensor of n_sums entries, or a row of a larger one)
+        also their fixed-order ensemble sums."""
         n = self.desc.n_mol
         dev = self.psi.device
-        d = torch.empty(tuple(self.d.shape), dtype=torch.float64, device=dev)
-        nrm = torch.empty(n, dtype=torch.float64, device=dev)
-        yld = torch.empty(n, dtype=torch.float64, device=dev)
-        dipole_readout(self.desc, self.ws, self.psi, self.absorbed, d, nrm, yld)
+        d = torch.empty((max(n, 1),) + tuple(self.d.shape[1:]), dtype=torch.float64, device=dev)
+        nrm = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        yld = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        dipole_readout(self.desc, self.ws, self.psi, self.absorbed, d, nrm, yld, sums)
         return d, nrm, yld
+
+    def ensemble_sums(self, out=None):
+        """Device float64 [n_sums]: sum of the dipoles, of the norms and of
+        the yields over the batch (dipole_readout's sums), written into `out`
+        when given."""
+        if out is None:
+            out = torch.empty(self.n_sums, dtype=torch.float64, device=self.psi.device)
+        if not hasattr(self, "_rd_buf"):       # per-molecule outputs the sums reduce, kept for reuse
+            n = max(self.desc.n_mol, 1)
+            self._rd_buf = (torch.empty((n,) + tuple(self.d.shape[1:]), dtype=torch.float64,
+                                        device=self.psi.device),
+                            torch.empty(n, dtype=torch.float64, device=self.psi.device),
+                            torch.empty(n, dtype=torch.float64, device=self.psi.device))
+        d, nrm, yld = self._rd_buf
+        dipole_readout(self.desc, self.ws, self.psi, self.absorbed, d, nrm, yld, out)
+        return out
 
 
 def excited_r(mols):
     """Eq. (8) readout of a Molecules batch: (per-molecule <R>_e numerators,
     excited populations, ensemble <R>_e) as device tensors.  The ensemble
-    value is the ratio of the two sums, so it is NaN while the excited
-    population is exactly zero."""
+    value is the library's ratio of the two ensemble sums, so it is NaN while
+    the excited population is exactly zero."""
     n = max(mols.desc.n_mol, 1)
     dev = mols.psi.device
     num = torch.empty(n, dtype=torch.float64, device=dev)
     pop = torch.empty(n, dtype=torch.float64, device=dev)
-    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    sums = torch.empty(3, dtype=torch.float64, device=dev)
     _check(lib.excited_r_readout(C.byref(mols.desc), _ptr(mols.ws), _ptr(mols.psi), _ptr(num),
                                  _ptr(pop), _ptr(sums), current_stream()))
-    return num, pop, sums[0] / sums[1]
+    return num, pop, sums[2]
 
 
-def spectra(S_trans, S_inc_side, S_ref):
-    """T, R, A per monitor frequency from the flux readouts of a run (the
-    mon_k plane beyond the structure, the mon_k2 plane on the incident side)
-    and the incident-side flux of a reference run without the structure:
-    T = S_trans / S_ref, R = 1 - S_inc_side / S_ref, A = 1 - T - R."""
-    st = np.asarray(S_trans, np.float64)
-    si = np.asarray(S_inc_side, np.float64)
-    sr = np.asarray(S_ref, np.float64)
-    T = st / sr
-    R = (sr - si) / sr
-    return T, R, (si - st) / sr
+def spectra(fields, flux, flux_ref):
+    """(T, R, A) device tensors per monitor frequency (spectra_readout): flux
+    is the [2, n_freq] readout of a run with both detection planes, flux_ref
+    the [n_freq] incident-side flux of a reference run without the
+    structure."""
+    tra = torch.empty((3, fields.desc.n_freq), dtype=torch.float64, device=flux.device)
+    spectra_readout(fields.desc, flux.contiguous(), flux_ref.contiguous(), tra)
+    return tra[0], tra[1], tra[2]
 
 
 def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
@@ -501,10 +550,10 @@ class Coupled:
         self.J_mol.copy_(snap["J_mol"])
         self.n = snap["n"]
 
-    def yield_mean(self):
-        """Mean dissociated population (norm beyond r_diss plus absorbed)."""
-        _, _, y = self.mol.readout()
-        return y.mean()
+    def ensemble_sums(self, out=None):
+        """dipole_readout's ensemble sums of the current state (device
+        float64: the dipole components, then the norm and the yield)."""
+        return self.mol.ensemble_sums(out)
 
     def adjoint_buffers(self):
         """Allocate the adjoint state (same shapes as the forward state)."""
@@ -636,6 +685,7 @@ def version():
     return lib.msqd_version()
 
 
-__all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "CarrierBatch", "qd_init", "qd_step", "dipole_readout", "fdtd_init",
-           "fdtd_step", "flux_readout", "map_build", "map_csr", "coupled_step", "check_status", "jm_tables",
-           "MsqdError", "lib", "LIB_PATH", "EXPORTS"]
+__all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "CarrierBatch", "qd_init", "qd_step",
+           "dipole_readout", "fdtd_init", "fdtd_step", "flux_readout", "spectra_readout", "spectra",
+           "excited_r", "map_build", "map_csr", "coupled_step", "check_status", "jm_tables", "MsqdError", "lib",
+           "LIB_PATH", "EXPORTS"]

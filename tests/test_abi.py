@@ -42,6 +42,9 @@ def test_library_exports_every_declared_symbol(msqd):
 def test_workspace_queries_and_validation(msqd):
     d = msqd.qd_desc(10, 256, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 0)
     assert msqd.lib.qd_workspace_bytes(C.byref(d)) > 0
+    # dipole_readout's partial sums grow with the batch: 3 doubles per block of 1024 molecules
+    grow = msqd.qd_desc(10 + 3 * 1024, 256, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 0)
+    assert msqd.lib.qd_workspace_bytes(C.byref(grow)) == msqd.lib.qd_workspace_bytes(C.byref(d)) + 3 * 3 * 8
     bad = msqd.qd_desc(10, 100, 10, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 0)
     assert msqd.lib.qd_workspace_bytes(C.byref(bad)) == 0
     assert "n_r" in msqd.last_error()
@@ -156,12 +159,17 @@ def test_jm_basis_validation(msqd):
 
     assert ws(128, 1) > 0
     base = {jm: ws(128, jm, msqd.FP32) for jm in range(1, 6)}
-    # the general tables: sum (2j+1)^2 + sum (j_max+1-a)^2 + (j_max+1)(j_max+2)/2 + 3 (j_max+1)^2 doubles
+    # the general tables: sum (2j+1)^2 + sum (j_max+1-a)^2 + (j_max+1)(j_max+2)/2 + 3 (j_max+1)^2
+    # doubles after the common tables, then (256-aligned) the partial sums of
+    # dipole_readout: one block of 1024 molecules x (3 dipole components,
+    # norm, yield) here, against (1, norm, yield) in the m = 0 basis
     for jm in range(2, 6):
         n = sum((2 * j + 1) ** 2 for j in range(jm + 1)) + sum((jm + 1 - a) ** 2 for a in range(jm + 1)) \
             + (jm + 1) * (jm + 2) // 2 + 3 * (jm + 1) ** 2
         d0 = msqd.qd_desc(4, 128, jm, msqd.FP32, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, msqd.BASIS_M0)
-        assert base[jm] == msqd.lib.qd_workspace_bytes(C.byref(d0)) + 8 * n
+        common = msqd.lib.qd_workspace_bytes(C.byref(d0)) - 8 * 3
+        assert common % 256 == 0
+        assert base[jm] == (common + 8 * n + 255) // 256 * 256 + 8 * 5
     assert ws(256, 5, msqd.MIXED) > 0
     for n_r, jm, prec in [(128, 0, msqd.FP64), (128, 6, msqd.FP32)]:
         assert ws(n_r, jm, prec) == 0

@@ -30,26 +30,36 @@ def _oracle(cfg, nsteps):
 
 
 def _gpu_run(cfg, prec, nsteps):
+    """Per-step dipoles of every molecule and the library's ensemble sums
+    (dipole_readout: sum d, sum norm, sum yield) after every step."""
     from paper_2209_04487_amd import msqd
     sysm = msqd.Coupled(cfg, prec=prec)
     src = source_values(cfg, 0, nsteps)
     d = np.zeros((nsteps, sysm.mol.desc.n_mol))
+    sums = torch.zeros((nsteps, sysm.mol.n_sums), dtype=torch.float64, device="cuda")
     for n in range(nsteps):
         sysm.step(src[n:n + 1])
         d[n] = sysm.mol.d.cpu().numpy()
+        sysm.ensemble_sums(sums[n])
     torch.cuda.synchronize()
-    return sysm, d
+    return sysm, d, sums.cpu().numpy()
 
 
 def test_coupled_tiny_fp64_matches_oracle():
     cfg = get_config("cfg0")
     nsteps = cfg.n_steps
     banner(f"coupled cfg0 fp64 {nsteps} steps")
-    sysm, d = _gpu_run(cfg, "fp64", nsteps)
+    sysm, d, sums = _gpu_run(cfg, "fp64", nsteps)
     o, tr = _oracle(cfg, nsteps)
-    D = d.sum(axis=1)
+    D = sums[:, 0]
     assert np.linalg.norm(D - tr["D"]) / np.linalg.norm(tr["D"]) < 1e-10
     assert rel_err(d, tr["d"]) < 1e-10
+    # the ensemble sums equal the sums of the per-molecule values (the
+    # coupled step's own dipoles), and the final norm and yield sums the oracle's
+    np.testing.assert_allclose(D, d.sum(axis=1), rtol=1e-13, atol=1e-13 * np.abs(D).max())
+    np.testing.assert_allclose(sums[-1, 1], o.mol.norm(o.psi).sum(), rtol=1e-12)
+    np.testing.assert_allclose(sums[-1, 2], o.mol.dissociated(o.psi, o.absorbed).sum(), rtol=1e-10,
+                               atol=1e-20)
     # fields: relative to the field scale (the scattered E_y, E_z are small
     # differences of nearly equal cell currents, so their own scale is not a
     # meaningful denominator)
@@ -74,9 +84,9 @@ def test_coupled_tiny_reduced_precision_dipole_error(prec):
     cfg = get_config("cfg0")
     nsteps = cfg.n_steps
     banner(f"coupled cfg0 {prec} {nsteps} steps")
-    sysm, d = _gpu_run(cfg, prec, nsteps)
+    sysm, d, sums = _gpu_run(cfg, prec, nsteps)
     o, tr = _oracle(cfg, nsteps)
-    D = d.sum(axis=1)
+    D = sums[:, 0]
     err = np.linalg.norm(D - tr["D"]) / np.linalg.norm(tr["D"])
     print(f"{prec} relative dipole-trace error {err:.3e}")
     assert err < 1e-4
@@ -100,7 +110,7 @@ def test_coupled_multirate_fp64_matches_oracle(mol_every):
     chunk = 3
     for s in range(0, nsteps, chunk):
         sysm.step(src[s:s + chunk])
-        D[s:s + chunk] = float(sysm.mol.d.sum())   # constant between updates
+        D[s:s + chunk] = float(sysm.ensemble_sums()[0])   # constant between updates
     torch.cuda.synchronize()
     o = CoupledOracle(cfg, mol_every=mol_every)
     Do = np.zeros(nsteps)

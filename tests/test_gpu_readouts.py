@@ -6,8 +6,13 @@
   ensemble <R>_e as the population-weighted ratio;
 - the two-plane monitor (transmitted side and incident side) of a coupled
   run under the CW drive with a 5 fs turn-on: both planes' flux spectra at
-  1e-9 of the oracle's, and T/R/A from the GPU fluxes against the oracle's
-  spectra helper."""
+  1e-9 of the oracle's, and T/R/A (spectra_readout) against the oracle's
+  spectra helper, on the oracle's fluxes (1e-8) and on the same GPU fluxes
+  (1e-13);
+- a carrier batch equal to separate runs bit for bit, its ensemble dipoles
+  read with dipole_readout's sums.
+Also the ensemble sums of dipole_readout against the sums of the per-molecule
+values at ragged batch sizes, the (j, m) basis' three components included."""
 
 import numpy as np
 import pytest
@@ -55,7 +60,8 @@ def test_two_plane_monitor_and_spectra_under_cw_drive():
     assert abs(src[0]) < 1e-3 * np.abs(src).max()            # smooth turn-on
     sysm = msqd.Coupled(cfg, prec="fp64")
     sysm.step(src)
-    S = sysm.fields.flux().cpu().numpy()
+    S_dev = sysm.fields.flux()
+    S = S_dev.cpu().numpy()
     assert S.shape == (2, cfg.n_freq)
     o = CoupledOracle(cfg)
     for n in range(nsteps):
@@ -66,12 +72,19 @@ def test_two_plane_monitor_and_spectra_under_cw_drive():
     # vacuum reference run (no molecules) for the incident flux
     ref = msqd.Coupled(ref_cfg, prec="fp64", cells=np.zeros(0, np.int32))
     ref.step(src)
-    Sref = ref.fields.flux().cpu().numpy()
-    T, R, A = msqd.spectra(S[0], S[1], Sref[1])
+    Sref_dev = ref.fields.flux()
+    Sref = Sref_dev.cpu().numpy()
+    T, R, A = (x.cpu().numpy() for x in msqd.spectra(sysm.fields, S_dev, Sref_dev[1]))
     oT, oR, oA = oracle_spectra(o.monitor.flux(), o.monitor2.flux(), Sref[1])
     np.testing.assert_allclose(T, oT, rtol=1e-8)
     np.testing.assert_allclose(R, oR, atol=1e-8)
     np.testing.assert_allclose(A, oA, atol=1e-8)
+    # the library's T, R, A from the same GPU fluxes against the oracle's
+    # spectra helper applied to them
+    gT, gR, gA = oracle_spectra(S[0], S[1], Sref[1])
+    np.testing.assert_allclose(T, gT, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(R, gR, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(A, gA, rtol=1e-13, atol=1e-15)
 
 
 def test_carrier_batch_equals_separate_runs():
@@ -89,16 +102,51 @@ def test_carrier_batch_equals_separate_runs():
         batch.step([s[t:t + 1] for s in srcs])
         for i, sysm in enumerate(batch.systems):
             with torch.cuda.stream(batch.streams[i]):
-                traces[i, t] = float(sysm.mol.d.sum())
+                traces[i, t] = float(sysm.ensemble_sums()[0])
     batch.synchronize()
     for i, c in enumerate(cfgs):
         alone = msqd.Coupled(c, prec="mixed")
         tr = np.zeros(nsteps)
         for t in range(nsteps):
             alone.step(srcs[i][t:t + 1])
-            tr[t] = float(alone.mol.d.sum())
+            tr[t] = float(alone.ensemble_sums()[0])
         torch.cuda.synchronize()
         assert np.array_equal(tr, traces[i]), i
         assert torch.equal(alone.fields.Ex, batch.systems[i].fields.Ex)
         assert torch.equal(alone.mol.psi, batch.systems[i].mol.psi)
     assert not np.array_equal(traces[0], traces[2])
+
+
+@pytest.mark.parametrize("basis,j_max,n_mol", [("m0", 4, 1), ("m0", 4, 1023), ("m0", 4, 1025),
+                                               ("m0", 10, 2500), ("jm", 2, 1500), ("m0", 4, 0)])
+def test_ensemble_sums_match_per_molecule_sums(basis, j_max, n_mol):
+    """dipole_readout's FP64 sums (two-stage, blocks of 1024 molecules)
+    against the sums of the per-molecule readouts it writes, on seeded random
+    states: both ragged block tails, one block, several, the (j, m) basis'
+    [n][3] dipoles, and the empty batch (zeros).  Repeated calls give the
+    same bits."""
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg0", j_max=j_max, n_mol=max(n_mol, 1), basis=basis)
+    banner(f"ensemble sums {basis} j_max={j_max} n_mol={n_mol}")
+    mols = msqd.Molecules(n_mol, cfg.n_r, j_max, cfg.r_min, cfg.r_max, cfg.mass, cfg.dt_au,
+                          *potentials(cfg), np.ones(cfg.n_r), prec="fp64", basis=basis)
+    if n_mol:
+        rng = np.random.default_rng(n_mol)
+        psi = rng.standard_normal(tuple(mols.psi.shape) + (2,))
+        mols.psi.copy_(torch.view_as_complex(torch.as_tensor(psi)))
+        mols.absorbed.copy_(torch.as_tensor(rng.uniform(0, 1e-3, n_mol)))
+    sums = torch.zeros(mols.n_sums, dtype=torch.float64, device="cuda") + 7.0
+    d, nrm, yld = mols.readout(sums)
+    again = mols.ensemble_sums()
+    torch.cuda.synchronize()
+    s = sums.cpu().numpy()
+    assert np.array_equal(s, again.cpu().numpy())
+    if n_mol == 0:
+        assert np.all(s == 0.0)
+        return
+    nc = mols.n_sums - 2
+    dd = d.cpu().numpy().reshape(n_mol, nc)
+    for c in range(nc):
+        np.testing.assert_allclose(s[c], dd[:, c].sum(), rtol=1e-12, atol=1e-12 * np.abs(dd).sum())
+    np.testing.assert_allclose(s[nc], nrm.cpu().numpy()[:n_mol].sum(), rtol=1e-13)
+    np.testing.assert_allclose(s[nc + 1], yld.cpu().numpy()[:n_mol].sum(), rtol=1e-13)

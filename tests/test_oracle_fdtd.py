@@ -163,14 +163,3 @@ def test_reflection_and_absorption_spectra_of_a_dielectric_interface():
     np.testing.assert_allclose(R, ((n - 1) / (n + 1)) ** 2, atol=2e-3)
     np.testing.assert_allclose(T, 4 * n / (1 + n) ** 2, atol=2e-3)
     np.testing.assert_allclose(A, 0.0, atol=3e-3)
-
-
-def test_product_spectra_helper_agrees_with_oracle_definition():
-    """The library's host helper (T, R, A from three flux spectra) against
-    the oracle's, on arbitrary positive spectra (no GPU needed)."""
-    from oracle.fdtd import spectra
-    from paper_2209_04487_amd.msqd import spectra as lib_spectra
-    rng = np.random.default_rng(2)
-    st, si, sr = rng.uniform(0.1, 1.0, (3, 16))
-    for a, b in zip(spectra(st, si, sr), lib_spectra(st, si, sr)):
-        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
