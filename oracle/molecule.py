@@ -27,6 +27,7 @@ Array layout: psi[mol, s, J, r] complex128 with s in {0: g, 1: e}.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft as sfft
 from numpy.polynomial.legendre import leggauss
 from scipy.special import eval_legendre
 
@@ -89,8 +90,10 @@ class MoleculeModel:
 
     # ------------------------------------------------------------------ factors
     def kinetic_half(self, psi):
-        """F^-1 diag(exp(-i kappa^2 dt / 4 mu)) F along r, per (mol, s, J) line."""
-        return np.fft.ifft(self.kin_half * np.fft.fft(psi, axis=-1), axis=-1)
+        """F^-1 diag(exp(-i kappa^2 dt / 4 mu)) F along r, per (mol, s, J) line
+        (forward transform exp(-2 pi i m k / N), inverse with 1/N; the batch
+        of lines spread over all host threads)."""
+        return sfft.ifft(self.kin_half * sfft.fft(psi, axis=-1, workers=-1), axis=-1, workers=-1)
 
     def potential_half(self, psi):
         return psi * self.v_half[None]

@@ -26,6 +26,7 @@ The dipole is the vector d_c = <psi| mu12 sigma_x (x) D_c |psi>.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft as sfft
 from numpy.polynomial.legendre import leggauss
 from scipy.special import sph_harm_y
 
@@ -82,7 +83,7 @@ class MoleculeJM:
             self.mask[sel] = np.cos(np.pi * (self.r[sel] - ra) / (2.0 * absorb_width)) ** 0.125
 
     def kinetic_half(self, psi):
-        return np.fft.ifft(self.kin_half * np.fft.fft(psi, axis=-1), axis=-1)
+        return sfft.ifft(self.kin_half * sfft.fft(psi, axis=-1, workers=-1), axis=-1, workers=-1)
 
     def potential_half(self, psi):
         return psi * self.v_half[None]
