@@ -179,9 +179,9 @@ def default_first_step(cfg):
 
 
 def stencil_bytes_per_cell(prec):
-    """Algorithmic bytes per cell-update of the two stencil kernels as
-    launched: H update reads E (3) and H (3), writes H (3); E update reads H
-    (3), E (3), material ids (3 B), writes E (3)."""
+    """Bytes per cell-update of the two stencil kernels as launched: H update
+    reads E (3) and H (3), writes H (3); E update reads H (3), E (3),
+    material ids (3 B), writes E (3)."""
     w = 8 if prec == "fp64" else 4
     return 18 * w + 3
 
@@ -194,9 +194,33 @@ def stencil_min_bytes_per_cell(prec):
     return 12 * w + 3
 
 
-def run_coupled(cfg, prec, steps, warmup, n0, mol_every=1):
+def material_fractions(cfg):
+    """(metal share of the E-component locations, averaged over the three
+    components; share of the cells in the CPML slabs)."""
+    from workloads.configs import MAT_METAL
+    from workloads.geometry import material_map
+    mat = material_map(cfg)
+    return float((mat == MAT_METAL).mean()), 2.0 * cfg.npml / cfg.nz
+
+
+def stencil_alg_bytes_per_cell(cfg, prec):
+    """Algorithmic bytes per cell-update of a whole field step (the count the
+    roofline is taken against): E and H each read and written once (12
+    words), the Drude current read and written at the metal edges (2 words
+    per metal E-component location, i.e. 6 words times the metal share), the
+    four CPML auxiliaries read and written in the CPML slabs (8 words times
+    their share of the cells), and the material ids (3 B)."""
+    w = 8 if prec == "fp64" else 4
+    f_metal, f_pml = material_fractions(cfg)
+    return w * (12.0 + 6.0 * f_metal + 8.0 * f_pml) + 3.0
+
+
+def run_coupled(cfg, prec, steps, warmup, n0, mol_every=1, time_mol=False):
     """Time `steps` coupled steps (after `warmup` untimed ones) with HIP
-    events on the stream the steps are launched on."""
+    events on the stream the steps are launched on.  With time_mol, the
+    library also records HIP events around each molecular-step launch inside
+    the timed window (msqd_mol_timing_begin/end), giving the kernel's own
+    average duration in that same window."""
     import torch
 
     from paper_2209_04487_amd import msqd
@@ -209,13 +233,19 @@ def run_coupled(cfg, prec, steps, warmup, n0, mol_every=1):
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    if time_mol:
+        msqd.mol_timing_begin(steps)
     t_start.record(stream)
     msqd.coupled_step(sysm.desc, sysm.state, src[warmup:], n0 + warmup)
     t_end.record(stream)
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end)
-    msqd.check_status(sysm.mol.ws)
     out = {"ms": ms, "n_mol": sysm.mol.desc.n_mol}
+    if time_mol:
+        mol_total, n_launch = msqd.mol_timing_end()
+        out["mol_kernel_ms"] = mol_total / max(n_launch, 1)
+        out["mol_launches"] = n_launch
+    msqd.check_status(sysm.mol.ws)
     del sysm
     torch.cuda.empty_cache()
     return out
@@ -231,17 +261,35 @@ def run_accuracy(cfg, prec, steps, n0):
     from workloads.pulses import source_values
     sysm = msqd.Coupled(cfg, prec=prec)
     src = source_values(cfg, n0, steps)
-    acc = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    # one row of ensemble sums (dipole, norm, yield; dipole_readout) per step
+    sums = torch.zeros((steps, sysm.mol.n_sums), dtype=torch.float64, device="cuda")
     for s in range(steps):
         msqd.coupled_step(sysm.desc, sysm.state, src[s:s + 1], n0 + s)
-        acc[s] = sysm.mol.d.sum()
+        sysm.ensemble_sums(sums[s])
     flux = sysm.fields.flux().cpu().numpy()
-    y = float(sysm.yield_mean())
     msqd.check_status(sysm.mol.ws)
-    out = {"D": acc.cpu().numpy(), "flux": flux, "yield": y}
+    sums = sums.cpu().numpy()
+    out = {"D": sums[:, 0], "flux": flux, "yield": sums[-1, -1] / sysm.mol.desc.n_mol}
     del sysm
     torch.cuda.empty_cache()
     return out
+
+
+def dissociating_config(cfg):
+    """A variant of a workload in which the dissociation probability is a
+    real signal: lighter nuclei (500 m_e), a carrier at the vertical gap
+    (0.45 Eh), a short strong pulse (FWHM 2 fs, peak 5e-3 au, centred at
+    3 fs) and r_diss = 4 a0, so that the excited packet crosses r_diss within
+    the window.  Grid, geometry, molecules and radial/rotational basis stay
+    those of the workload."""
+    return cfg.replace(mass=500.0, omega_h=0.45, e0_au=5e-3, fwhm_fs=2.0, t0_steps=None, t0_fs=3.0,
+                       r_diss=4.0)
+
+
+def dissociating_steps(cfg):
+    """Steps of the dissociating window: the pulse peak (at the slab about
+    900 steps in) and 1,100 steps of dissociation after it."""
+    return 2000
 
 
 def rel_l2(a, b):
@@ -349,11 +397,15 @@ def run_scale(steps):
     return out
 
 
-def run_adjoint(steps):
+def run_adjoint(steps, fp64_check=True):
     """Gradient of the dissociated population of the differentiation
     workload (one SRR cell, 20,000 molecules, N_r = 128, J <= 6, FP32) over a
     window of `steps` steps with one checkpoint per 200 steps: forward run,
-    segment recompute and reverse steps, timed as one call."""
+    segment recompute and reverse steps, timed as one call.  With fp64_check
+    the same gradient is also taken in the FP64 form and the FP32 yield and
+    gradient are reported against it: at the workload's own parameters the
+    pulse barely excites the molecules, and the comparison says whether FP32
+    resolves the yield and its gradient there."""
     import torch
 
     from paper_2209_04487_amd.grad import yield_and_gradient
@@ -367,10 +419,28 @@ def run_adjoint(steps):
     Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp32")
     torch.cuda.synchronize()
     dt = time.time() - t
-    return {"workload": f"SRR cell {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.n_mol} molecules, N_r={cfg.n_r}, "
-                        f"J<={cfg.j_max}, FP32, checkpoint every {cfg.ckpt_every}",
-            "steps": steps, "s_total": dt, "ms_per_forward_plus_reverse_step": dt * 1e3 / steps,
-            "yield": Y, "grad_norm_knots": float(np.linalg.norm(dk)), "dY_domega": dw}
+    torch.cuda.empty_cache()
+    out = {"workload": f"SRR cell {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.n_mol} molecules, N_r={cfg.n_r}, "
+                       f"J<={cfg.j_max}, FP32, checkpoint every {cfg.ckpt_every}",
+           "steps": steps, "s_total": dt, "ms_per_forward_plus_reverse_step": dt * 1e3 / steps,
+           "yield": Y, "grad_norm_knots": float(np.linalg.norm(dk)), "dY_domega": dw}
+    if fp64_check:
+        t = time.time()
+        Y64, dk64, dw64 = yield_and_gradient(cfg, kn, cfg.omega, prec="fp64")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        rel = {"yield": abs(Y - Y64) / abs(Y64),
+               "grad_knots": float(np.abs(dk - dk64).max() / np.abs(dk64).max()),
+               "dY_domega": abs(dw - dw64) / abs(dw64)}
+        out["fp64"] = {"s_total": time.time() - t, "yield": Y64,
+                       "grad_norm_knots": float(np.linalg.norm(dk64)), "dY_domega": dw64}
+        out["fp32_vs_fp64_rel"] = rel
+        out["fp32_resolves_yield"] = bool(rel["yield"] <= 1e-3)
+        out["fp32_resolves_gradient"] = bool(max(rel["grad_knots"], rel["dY_domega"]) <= 1e-3)
+        if not out["fp32_resolves_yield"]:
+            out["note"] = ("the yield itself (FP64 value above) lies below what FP32 resolves at these parameters "
+                           "(round-off of the ground-state tail beyond r_diss); the FP32 yield is throughput only")
+    return out
 
 
 def calibration_copy(nbytes=1 << 30, reps=3):
@@ -436,15 +506,42 @@ def time_stencil(cfg, prec, launches):
     return ms
 
 
+def stencil_entry(cfg, prec, launches):
+    """The H + E stencil pair on a workload's grid: time per field step, cell
+    updates per second, and the HBM fraction against the algorithmic bytes of
+    a whole field step (stencil_alg_bytes_per_cell), with the two-kernel and
+    the fused 12-word counts beside it."""
+    ms = time_stencil(cfg, prec, launches)
+    n_c = cfg.nx * cfg.ny * cfg.nz
+    rate = n_c / (ms / 1e3)
+    alg = stencil_alg_bytes_per_cell(cfg, prec)
+    f_metal, f_pml = material_fractions(cfg)
+    return {"grid": f"{cfg.nx}x{cfg.ny}x{cfg.nz}", "prec": prec, "ms_per_step": ms, "cell_updates_per_s": rate,
+            "achieved_GBs": alg * rate / 1e9, "frac": alg * rate / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_cell": alg, "bytes_counted": ("12 words (E, H read and written once) + 6 words x metal "
+                                                     f"share {f_metal:.4f} + 8 words x CPML share {f_pml:.3f} "
+                                                     "+ 3 B material ids"),
+            "two_kernel": {"bytes_per_cell": stencil_bytes_per_cell(prec),
+                           "frac": stencil_bytes_per_cell(prec) * rate / 1e9 / HBM_PEAK_GBS},
+            "fused_12_words": {"bytes_per_cell": stencil_min_bytes_per_cell(prec),
+                               "frac": stencil_min_bytes_per_cell(prec) * rate / 1e9 / HBM_PEAK_GBS}}
+
+
 def cpu_baseline(cfg, budget_s=20.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (about budget_s seconds): the full-grid field update for a few
     steps and a block of 2,048 molecules for up to 30 steps; the coupled-step
-    rate for all molecules is n_mol / (t_fields + n_mol * t_molecule)."""
+    rate for all molecules is n_mol / (t_fields + n_mol * t_molecule).  The
+    oracle's radial FFTs run on scipy.fft with all host threads.  Also the
+    whole tiny parity run (24^3 grid, 64 molecules, 500 coupled steps) as the
+    oracle computes it."""
+    from oracle.coupled import CoupledOracle
     from oracle.fdtd import yee_from_config
     from oracle.molecule import model_from_config
+    from workloads import get_config
     from workloads.geometry import eps_table, material_map
     from workloads.molecule_inputs import morse_v0, potentials
+    from workloads.pulses import source_values
     t0 = time.time()
     yee = yee_from_config(cfg, material_map(cfg), eps_table(cfg))
     n_f = 0
@@ -465,14 +562,18 @@ def cpu_baseline(cfg, budget_s=20.0):
     while True:
         psi, ab = m.step(psi, E, ab)
         n_m += 1
-        if time.time() - t > 0.7 * budget_s or n_m >= 30:
+        if time.time() - t > 0.6 * budget_s or n_m >= 30:
             break
     t_mol = (time.time() - t) / (n_m * n_blk)
     rate = cfg.n_mol / (t_field + cfg.n_mol * t_mol)
-    threads = 1
+    c0 = get_config("cfg0")
+    t = time.time()
+    CoupledOracle(c0).run(source_values(c0, 0, c0.n_steps))
+    t_tiny = time.time() - t
+    blas = 1
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         pass
     model = "unknown"
@@ -484,12 +585,16 @@ def cpu_baseline(cfg, budget_s=20.0):
                     break
     except OSError:
         pass
-    return {"value": rate, "unit": "molecule-steps/s", "cores": threads, "kind": "oracle",
-            "cpu_count": os.cpu_count(), "cpu_model": model,
-            "sample": (f"FP64 NumPy oracle: full {cfg.nx}x{cfg.ny}x{cfg.nz} field update x{n_f} "
+    ncpu = os.cpu_count() or 1
+    return {"value": rate, "unit": "molecule-steps/s", "cores": max(ncpu, blas), "kind": "oracle",
+            "cpu_count": ncpu, "cpu_model": model,
+            "sample": (f"FP64 NumPy/SciPy oracle: full {cfg.nx}x{cfg.ny}x{cfg.nz} field update x{n_f} "
                        f"({t_field:.3f} s/step) and {n_blk} molecules x {n_m} steps "
                        f"({t_mol * 1e3:.3f} ms/molecule-step), combined for {cfg.n_mol} molecules; "
-                       f"FFTs single-threaded, BLAS {threads} threads; {time.time() - t0:.1f} s total")}
+                       f"radial FFTs on scipy.fft with {ncpu} workers, BLAS {blas} threads, elementwise NumPy "
+                       f"on one thread; {time.time() - t0:.1f} s total"),
+            "tiny_parity_run": {"workload": "24^3 vacuum grid, 64 molecules, N_r=128, J<=4, 500 coupled steps",
+                                "s_total": t_tiny, "molecule_steps_per_s": 64 * 500 / t_tiny}}
 
 
 def main():
@@ -508,6 +613,9 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload (4,000 forward + reverse steps) and its "
                          "forward-only timing, for a kernel trace of the adjoint")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed coupled window of the precision form (the run a kernel trace of the "
+                         "headline is taken from)")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm", "jm5"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
@@ -572,12 +680,23 @@ def main():
         return
 
     log(f"mixed coupled run: {cfg.n_mol} molecules, {W}+{K} steps from step {n0}")
-    mixed = run_coupled(cfg, "mixed", K, W, n0)
+    mixed = run_coupled(cfg, "mixed", K, W, n0, time_mol=True)
     value = mixed["n_mol"] * K / (mixed["ms"] / 1e3)
+    mol_ms = mixed["mol_kernel_ms"]
+    unit_bytes = mol_bytes_per_step(cfg, "mixed")
+    unit_flops = mol_flops_per_step(cfg)
+    achieved_gbs = unit_bytes * cfg.n_mol / (mol_ms / 1e3) / 1e9
+    achieved_tf = unit_flops * cfg.n_mol / (mol_ms / 1e3) / 1e12
+    if args.headline_only:
+        print(json.dumps({"value": value, "unit": "molecule-steps/s", "steps": K, "warmup": W,
+                          "ms_per_step": mixed["ms"] / K, "mol_kernel_ms": mol_ms,
+                          "mol_launches": mixed["mol_launches"], "first_step": n0,
+                          "mol_kernel_TFLOPs": achieved_tf, "mol_kernel_GBs": achieved_gbs}), flush=True)
+        return
     fp64 = None
     if not args.no_fp64:
         log("fp64 coupled run")
-        fp64 = run_coupled(cfg64, "fp64", K, W, n0)
+        fp64 = run_coupled(cfg64, "fp64", K, W, n0, time_mol=True)
     acc = None
     if args.acc_steps > 0 and not args.no_fp64:
         log(f"accuracy: {args.acc_steps} steps of both forms from step {n0}")
@@ -586,9 +705,25 @@ def main():
         acc = {"steps": f"{n0}..{n0 + args.acc_steps}",
                "dipole_trace_rel_l2": rel_l2(am["D"], a64["D"]),
                "flux_spectrum_rel_l2": rel_l2(am["flux"], a64["flux"]),
-               "yield_rel": abs(am["yield"] - a64["yield"]) / max(abs(a64["yield"]), 1e-300),
-               "yield_fp64": a64["yield"],
+               "yield_abs_err": abs(am["yield"] - a64["yield"]),
+               "yield_fp64": a64["yield"], "yield_mixed": am["yield"],
                "dipole_peak_fp64": float(np.abs(a64["D"]).max())}
+        # the dissociation probability is below what FP32 resolves in that
+        # window (the ground-state tail beyond r_diss); a dissociating variant
+        # of the same geometry and pulse shape makes it a real signal
+        dc = dissociating_config(cfg)
+        n_d = dissociating_steps(dc)
+        log(f"accuracy, dissociating variant: {n_d} steps of both forms")
+        dm = run_accuracy(dc, "mixed", n_d, 0)
+        d64 = run_accuracy(dc.replace(precision="fp64"), "fp64", n_d, 0)
+        acc["dissociating_variant"] = {
+            "workload": (f"same grid, molecules and pulse shape; reduced mass {dc.mass:g} m_e, carrier "
+                         f"{dc.omega_h:g} Eh at the vertical gap, peak {dc.e0_au:g} au, r_diss {dc.r_diss:g} a0, "
+                         f"steps 0..{n_d}"),
+            "yield_fp64": d64["yield"], "yield_mixed": dm["yield"],
+            "yield_rel_err": abs(dm["yield"] - d64["yield"]) / abs(d64["yield"]),
+            "dipole_trace_rel_l2": rel_l2(dm["D"], d64["D"]),
+            "flux_spectrum_rel_l2": rel_l2(dm["flux"], d64["flux"])}
 
     M = 40
     k_mr = max(M, (K // M) * M)
@@ -629,32 +764,18 @@ def main():
     if not args.no_scale:
         log("scale workload: 700,000 molecules, one run and a 3-carrier batch")
         scale = run_scale(10)
-        log("adjoint: differentiation workload, 4,000 steps")
-        adjoint = run_adjoint(4000)
+        log("adjoint: differentiation workload, 4,000 steps, FP32 and FP64")
+        adjoint = run_adjoint(4000, fp64_check=not args.no_fp64)
 
-    log("kernel timing")
+    log("stencil timing")
     launches = max(10, min(K, 100))
-    mol_ms = time_mol_kernel(cfg, "mixed", launches)
-    unit_bytes = mol_bytes_per_step(cfg, "mixed")
-    unit_flops = mol_flops_per_step(cfg)
-    achieved_gbs = unit_bytes * cfg.n_mol / (mol_ms / 1e3) / 1e9
-    achieved_tf = unit_flops * cfg.n_mol / (mol_ms / 1e3) / 1e12
     traffic, traffic_src = counter_traffic()
-    sten_ms = time_stencil(cfg, "mixed", launches)
     cells = cfg.nx * cfg.ny * cfg.nz
-    sten_gbs = stencil_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
+    stencil = stencil_entry(cfg, "mixed", launches)
     # cell-updates/s of the other grids: the differentiation cell (FP32), the
     # nanohole film (precision form) and the SRR grid in FP64
-    sten_grids = {}
-    for name, pr in (("cfg3", "fp32"), ("cfg4", "mixed"), ("cfg1", "fp64")):
-        c = get_config(name)
-        ms_g = time_stencil(c, pr, launches)
-        n_c = c.nx * c.ny * c.nz
-        gbs = stencil_bytes_per_cell(pr) * n_c / (ms_g / 1e3) / 1e9
-        sten_grids[name] = {"grid": f"{c.nx}x{c.ny}x{c.nz}", "prec": pr, "ms_per_step": ms_g,
-                            "cell_updates_per_s": n_c / (ms_g / 1e3), "achieved_GBs": gbs,
-                            "frac": gbs / HBM_PEAK_GBS, "bytes_per_cell": stencil_bytes_per_cell(pr)}
-    mol64_ms = time_mol_kernel(cfg64, "fp64", max(5, launches // 4)) if not args.no_fp64 else None
+    stencil["other_grids"] = {name: stencil_entry(get_config(name), pr, launches)
+                              for name, pr in (("cfg3", "fp32"), ("cfg4", "mixed"), ("cfg1", "fp64"))}
 
     cpu = None
     if not args.no_cpu:
@@ -686,6 +807,8 @@ def main():
             "traffic": None if traffic is None else traffic,
             "traffic_source": traffic_src,
             "kernel": "mol_step_kernel<float,256,bf16x3,single-step>", "kernel_ms": mol_ms,
+            "kernel_ms_source": (f"HIP events around each of the {mixed['mol_launches']} molecular-step launches "
+                                 f"inside the timed window, on the coupled step's stream"),
             "flops_per_molecule_step": unit_flops,
             "mfma_flops_per_molecule_step": mol_mfma_flops_per_step(cfg),
             "mfma": {"achieved": mol_mfma_flops_per_step(cfg) * cfg.n_mol / (mol_ms / 1e3) / 1e12,
@@ -698,15 +821,10 @@ def main():
                     "frac": achieved_gbs / HBM_PEAK_GBS, "bytes_per_molecule_step": unit_bytes,
                     "algorithmic_bytes_per_launch": unit_bytes * cfg.n_mol},
         },
-        "stencil": {"ms_per_step": sten_ms, "cell_updates_per_s": cells / (sten_ms / 1e3),
-                    "achieved_GBs": sten_gbs, "frac": sten_gbs / HBM_PEAK_GBS,
-                    "bytes_per_cell": stencil_bytes_per_cell("mixed"),
-                    "frac_vs_fused_minimum": stencil_min_bytes_per_cell("mixed") * cells / (sten_ms / 1e3) / 1e9
-                    / HBM_PEAK_GBS,
-                    "other_grids": sten_grids},
+        "stencil": stencil,
         "fp64": None if fp64 is None else {
             "value": fp64["n_mol"] * K / (fp64["ms"] / 1e3), "ms_per_step": fp64["ms"] / K,
-            "mol_kernel_ms": mol64_ms},
+            "mol_kernel_ms": fp64["mol_kernel_ms"]},
         "speedup_vs_fp64": None if fp64 is None else fp64["ms"] / mixed["ms"],
         "accuracy_vs_fp64": acc,
         "multirate": multirate,

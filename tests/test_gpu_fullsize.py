@@ -43,33 +43,48 @@ EA0 = 8.4783536255e-30
 
 @pytest.mark.parametrize("name,prec", [("cfg1", "fp64"), ("cfg2", "mixed"), ("cfg4", "mixed")])
 def test_full_batch_sampled_molecules(name, prec):
+    """The whole batch of a workload in one single-step launch (the launch
+    the coupled step makes), with seeded random two-state, all-J states
+    planted in a sample of molecules (the last workgroup included) so that
+    every channel, the J <-> angle coupling and the absorber carry amplitude
+    of the state's own size; seeded fields of either sign, one strong enough
+    for the large-angle branch.  Wavepackets element by element, dipoles and
+    absorbed norms against the oracle."""
+    from gpu_helpers import random_state
     from paper_2209_04487_amd import msqd
+    torch.cuda.empty_cache()
     cfg = get_config(name)
-    banner(f"full batch {name} {prec}: {cfg.n_mol} molecules, 2 steps")
+    banner(f"full batch {name} {prec}: {cfg.n_mol} molecules, planted states, 1 step")
     rng = np.random.default_rng(11)
     E = rng.uniform(-2e-3, 2e-3, cfg.n_mol)
+    sample = np.sort(rng.choice(cfg.n_mol - 1, 15, replace=False))
+    sample = np.concatenate([sample, [cfg.n_mol - 1]])          # the last workgroup
+    E[sample[0]] = 0.3                                            # large-angle branch
+    E[sample[1]] = 0.0
     mols = msqd.Molecules.from_config(cfg, prec=prec)
-    Et = torch.as_tensor(E, device="cuda")
-    for _ in range(2):
-        mols.step(Et)
+    dr = (cfg.r_max - cfg.r_min) / cfg.n_r
+    psi0 = random_state(31, len(sample), cfg.n_j, cfg.n_r, dr)
+    idx = torch.as_tensor(sample, device="cuda")
+    mols.psi[idx] = torch.as_tensor(psi0, device="cuda").to(mols.psi.dtype)
+    psi0 = mols.psi[idx].to(torch.complex128).cpu().numpy()       # the state as stored
+    mols.step(torch.as_tensor(E, device="cuda"))
     torch.cuda.synchronize()
-    sample = np.sort(rng.choice(cfg.n_mol, 16, replace=False))
-    sample[-1] = cfg.n_mol - 1                      # the last workgroup
     ug, ue, mu = potentials(cfg)
     om = model_from_config(cfg, ug, ue, mu)
-    from workloads.molecule_inputs import morse_v0
-    psi = om.initial_state(len(sample), morse_v0(cfg))
-    ab = np.zeros(len(sample))
-    for _ in range(2):
-        psi, ab = om.step(psi, E[sample], ab)
-    got = mols.psi[torch.as_tensor(sample, device="cuda")].to(torch.complex128).cpu().numpy()
+    psi, ab = om.step(psi0, E[sample], np.zeros(len(sample)))
+    got = mols.psi[idx].to(torch.complex128).cpu().numpy()
     assert rel_err(got, psi) < TOL[prec]
-    d_gpu = mols.d.cpu().numpy()[sample]
-    assert rel_err(d_gpu, om.dipole(psi)) < 10 * TOL[prec]
-    # the absorbed norm is a probability: in two steps from the ground state
-    # it is round-off of the far tail, ~eps^2 of the working precision
-    ab_gpu = mols.absorbed.cpu().numpy()[sample]
-    np.testing.assert_allclose(ab_gpu, ab, rtol=10 * TOL[prec], atol=1e-24 if prec == "fp64" else 1e-10)
+    assert rel_err(mols.d[idx].cpu().numpy(), om.dipole(psi)) < 10 * TOL[prec]
+    assert ab.min() > 1e-3                                        # the absorber removes real norm
+    np.testing.assert_allclose(mols.absorbed[idx].cpu().numpy(), ab, rtol=10 * TOL[prec])
+    # the molecules outside the sample are untouched Morse starts: their
+    # norm stays 1 to the working precision
+    _, nrm, _ = mols.readout()
+    rest = np.ones(cfg.n_mol, bool)
+    rest[sample] = False
+    assert np.abs(nrm.cpu().numpy()[:cfg.n_mol][rest] - 1.0).max() < (1e-12 if prec == "fp64" else 1e-5)
+    del mols
+    torch.cuda.empty_cache()
 
 
 def test_full_jm_general_sampled_molecules():
