@@ -537,7 +537,7 @@ static int readout_impl(const qd_desc* d, const void* ws, const void* psi, const
     MolArgs a = make_mol_args(d, ws);
     a.n_steps = 0;
     a.psi = const_cast<void*>(psi);
-    a.E_mol = absorbed;  // unused with n_steps = 0 (any valid pointer)
+    a.E_mol = nullptr;   // no step: the kernels read no field
     a.absorbed = const_cast<double*>(absorbed);
     a.d_mol = d_mol;
     a.norm_mol = norm_mol;

@@ -656,14 +656,17 @@ void mol_step_kernel(MolArgs a) {
   tb.mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
   tb.cj = reinterpret_cast<const double*>(ws + a.lay.cj_d);
 
-  // field seen by this molecule (gathered from E_x at its cell, or given)
-  double Ed;
-  if (a.Ex != nullptr) {
-    const int c = a.cell_of_mol[mol];
-    Ed = (a.ex_is_float ? static_cast<double>(reinterpret_cast<const float*>(a.Ex)[c])
-                        : reinterpret_cast<const double*>(a.Ex)[c]) * a.inv_eau;
-  } else {
-    Ed = a.E_mol[mol];
+  // field seen by this molecule (gathered from E_x at its cell, or given);
+  // a readout-only launch (no step) reads no field
+  double Ed = 0.0;
+  if (ONE || a.n_steps > 0) {
+    if (a.Ex != nullptr) {
+      const int c = a.cell_of_mol[mol];
+      Ed = (a.ex_is_float ? static_cast<double>(reinterpret_cast<const float*>(a.Ex)[c])
+                          : reinterpret_cast<const double*>(a.Ex)[c]) * a.inv_eau;
+    } else {
+      Ed = a.E_mol[mol];
+    }
   }
   if (a.E_out != nullptr && tid == 0) a.E_out[mol] = Ed;
   const T E = static_cast<T>(Ed);

@@ -352,18 +352,21 @@ void mol_jmg_kernel(MolArgs a) {
   const double* mu = reinterpret_cast<const double*>(ws + a.lay.mu_d);
   const double* tg = reinterpret_cast<const double*>(ws + a.lay.total);
 
-  // field at the molecule (each component at its own edge of the cell)
-  double E3[3];
-  if (a.Ex != nullptr) {
-    const int c = a.cell_of_mol[mol];
-    const void* f3[3] = {a.Ex, a.Ey, a.Ez};
+  // field at the molecule (each component at its own edge of the cell);
+  // a readout-only launch (no step) reads no field
+  double E3[3] = {0.0, 0.0, 0.0};
+  if (a.n_steps > 0) {
+    if (a.Ex != nullptr) {
+      const int c = a.cell_of_mol[mol];
+      const void* f3[3] = {a.Ex, a.Ey, a.Ez};
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      E3[k] = (a.ex_is_float ? static_cast<double>(static_cast<const float*>(f3[k])[c])
-                             : static_cast<const double*>(f3[k])[c]) * a.inv_eau;
-  } else {
+      for (int k = 0; k < 3; ++k)
+        E3[k] = (a.ex_is_float ? static_cast<double>(static_cast<const float*>(f3[k])[c])
+                               : static_cast<const double*>(f3[k])[c]) * a.inv_eau;
+    } else {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) E3[k] = a.E_mol[3 * mol + k];
+      for (int k = 0; k < 3; ++k) E3[k] = a.E_mol[3 * mol + k];
+    }
   }
   if (a.E_out != nullptr && tid == 0) {
 #pragma unroll
