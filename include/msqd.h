@@ -180,6 +180,21 @@ int qd_step(const qd_desc* d, const void* ws, void* psi, const double* E_mol,
 int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
                    double* d_mol, double* norm_mol, double* yield_mol, double* sums, void* stream);
 
+/* dipole_readout for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, results and errors, but the stage-one partial sums of
+ * `sums` go to a static device array of the library (40 KB per GPU, held
+ * until the process ends) instead of the tail of ws, so ws only needs the
+ * tables (qd_workspace_bytes still covers it).  It calls no hipMalloc,
+ * hipFree or allocating routine.  Limit: with sums, n_mol <= 1,048,576
+ * (1024 blocks of 1024 molecules), else MSQD_EUNSUP and nothing is launched.
+ * Every call on one GPU shares that GPU's array, so calls whose sums overlap
+ * in time on one GPU (different streams, or threads) race; calls ordered on
+ * one stream do not.  The first call on a device looks up the array's
+ * device address (hipGetSymbolAddress) with that device current. */
+int dipole_readout_noalloc(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
+                           double* d_mol, double* norm_mol, double* yield_mol, double* sums, void* stream);
+
 /* Excited-state internuclear distance, Eq. (8): per molecule (float64,
  * device) r_num = <chi_e|R|chi_e> = sum_{J,k} r_k |psi_e,J(r_k)|^2 dr and
  * pop = <chi_e|chi_e>; the ratio is the molecule's <R>_e.  sums: device

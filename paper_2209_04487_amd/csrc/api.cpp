@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -574,6 +575,51 @@ int dipole_readout(const qd_desc* d, const void* ws, const void* psi, const doub
   double* partial = (sums && d->n_mol > 0)
                         ? reinterpret_cast<double*>(static_cast<char*>(const_cast<void*>(ws)) + qd_partials_offset(d))
                         : nullptr;
+  return readout_impl(d, ws, psi, absorbed, d_mol, norm_mol, yield_mol, sums, partial,
+                      static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------- no-allocation readout
+// Stage-one partial sums of dipole_readout_noalloc live in this file-scope
+// device array instead of the workspace tail: 1024 blocks of 1024 molecules
+// (n_mol <= 1,048,576) times five sums, 40 KB.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is passed to kernels.
+constexpr int kNoallocMaxBlocks = 1024;
+static __device__ __align__(256) double scratch[kNoallocMaxBlocks * kMaxSumVecs];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[64];   // device address of `scratch` per device ordinal
+
+static int noalloc_scratch(double** out) {
+  int dev = 0;
+  MSQD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MSQD_EUNSUP, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(MSQD_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_dev[dev]);
+  return MSQD_OK;
+}
+
+int dipole_readout_noalloc(const qd_desc* d, const void* ws, const void* psi, const double* absorbed,
+                           double* d_mol, double* norm_mol, double* yield_mol, double* sums, void* stream) {
+  int rc = check_qd(d);
+  if (rc) return rc;
+  double* partial = nullptr;
+  if (sums) {
+    if (sum_blocks(d->n_mol) > kNoallocMaxBlocks)
+      return fail(MSQD_EUNSUP, "dipole_readout_noalloc: n_mol above " + std::to_string(kNoallocMaxBlocks * kSumBlock) +
+                                   " (the size of its static scratch); use dipole_readout");
+    rc = noalloc_scratch(&partial);
+    if (rc) return rc;
+  }
   return readout_impl(d, ws, psi, absorbed, d_mol, norm_mol, yield_mol, sums, partial,
                       static_cast<hipStream_t>(stream));
 }

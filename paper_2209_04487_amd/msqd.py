@@ -39,7 +39,7 @@ EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "
            "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
            "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
-           "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end"]
+           "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end", "dipole_readout_noalloc"]
 
 
 class MsqdError(RuntimeError):
@@ -125,6 +125,7 @@ _sigs = {
     "qd_init": (C.c_int, [C.POINTER(qd_desc), _dp, _dp, _dp, _dp, _vp, C.c_size_t, _vp, _vp, _vp]),
     "qd_step": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]),
     "dipole_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "dipole_readout_noalloc": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "msqd_check_status": (C.c_int, [_vp, _vp]),
     "qd_jm_tables_size": (C.c_size_t, [C.c_int32]),
     "qd_jm_tables": (C.c_int, [C.c_int32, _dp, C.c_size_t]),
@@ -213,6 +214,13 @@ def dipole_readout(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=No
     return _check(lib.dipole_readout(C.byref(d), _ptr(ws), _ptr(psi), _ptr(absorbed), _ptr(d_mol),
                                      _ptr(norm_mol), _ptr(yield_mol), _ptr(sums),
                                      stream or current_stream()))
+
+
+def dipole_readout_noalloc(d, ws, psi, absorbed, d_mol=None, norm_mol=None, yield_mol=None, sums=None,
+                           stream=None):
+    return _check(lib.dipole_readout_noalloc(C.byref(d), _ptr(ws), _ptr(psi), _ptr(absorbed), _ptr(d_mol),
+                                             _ptr(norm_mol), _ptr(yield_mol), _ptr(sums),
+                                             stream or current_stream()))
 
 
 def jm_tables(j_max):
