@@ -245,12 +245,23 @@ typedef struct {
   uint8_t* mat;    /* [3][nz][ny][nx] material id per E-component location  */
   double* dft;     /* [planes][4][n_freq][ny][nx] complex128 (E_x, E_y, H_x,
                       H_y), planes = 2 with mon_k2, else 1; or NULL         */
+  void* spare;     /* NULL, or fdtd_spare_bytes() of device memory: a second
+                      set of E, H and H-CPML arrays.  With it, coupled_step
+                      runs each pair of field steps as two fused sweeps (H
+                      and E of a step in one pass over the grid, reading one
+                      set and writing the other), so every call still ends
+                      with the fields in the arrays above; an odd last step
+                      of a call uses the two-kernel update.  Its contents
+                      between calls are scratch.                           */
 } fdtd_fields;
 
 size_t fdtd_workspace_bytes(const fdtd_desc* d);
-/* Bytes of the CPML auxiliary buffer `psi` and of the monitor buffer `dft`. */
+/* Bytes of the CPML auxiliary buffer `psi`, of the monitor buffer `dft`, and
+ * of the optional second field set `spare`: (6 nx ny nz + 4 npml nx ny)
+ * elements of the field type. */
 size_t fdtd_psi_bytes(const fdtd_desc* d);
 size_t fdtd_dft_bytes(const fdtd_desc* d);
+size_t fdtd_spare_bytes(const fdtd_desc* d);
 
 /* Zero every field, copy the host material map mat_host [3][nz][ny][nx] to
  * f->mat, and build the CPML coefficient profiles and monitor frequencies
@@ -326,6 +337,15 @@ typedef struct {
   fdtd_fields f;
   const void* qd_ws;
   const void* fd_ws;
+  void* psi_next;            /* NULL: the molecular step updates psi in
+                                place.  Else (m = 0 basis, n_steps = 1) it
+                                reads psi and writes the stepped wavepackets
+                                to psi_next (same layout, caller-owned, 16-byte
+                                aligned, not overlapping psi), leaving psi as
+                                it was, so that a gradient's segment recompute
+                                keeps every step's state without copies.  With
+                                mol_every > 1 only the steps where the
+                                molecules step (n % mol_every == 0) write it. */
 } cpl_state;
 
 /* n_steps coupled steps from step n0 (section on molecular mapping, with
@@ -338,7 +358,9 @@ typedef struct {
  * molecule taking one step of M dt under E_x^n; J_mol = (P_new - P_old)/(M dt)
  * is then applied unchanged at every field step until the next update.
  * src_values: host [n_steps], E_inc(t_{n+1/2}) in V/m.
- * Errors: MSQD_EINVAL for a step/precision mismatch (qd.dt_au != M fd.dt). */
+ * Errors: MSQD_EINVAL for a step/precision mismatch (qd.dt_au != M fd.dt),
+ * and for s->psi_next set with n_steps != 1, misaligned or equal to s->psi;
+ * MSQD_EUNSUP for s->psi_next set in the (j, m) basis. */
 int coupled_step(const cpl_desc* d, const cpl_state* s, const double* src_values, int64_t n0,
                  int32_t n_steps, void* stream);
 
@@ -438,10 +460,15 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* s, cpl_adj* adj, void
  * (device float64).  psi_n and E_mol_n are the wavepackets before step n
  * and the field it gathered (recorded by a forward recompute; with
  * mol_every > 1 they are read only at the update steps n % mol_every == 0);
- * s supplies the maps, tables and material map of the forward system.
- * Errors: MSQD_EINVAL also for n < 0. */
-int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, const double* E_mol_n,
-                 cpl_adj* adj, int64_t n, double* g_src, void* stream);
+ * psi_np1 is the wavepackets after step n (the recompute's next state, e.g.
+ * written there by coupled_step's psi_next), or NULL: given, the molecular
+ * adjoint reads the absorber's input back from it instead of recomputing
+ * the second half of the forward step.  s supplies the maps, tables and
+ * material map of the forward system.
+ * Errors: MSQD_EINVAL also for n < 0 and for psi_np1 misaligned or equal
+ * to psi_n. */
+int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, const void* psi_np1,
+                 const double* E_mol_n, cpl_adj* adj, int64_t n, double* g_src, void* stream);
 
 #ifdef __cplusplus
 }

@@ -129,7 +129,10 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
   return grad;
 }
 
-template <typename T, int NR>
+// NEXT: the state after the step (psi^{n+1} = m psi_pre) is given, so the
+// recompute stops at chi = V K psi; otherwise the whole forward step is
+// recomputed to obtain psi_pre.
+template <typename T, int NR, bool NEXT>
 __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   constexpr int LS = line_stride<NR, T>();
@@ -167,7 +170,8 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   cx<T>* slot = B + line * LS;
   const int loff = line * NR + q;
 
-  // ---- forward recompute: chi = V K psi -> A; psi_pre = K V C(chi)
+  // ---- forward recompute: chi = V K psi -> A; psi_pre = K V C(chi), or
+  // psi^{n+1} = m psi_pre read back (v then holds psi^{n+1})
   cx<T> v[R1];
   if (active) {
 #pragma unroll
@@ -176,20 +180,32 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
 #pragma unroll
     for (int p = 0; p < R1; ++p) A[line * LS + q + R2 * p] = phase_mul(v[p], vph[loff + R2 * p]);
   }
-  __syncthreads();
-  coupling_adj_mfma<T, NR, false>(A, B, LS, nj, frag, xk, mudt, E);
-  __syncthreads();
-  if (active) {
+  if constexpr (NEXT) {
+    const cx<T>* nxt = reinterpret_cast<const cx<T>*>(a.psi_np1) + base;
+    if (active) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) v[p] = phase_mul(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
-    kinetic_half<T, NR>(v, slot, q, kin, tw);       // v = psi_pre (before the absorber)
-  }
-  __syncthreads();
-  if (active) {
+      for (int p = 0; p < R1; ++p) {
+        v[p] = nxt[loff + R2 * p];
+        B[line * LS + q + R2 * p] = v[p];
+      }
+    }
+    __syncthreads();
+  } else {
+    __syncthreads();
+    coupling_adj_mfma<T, NR, false>(A, B, LS, nj, frag, xk, mudt, E);
+    __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = cscale(v[p], mask[q + R2 * p]);
+      for (int p = 0; p < R1; ++p) v[p] = phase_mul(B[line * LS + q + R2 * p], vph[loff + R2 * p]);
+      kinetic_half<T, NR>(v, slot, q, kin, tw);       // v = psi_pre (before the absorber)
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int p = 0; p < R1; ++p) B[line * LS + q + R2 * p] = cscale(v[p], mask[q + R2 * p]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- reverse: dipole and absorber terms, then K^H V^H
   const double ld = a.ld ? a.ld[mol] : 0.0;
@@ -211,7 +227,10 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
       if (J_of_line + 1 < nj) dpsi = dpsi + cscale(B[(sb * nj + J_of_line + 1) * LS + r], cjp);
       l = l + cscale(dpsi, fd * static_cast<T>(mu[r]));
       const T m = mask[r];
-      l = cscale(l, m) + cscale(v[p], fa * (T(1) - m * m));
+      // absorber term 2 dr labs (1 - m^2) psi_pre, with psi_pre = psi^{n+1} / m
+      // when the state after the step was given (m > 0 on the periodic grid)
+      const T wa = NEXT ? (T(1) - m * m) / m : (T(1) - m * m);
+      l = cscale(l, m) + cscale(v[p], fa * wa);
       lam[p] = l;
     }
   }
@@ -245,8 +264,8 @@ size_t mol_adj_lds_bytes(int n_r, int nj, bool f32) {
   return 2 * el * static_cast<size_t>(2 * nj) * (n_r + r2) + 16 * 4 * sizeof(double);
 }
 
-template <typename T, int NR>
-static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
+template <typename T, int NR, bool NEXT>
+static int launch_mol_adj_n(const MolAdjArgs& a, hipStream_t s) {
   constexpr int R2 = FftShape<NR, T>::R2;
   const int L = 2 * a.nj;
   int threads = ((L * R2 + 63) / 64) * 64;
@@ -254,11 +273,16 @@ static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
   const size_t shm = mol_adj_lds_bytes(NR, a.nj, sizeof(T) == 4);
   static std::atomic<unsigned long long> lds_set{0};
   if (shm > 64 * 1024) {
-    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR>), lds_set);
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR, NEXT>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
   }
-  hipLaunchKernelGGL((mol_adj_kernel<T, NR>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  hipLaunchKernelGGL((mol_adj_kernel<T, NR, NEXT>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());
+}
+
+template <typename T, int NR>
+static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
+  return a.psi_np1 ? launch_mol_adj_n<T, NR, true>(a, s) : launch_mol_adj_n<T, NR, false>(a, s);
 }
 
 int launch_mol_adj(const MolAdjArgs& a, int n_r, bool f32, hipStream_t s) {

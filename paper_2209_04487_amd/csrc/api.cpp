@@ -224,7 +224,47 @@ static int check_fields(const fdtd_desc* d, const fdtd_fields* f) {
   if (!f->mat) return fail(MSQD_EINVAL, "material pointer is NULL");
   if (d->n_freq > 0 && (!f->dft || !aligned16(f->dft)))
     return fail(MSQD_EINVAL, "monitor buffer missing or misaligned");
+  if (f->spare && !aligned16(f->spare)) return fail(MSQD_EINVAL, "spare field buffer misaligned");
   return MSQD_OK;
+}
+
+// The arrays a field step reads and rewrites whole (E, H and the H CPML
+// auxiliaries): the caller's, or the second set in fdtd_fields.spare that the
+// fused sweep alternates with ([Ex][Ey][Ez][Hx][Hy][Hz] cells, then
+// [psi_Hx][psi_Hy] CPML planes).
+struct FieldSet {
+  void* a[8];   // Ex, Ey, Ez, Hx, Hy, Hz, psi_Hx, psi_Hy
+};
+
+static FieldSet caller_set(const fdtd_desc* d, const fdtd_fields* f) {
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
+  char* psi = static_cast<char*>(f->psi);
+  return {{f->Ex, f->Ey, f->Ez, f->Hx, f->Hy, f->Hz, psi + 2 * np * el, psi + 3 * np * el}};
+}
+
+static FieldSet spare_set(const fdtd_desc* d, const fdtd_fields* f) {
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  const size_t n = static_cast<size_t>(d->nx) * d->ny * d->nz;
+  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
+  char* b = static_cast<char*>(f->spare);
+  FieldSet s{};
+  for (int c = 0; c < 6; ++c) s.a[c] = b + c * n * el;
+  s.a[6] = b + 6 * n * el;
+  s.a[7] = b + (6 * n + np) * el;
+  return s;
+}
+
+// the monitor's view of a set: the caller's fields with E and H replaced
+static fdtd_fields with_set(const fdtd_fields* f, const FieldSet& fs) {
+  fdtd_fields g = *f;
+  g.Ex = fs.a[0];
+  g.Ey = fs.a[1];
+  g.Ez = fs.a[2];
+  g.Hx = fs.a[3];
+  g.Hy = fs.a[4];
+  g.Hz = fs.a[5];
+  return g;
 }
 
 static FdArgs make_fd_args(const fdtd_desc* d, const fdtd_fields* f, const void* ws) {
@@ -671,6 +711,14 @@ size_t fdtd_psi_bytes(const fdtd_desc* d) {
   return 4 * 2 * static_cast<size_t>(d->npml) * d->ny * d->nx * el;
 }
 
+size_t fdtd_spare_bytes(const fdtd_desc* d) {
+  if (check_fd(d) != MSQD_OK) return 0;
+  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
+  const size_t n = static_cast<size_t>(d->nx) * d->ny * d->nz;
+  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
+  return (6 * n + 2 * np) * el;
+}
+
 size_t fdtd_dft_bytes(const fdtd_desc* d) {
   if (check_fd(d) != MSQD_OK) return 0;
   return fd_planes(d) * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
@@ -868,6 +916,11 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     return fail(MSQD_EINVAL, "NULL coupling pointer");
   if (!st->fd_ws) return fail(MSQD_EINVAL, "NULL field workspace");
   if (d->mol_every < 0) return fail(MSQD_EINVAL, "mol_every < 0");
+  if (st->psi_next) {
+    if (d->qd.basis != MSQD_BASIS_M0) return fail(MSQD_EUNSUP, "psi_next (out-of-place step) needs the m = 0 basis");
+    if (n_steps != 1) return fail(MSQD_EINVAL, "psi_next (out-of-place step) needs n_steps = 1");
+    if (!aligned16(st->psi_next) || st->psi_next == st->psi) return fail(MSQD_EINVAL, "psi_next misaligned or equal to psi");
+  }
   const int M = d->mol_every > 1 ? d->mol_every : 1;
   {
     // the molecular step must be M field steps (atomic unit of time, CODATA 2018)
@@ -880,6 +933,7 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
   MolArgs ma = make_mol_args(&d->qd, st->qd_ws);
   ma.n_steps = 1;
   ma.psi = st->psi;
+  ma.psi_out = st->psi_next;
   ma.E_mol = nullptr;
   ma.Ex = st->f.Ex;
   ma.ex_is_float = f32 ? 1 : 0;
@@ -912,13 +966,67 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     da.Ez = st->f.Ez;
   }
   da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
+  for (int32_t t = 0; t < n_steps; ++t)
+    if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
+  // With a spare field set the steps run as fused sweeps that alternate
+  // between the caller's arrays (A) and the spare ones (B); an even number of
+  // them leaves the fields in A, and an odd last step takes the two-kernel
+  // update in place.  The molecules gather E^n from the set holding step n;
+  // the deposit and the monitor act on the set the sweep wrote.
+  const FieldSet setA = caller_set(&d->fd, &st->f);
+  const FieldSet setB = st->f.spare ? spare_set(&d->fd, &st->f) : setA;
+  const int32_t n_fused = (st->f.spare && n_steps >= 2) ? (n_steps & ~1) : 0;
+  SweepArgs sw{};
+  sw.f = fa;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
-    if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
-    fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
-    int e = launch_yee_h(fa, f32, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
     const bool mol_now = (n % M) == 0;
+    fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
+    int e = 0;
+    if (t < n_fused) {
+      const FieldSet& cur = (t & 1) ? setB : setA;
+      const FieldSet& nxt = (t & 1) ? setA : setB;
+      if (mol_now) {
+        ma.Ex = cur.a[0];
+        ma.Ey = cur.a[1];
+        ma.Ez = cur.a[2];
+        if (d->qd.basis != MSQD_BASIS_JM) ma.Ey = ma.Ez = nullptr;
+        timing_mark(true, s);
+        rc = launch_mol(&d->qd, ma, s);
+        if (rc) return rc;
+        timing_mark(false, s);
+      }
+      sw.f.src_term = fa.src_term;
+      for (int c = 0; c < 8; ++c) {
+        sw.src[c] = cur.a[c];
+        sw.dst[c] = nxt.a[c];
+      }
+      e = launch_yee_sweep(sw, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "field sweep launch");
+      da.Ex = nxt.a[0];
+      if (da.ncomp == 3) {
+        da.Ey = nxt.a[1];
+        da.Ez = nxt.a[2];
+      }
+      da.update = mol_now ? 1 : 0;
+      e = launch_deposit(da, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+      const fdtd_fields g = with_set(&st->f, nxt);
+      rc = fd_monitor(&d->fd, &g, st->fd_ws, n, s);
+      if (rc) return rc;
+      continue;
+    }
+    // two-kernel update in place on the caller's arrays
+    ma.Ex = st->f.Ex;
+    ma.Ey = d->qd.basis == MSQD_BASIS_JM ? st->f.Ey : nullptr;
+    ma.Ez = d->qd.basis == MSQD_BASIS_JM ? st->f.Ez : nullptr;
+    da.Ex = st->f.Ex;
+    if (da.ncomp == 3) {
+      da.Ey = st->f.Ey;
+      da.Ez = st->f.Ez;
+    }
+    e = launch_yee_h(fa, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
     if (mol_now) {
       timing_mark(true, s);
       rc = launch_mol(&d->qd, ma, s);
@@ -1116,12 +1224,13 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* st, cpl_adj* adj, voi
   return MSQD_OK;
 }
 
-int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, const double* E_mol_n,
-                 cpl_adj* adj, int64_t n, double* g_src, void* stream) {
+int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, const void* psi_np1,
+                 const double* E_mol_n, cpl_adj* adj, int64_t n, double* g_src, void* stream) {
   int rc = check_adj(d, st, adj);
   if (rc) return rc;
   if (!g_src) return fail(MSQD_EINVAL, "g_src NULL");
   if (d->qd.n_mol > 0 && (!psi_n || !E_mol_n)) return fail(MSQD_EINVAL, "recorded state NULL");
+  if (psi_np1 && (!aligned16(psi_np1) || psi_np1 == psi_n)) return fail(MSQD_EINVAL, "psi_np1 misaligned or equal to psi_n");
   if (n < 0) return fail(MSQD_EINVAL, "step index < 0");
   // multi-rate coupling: the molecules stepped (by M dt) only at n % M == 0
   const int M = d->mol_every > 1 ? d->mol_every : 1;
@@ -1169,6 +1278,7 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, cons
     ma.kdiss = m.kdiss;
     ma.dr = m.dr;
     ma.psi_n = psi_n;
+    ma.psi_np1 = psi_np1;
     ma.E_mol = E_mol_n;
     ma.lpsi = adj->lpsi;
     ma.labs = adj->labs;

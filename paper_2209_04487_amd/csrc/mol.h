@@ -42,6 +42,7 @@ struct MolArgs {
   int want_d, want_norm, want_yield;
   double dr;
   void* psi;            // cx<T> [n_mol][2][nj][n_r]
+  void* psi_out;        // where the stepped state goes (m = 0 kernels), or nullptr: back to psi
   const double* E_mol;  // [n_mol] field (au), used when Ex == nullptr
   const void* Ex;       // field array (double or float) or nullptr
   const void* Ey;       // (j, m) basis: the other two components, same cells

@@ -806,8 +806,9 @@ void mol_step_kernel(MolArgs a) {
     if (!isfinite(d) || !isfinite(sums[1]) || !isfinite(absorbed)) atomicOr(a.status, 1);
   }
   if (active && n_steps > 0) {
+    cx<T>* out = a.psi_out ? reinterpret_cast<cx<T>*>(a.psi_out) + static_cast<size_t>(mol) * L * NR : psi;
 #pragma unroll
-    for (int p = 0; p < R1; ++p) psi[loff + R2 * p] = v[p];
+    for (int p = 0; p < R1; ++p) out[loff + R2 * p] = v[p];
   }
 }
 

@@ -62,20 +62,34 @@ def source_gradient(sysm, ckpts, src, K):
     msqd.adjoint_init_yield(sysm.desc, sysm.state, adj)
     g = torch.zeros(n_steps, dtype=torch.float64, device=dev)
     n_mol = sysm.mol.desc.n_mol
+    M = sysm.mol_every
     for seg in reversed(range(len(ckpts))):
         s0 = seg * K
         s1 = min(s0 + K, n_steps)
         sysm.restore(ckpts[seg])
-        psi_hist = torch.empty((s1 - s0,) + tuple(sysm.mol.psi.shape), dtype=sysm.mol.psi.dtype,
+        # the segment's wavepackets: slot 0 is the checkpoint, and each step
+        # that moves the molecules reads its slot and writes the next one
+        # (coupled_step's out-of-place form), so no step copies a state
+        psi_hist = torch.empty((s1 - s0 + 1,) + tuple(sysm.mol.psi.shape), dtype=sysm.mol.psi.dtype,
                                device=dev)
         e_hist = torch.empty((s1 - s0, max(n_mol, 1)), dtype=torch.float64, device=dev)
+        psi_hist[0].copy_(sysm.mol.psi)
+        cur = 0
+        slot_of = []                      # slot holding the state before step t
         for t in range(s0, s1):
-            psi_hist[t - s0].copy_(sysm.mol.psi)
-            sysm.step(src[t:t + 1])
+            slot_of.append(cur)
+            if t % M == 0 and n_mol > 0:
+                sysm.step_out_of_place(src[t], psi_hist[cur], psi_hist[t - s0 + 1])
+                cur = t - s0 + 1
+            else:
+                sysm.step(src[t:t + 1])
             e_hist[t - s0].copy_(sysm.E_mol)
         for t in reversed(range(s0, s1)):
-            msqd.adjoint_step(sysm.desc, sysm.state, psi_hist[t - s0], e_hist[t - s0], adj, t,
-                              g[t:t + 1])
+            i = slot_of[t - s0]
+            # at a molecular step the state after it sits in slot t - s0 + 1
+            nxt = psi_hist[t - s0 + 1] if (t % M == 0 and n_mol > 0) else None
+            msqd.adjoint_step(sysm.desc, sysm.state, psi_hist[i], e_hist[t - s0], adj, t, g[t:t + 1],
+                              psi_np1=nxt)
         del psi_hist, e_hist
     buffers.clear()
     return g

@@ -36,7 +36,7 @@ EA0 = 8.4783536255e-30
 
 EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
-           "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
+           "fdtd_dft_bytes", "fdtd_spare_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
            "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
            "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end", "dipole_readout_noalloc"]
@@ -77,7 +77,8 @@ class fdtd_fields(C.Structure):
     _fields_ = [("Ex", C.c_void_p), ("Ey", C.c_void_p), ("Ez", C.c_void_p),
                 ("Hx", C.c_void_p), ("Hy", C.c_void_p), ("Hz", C.c_void_p),
                 ("JDx", C.c_void_p), ("JDy", C.c_void_p), ("JDz", C.c_void_p),
-                ("psi", C.c_void_p), ("mat", C.c_void_p), ("dft", C.c_void_p)]
+                ("psi", C.c_void_p), ("mat", C.c_void_p), ("dft", C.c_void_p),
+                ("spare", C.c_void_p)]
 
 
 class cpl_desc(C.Structure):
@@ -90,7 +91,7 @@ class cpl_state(C.Structure):
                 ("E_mol", C.c_void_p), ("P_c", C.c_void_p), ("J_mol", C.c_void_p),
                 ("cell_of_mol", C.c_void_p), ("occ_cell", C.c_void_p), ("occ_ptr", C.c_void_p),
                 ("mol_perm", C.c_void_p), ("f", fdtd_fields), ("qd_ws", C.c_void_p),
-                ("fd_ws", C.c_void_p)]
+                ("fd_ws", C.c_void_p), ("psi_next", C.c_void_p)]
 
 
 class bloch_desc(C.Structure):
@@ -132,6 +133,7 @@ _sigs = {
     "fdtd_workspace_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_psi_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_dft_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
+    "fdtd_spare_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_init": (C.c_int, [C.POINTER(fdtd_desc), _vp, _dp, C.POINTER(fdtd_fields), _vp,
                             C.c_size_t, _vp]),
     "fdtd_step": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, C.c_int64,
@@ -146,7 +148,7 @@ _sigs = {
     "adjoint_scratch_bytes": (C.c_size_t, [C.POINTER(cpl_desc)]),
     "adjoint_init_yield": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), C.POINTER(cpl_adj),
                                      _vp]),
-    "adjoint_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _vp, _vp,
+    "adjoint_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _vp, _vp, _vp,
                                C.POINTER(cpl_adj), C.c_int64, _vp, _vp]),
     "excited_r_readout": (C.c_int, [C.POINTER(qd_desc), _vp, _vp, _vp, _vp, _vp, _vp]),
     "bloch_init": (C.c_int, [C.POINTER(bloch_desc), _vp, _vp]),
@@ -312,8 +314,8 @@ def adjoint_init_yield(d, st, adj, stream=None):
                                          stream or current_stream()))
 
 
-def adjoint_step(d, st, psi_n, E_mol_n, adj, n, g_src, stream=None):
-    return _check(lib.adjoint_step(C.byref(d), C.byref(st), _ptr(psi_n), _ptr(E_mol_n),
+def adjoint_step(d, st, psi_n, E_mol_n, adj, n, g_src, psi_np1=None, stream=None):
+    return _check(lib.adjoint_step(C.byref(d), C.byref(st), _ptr(psi_n), _ptr(psi_np1), _ptr(E_mol_n),
                                    C.byref(adj), int(n), _ptr(g_src), stream or current_stream()))
 
 
@@ -427,9 +429,11 @@ def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
 
 
 class Fields:
-    """Yee field buffers (torch) plus the descriptor and workspace."""
+    """Yee field buffers (torch) plus the descriptor and workspace.  With
+    spare (the default) a second set of E, H and H-CPML arrays is allocated,
+    which lets coupled_step run its field steps as fused sweeps."""
 
-    def __init__(self, desc: fdtd_desc, mat_host, freqs):
+    def __init__(self, desc: fdtd_desc, mat_host, freqs, spare=True):
         self.desc = desc
         dev = _dev()
         dt = torch.float64 if desc.prec == FP64 else torch.float32
@@ -446,8 +450,13 @@ class Fields:
         if nbytes == 0:
             raise MsqdError(MSQD_EINVAL, last_error())
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        if spare:
+            sp_bytes = lib.fdtd_spare_bytes(C.byref(desc))
+            self.t["spare"] = torch.empty(max(sp_bytes // (8 if desc.prec == FP64 else 4), 1), dtype=dt,
+                                          device=dev)
         self.f = fdtd_fields(*[C.c_void_p(self.t[n].data_ptr()) for n in names + ["psi", "mat"]],
-                             C.c_void_p(self.t["dft"].data_ptr()) if desc.n_freq > 0 else None)
+                             C.c_void_p(self.t["dft"].data_ptr()) if desc.n_freq > 0 else None,
+                             C.c_void_p(self.t["spare"].data_ptr()) if spare else None)
         fdtd_init(desc, mat_host, freqs, self.f, self.ws)
 
     def __getattr__(self, name):
@@ -535,6 +544,20 @@ class Coupled:
         src_values = np.atleast_1d(np.asarray(src_values, np.float64))
         coupled_step(self.desc, self.state, src_values, self.n)
         self.n += len(src_values)
+
+    def step_out_of_place(self, src_value, psi_in, psi_out):
+        """One coupled step whose molecules read psi_in and write the stepped
+        wavepackets to psi_out (coupled_step's psi_next); the fields, the
+        absorbed norms and the polarisation advance as in step()."""
+        src_values = np.atleast_1d(np.asarray(src_value, np.float64))
+        self.state.psi = C.c_void_p(psi_in.data_ptr())
+        self.state.psi_next = C.c_void_p(psi_out.data_ptr())
+        try:
+            coupled_step(self.desc, self.state, src_values, self.n)
+        finally:
+            self.state.psi = C.c_void_p(self.mol.psi.data_ptr())
+            self.state.psi_next = None
+        self.n += 1
 
     # -------------------------------------------------- checkpoint / restore
     _STATE = ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "JDx", "JDy", "JDz", "psi", "dft"]

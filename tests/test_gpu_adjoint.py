@@ -62,10 +62,15 @@ def _dot_state(sysm, vec):
     return s
 
 
-def test_adjoint_step_dot_product_fp64():
+@pytest.mark.parametrize("next_state", [False, True])
+def test_adjoint_step_dot_product_fp64(next_state):
+    """With next_state the forward step is taken out of place (coupled_step's
+    psi_next), which must equal the in-place step bit for bit and leave its
+    input untouched, and the reverse step reads the state after the step
+    (adjoint_step's psi_np1) instead of recomputing it."""
     from paper_2209_04487_amd import msqd
     cfg = _cfg()
-    banner("adjoint step dot product fp64")
+    banner(f"adjoint step dot product fp64, state after the step {'given' if next_state else 'recomputed'}")
     mat = _mat_with_metal(cfg)
     kn = knot_values(cfg) * 30.0
     src = source_values(cfg, 0, 60, knots=kn)
@@ -112,7 +117,17 @@ def test_adjoint_step_dot_product_fp64():
     # adjoint: restore x, recompute the step's gathered field, then reverse
     sysm.restore(x)
     psi_n = sysm.mol.psi.clone()
-    sysm.step(src[40:41])
+    psi_np1 = None
+    if next_state:
+        sysm.step(src[40:41])
+        in_place = sysm.mol.psi.clone()
+        sysm.restore(x)
+        psi_np1 = torch.empty_like(psi_n)
+        sysm.step_out_of_place(src[40], psi_n, psi_np1)
+        assert torch.equal(psi_np1, in_place)
+        assert torch.equal(sysm.mol.psi, psi_n)
+    else:
+        sysm.step(src[40:41])
     e_n = sysm.E_mol.clone()
     adj, buf = sysm.adjoint_buffers()
     for k in STATE:
@@ -121,7 +136,7 @@ def test_adjoint_step_dot_product_fp64():
     buf["labs"].copy_(lam["absorbed"])
     buf["lP"][: lam["P_c"].numel()].copy_(lam["P_c"])
     g = torch.zeros(1, dtype=torch.float64, device="cuda")
-    msqd.adjoint_step(sysm.desc, sysm.state, psi_n, e_n, adj, 40, g)
+    msqd.adjoint_step(sysm.desc, sysm.state, psi_n, e_n, adj, 40, g, psi_np1=psi_np1)
     torch.cuda.synchronize()
     jtl = 0.0
     for k in STATE:
