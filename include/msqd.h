@@ -245,23 +245,12 @@ typedef struct {
   uint8_t* mat;    /* [3][nz][ny][nx] material id per E-component location  */
   double* dft;     /* [planes][4][n_freq][ny][nx] complex128 (E_x, E_y, H_x,
                       H_y), planes = 2 with mon_k2, else 1; or NULL         */
-  void* spare;     /* NULL, or fdtd_spare_bytes() of device memory: a second
-                      set of E, H and H-CPML arrays.  With it, coupled_step
-                      runs each pair of field steps as two fused sweeps (H
-                      and E of a step in one pass over the grid, reading one
-                      set and writing the other), so every call still ends
-                      with the fields in the arrays above; an odd last step
-                      of a call uses the two-kernel update.  Its contents
-                      between calls are scratch.                           */
 } fdtd_fields;
 
 size_t fdtd_workspace_bytes(const fdtd_desc* d);
-/* Bytes of the CPML auxiliary buffer `psi`, of the monitor buffer `dft`, and
- * of the optional second field set `spare`: (6 nx ny nz + 4 npml nx ny)
- * elements of the field type. */
+/* Bytes of the CPML auxiliary buffer `psi` and of the monitor buffer `dft`. */
 size_t fdtd_psi_bytes(const fdtd_desc* d);
 size_t fdtd_dft_bytes(const fdtd_desc* d);
-size_t fdtd_spare_bytes(const fdtd_desc* d);
 
 /* Zero every field, copy the host material map mat_host [3][nz][ny][nx] to
  * f->mat, and build the CPML coefficient profiles and monitor frequencies

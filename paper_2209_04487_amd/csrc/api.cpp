@@ -224,47 +224,7 @@ static int check_fields(const fdtd_desc* d, const fdtd_fields* f) {
   if (!f->mat) return fail(MSQD_EINVAL, "material pointer is NULL");
   if (d->n_freq > 0 && (!f->dft || !aligned16(f->dft)))
     return fail(MSQD_EINVAL, "monitor buffer missing or misaligned");
-  if (f->spare && !aligned16(f->spare)) return fail(MSQD_EINVAL, "spare field buffer misaligned");
   return MSQD_OK;
-}
-
-// The arrays a field step reads and rewrites whole (E, H and the H CPML
-// auxiliaries): the caller's, or the second set in fdtd_fields.spare that the
-// fused sweep alternates with ([Ex][Ey][Ez][Hx][Hy][Hz] cells, then
-// [psi_Hx][psi_Hy] CPML planes).
-struct FieldSet {
-  void* a[8];   // Ex, Ey, Ez, Hx, Hy, Hz, psi_Hx, psi_Hy
-};
-
-static FieldSet caller_set(const fdtd_desc* d, const fdtd_fields* f) {
-  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
-  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
-  char* psi = static_cast<char*>(f->psi);
-  return {{f->Ex, f->Ey, f->Ez, f->Hx, f->Hy, f->Hz, psi + 2 * np * el, psi + 3 * np * el}};
-}
-
-static FieldSet spare_set(const fdtd_desc* d, const fdtd_fields* f) {
-  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
-  const size_t n = static_cast<size_t>(d->nx) * d->ny * d->nz;
-  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
-  char* b = static_cast<char*>(f->spare);
-  FieldSet s{};
-  for (int c = 0; c < 6; ++c) s.a[c] = b + c * n * el;
-  s.a[6] = b + 6 * n * el;
-  s.a[7] = b + (6 * n + np) * el;
-  return s;
-}
-
-// the monitor's view of a set: the caller's fields with E and H replaced
-static fdtd_fields with_set(const fdtd_fields* f, const FieldSet& fs) {
-  fdtd_fields g = *f;
-  g.Ex = fs.a[0];
-  g.Ey = fs.a[1];
-  g.Ez = fs.a[2];
-  g.Hx = fs.a[3];
-  g.Hy = fs.a[4];
-  g.Hz = fs.a[5];
-  return g;
 }
 
 static FdArgs make_fd_args(const fdtd_desc* d, const fdtd_fields* f, const void* ws) {
@@ -711,14 +671,6 @@ size_t fdtd_psi_bytes(const fdtd_desc* d) {
   return 4 * 2 * static_cast<size_t>(d->npml) * d->ny * d->nx * el;
 }
 
-size_t fdtd_spare_bytes(const fdtd_desc* d) {
-  if (check_fd(d) != MSQD_OK) return 0;
-  const size_t el = d->prec == MSQD_FP64 ? 8 : 4;
-  const size_t n = static_cast<size_t>(d->nx) * d->ny * d->nz;
-  const size_t np = 2 * static_cast<size_t>(d->npml) * d->ny * d->nx;
-  return (6 * n + 2 * np) * el;
-}
-
 size_t fdtd_dft_bytes(const fdtd_desc* d) {
   if (check_fd(d) != MSQD_OK) return 0;
   return fd_planes(d) * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
@@ -968,64 +920,11 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
   da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
   for (int32_t t = 0; t < n_steps; ++t)
     if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
-  // With a spare field set the steps run as fused sweeps that alternate
-  // between the caller's arrays (A) and the spare ones (B); an even number of
-  // them leaves the fields in A, and an odd last step takes the two-kernel
-  // update in place.  The molecules gather E^n from the set holding step n;
-  // the deposit and the monitor act on the set the sweep wrote.
-  const FieldSet setA = caller_set(&d->fd, &st->f);
-  const FieldSet setB = st->f.spare ? spare_set(&d->fd, &st->f) : setA;
-  const int32_t n_fused = (st->f.spare && n_steps >= 2) ? (n_steps & ~1) : 0;
-  SweepArgs sw{};
-  sw.f = fa;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     const bool mol_now = (n % M) == 0;
     fa.src_term = -2.0 * src_values[t] / (kEta0 * d->fd.dx);
-    int e = 0;
-    if (t < n_fused) {
-      const FieldSet& cur = (t & 1) ? setB : setA;
-      const FieldSet& nxt = (t & 1) ? setA : setB;
-      if (mol_now) {
-        ma.Ex = cur.a[0];
-        ma.Ey = cur.a[1];
-        ma.Ez = cur.a[2];
-        if (d->qd.basis != MSQD_BASIS_JM) ma.Ey = ma.Ez = nullptr;
-        timing_mark(true, s);
-        rc = launch_mol(&d->qd, ma, s);
-        if (rc) return rc;
-        timing_mark(false, s);
-      }
-      sw.f.src_term = fa.src_term;
-      for (int c = 0; c < 8; ++c) {
-        sw.src[c] = cur.a[c];
-        sw.dst[c] = nxt.a[c];
-      }
-      e = launch_yee_sweep(sw, f32, s);
-      if (e) return check_hip(static_cast<hipError_t>(e), "field sweep launch");
-      da.Ex = nxt.a[0];
-      if (da.ncomp == 3) {
-        da.Ey = nxt.a[1];
-        da.Ez = nxt.a[2];
-      }
-      da.update = mol_now ? 1 : 0;
-      e = launch_deposit(da, f32, s);
-      if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
-      const fdtd_fields g = with_set(&st->f, nxt);
-      rc = fd_monitor(&d->fd, &g, st->fd_ws, n, s);
-      if (rc) return rc;
-      continue;
-    }
-    // two-kernel update in place on the caller's arrays
-    ma.Ex = st->f.Ex;
-    ma.Ey = d->qd.basis == MSQD_BASIS_JM ? st->f.Ey : nullptr;
-    ma.Ez = d->qd.basis == MSQD_BASIS_JM ? st->f.Ez : nullptr;
-    da.Ex = st->f.Ex;
-    if (da.ncomp == 3) {
-      da.Ey = st->f.Ey;
-      da.Ez = st->f.Ez;
-    }
-    e = launch_yee_h(fa, f32, s);
+    int e = launch_yee_h(fa, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
     if (mol_now) {
       timing_mark(true, s);

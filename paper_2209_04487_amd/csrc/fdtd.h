@@ -28,18 +28,6 @@ struct FdArgs {
 int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s);
 int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s);
 
-// One field step as a single sweep from one set of E, H and H-CPML arrays to
-// another (the Drude currents and E-CPML auxiliaries in f, updated in place).
-// src/dst: Ex, Ey, Ez, Hx, Hy, Hz, psi_Hx, psi_Hy.  kc and tiles_x are set by
-// the launcher.
-struct SweepArgs {
-  FdArgs f;
-  const void* src[8];
-  void* dst[8];
-  int kc, tiles_x;
-};
-int launch_yee_sweep(const SweepArgs& a, bool f32, hipStream_t s);
-
 struct MonArgs {
   int nx, ny, mon_k, n_freq;
   double tE, tH, wdt;                  // sample times, weight (every * dt)

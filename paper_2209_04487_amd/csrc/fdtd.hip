@@ -197,212 +197,6 @@ __global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
   }
 }
 
-// ------------------------------------------------------- fused H + E sweep
-// One kernel for a whole field step: H^{n+1/2} and then E^{n+1}, plane by
-// plane, reading E^n, H^{n-1/2} and the H CPML auxiliaries from one set of
-// arrays (src) and writing the new values to a second set (dst).  The E
-// update of a cell needs H^{n+1/2} at its -x and -y neighbours; a workgroup
-// recomputes those for the cells just outside its tile from the old arrays,
-// which no workgroup writes during the sweep, so tiles never wait for each
-// other.  The Drude currents and the E CPML auxiliaries belong to one cell
-// each and are updated in place.  Traffic per cell: E and H read and
-// written once (12 words), the material ids, and the Drude / CPML words
-// where they exist.
-//
-// Workgroup: a kSwTX x kSwTY tile of the xy plane (x fastest), marching up a
-// chunk of planes [k0, k1).  The H of the plane below the chunk is
-// recomputed (own cells only) for the z derivative of the first E plane.
-constexpr int kSwTX = 32, kSwTY = 8;
-
-template <typename P>
-struct SwSet {
-  P *Ex, *Ey, *Ez, *Hx, *Hy, *Hz, *psiHx, *psiHy;
-};
-
-// H^{n+1/2} at cell (i, j, k) from the src arrays: the expressions of
-// yee_h_kernel.  With own = true the new CPML auxiliaries are written to dst.
-template <typename T>
-__device__ __forceinline__ void sw_h(const SweepArgs& a, const SwSet<const T>& src, const SwSet<T>& dst, int i, int j,
-                                     int k, bool own, T& hx1, T& hy1, T& hz1) {
-  const int nx = a.f.nx, ny = a.f.ny, nz = a.f.nz;
-  const long sy = nx, sz = static_cast<long>(nx) * ny;
-  const long idx = static_cast<long>(k) * sz + static_cast<long>(j) * sy + i;
-  const long ip = (i + 1 == nx) ? idx - (nx - 1) : idx + 1;
-  const long jp = (j + 1 == ny) ? idx - (ny - 1) * sy : idx + sy;
-  const bool below_top = k + 1 < nz;
-  const T ex = src.Ex[idx], ey = src.Ey[idx], ez = src.Ez[idx];
-  const T ex_kp = below_top ? src.Ex[idx + sz] : T(0);
-  const T ey_kp = below_top ? src.Ey[idx + sz] : T(0);
-  const T ez_jp = src.Ez[jp], ez_ip = src.Ez[ip], ey_ip = src.Ey[ip], ex_jp = src.Ex[jp];
-  const T hx = src.Hx[idx], hy = src.Hy[idx], hz = src.Hz[idx];
-  const T inv_dx = static_cast<T>(a.f.inv_dx);
-  const T cH = static_cast<T>(a.f.cH);
-  const T dEz_dy = (ez_jp - ez) * inv_dx;
-  const T dEz_dx = (ez_ip - ez) * inv_dx;
-  T dEy_dz = (ey_kp - ey) * inv_dx;
-  T dEx_dz = (ex_kp - ex) * inv_dx;
-  const T dEy_dx = (ey_ip - ey) * inv_dx;
-  const T dEx_dy = (ex_jp - ex) * inv_dx;
-  const int kk = pml_plane(k, nz, a.f.npml);
-  if (kk >= 0) {
-    const T b = prof<T>(a.f, a.f.lay.bH, a.f.lay.bHf)[k];
-    const T c = prof<T>(a.f, a.f.lay.aH, a.f.lay.aHf)[k];
-    const T ki = prof<T>(a.f, a.f.lay.kH, a.f.lay.kHf)[k];
-    const long o = kk * sz + (idx - static_cast<long>(k) * sz);
-    const T phx = b * src.psiHx[o] + c * dEy_dz;
-    const T phy = b * src.psiHy[o] + c * dEx_dz;
-    if (own) {
-      dst.psiHx[o] = phx;
-      dst.psiHy[o] = phy;
-    }
-    dEy_dz = dEy_dz * ki + phx;
-    dEx_dz = dEx_dz * ki + phy;
-  }
-  hx1 = hx - cH * (dEz_dy - dEy_dz);
-  hy1 = hy - cH * (dEx_dz - dEz_dx);
-  hz1 = hz - cH * (dEy_dx - dEx_dy);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kSwTX* kSwTY) void yee_sweep_kernel(SweepArgs a) {
-  __shared__ T sHx[kSwTY + 1][kSwTX + 1];
-  __shared__ T sHy[kSwTY + 1][kSwTX + 1];
-  __shared__ T sHz[kSwTY + 1][kSwTX + 1];
-  const FdArgs& f = a.f;
-  const int nx = f.nx, ny = f.ny, nz = f.nz;
-  const long sy = nx, sz = static_cast<long>(nx) * ny;
-  const long n = sz * nz;
-  const SwSet<const T> src = {static_cast<const T*>(a.src[0]), static_cast<const T*>(a.src[1]),
-                              static_cast<const T*>(a.src[2]), static_cast<const T*>(a.src[3]),
-                              static_cast<const T*>(a.src[4]), static_cast<const T*>(a.src[5]),
-                              static_cast<const T*>(a.src[6]), static_cast<const T*>(a.src[7])};
-  const SwSet<T> dst = {static_cast<T*>(a.dst[0]), static_cast<T*>(a.dst[1]), static_cast<T*>(a.dst[2]),
-                        static_cast<T*>(a.dst[3]), static_cast<T*>(a.dst[4]), static_cast<T*>(a.dst[5]),
-                        static_cast<T*>(a.dst[6]), static_cast<T*>(a.dst[7])};
-  const int tx = threadIdx.x % kSwTX, ty = threadIdx.x / kSwTX;
-  const int tile = blockIdx.x;
-  const int i0 = (tile % a.tiles_x) * kSwTX, j0 = (tile / a.tiles_x) * kSwTY;
-  const int k0 = blockIdx.y * a.kc;
-  const int k1 = min(k0 + a.kc, nz);
-  const int i = i0 + tx, j = j0 + ty;
-  const bool valid = i < nx && j < ny;
-  // halo cells: thread t < kSwTX takes (i0 + t, j0 - 1), the next kSwTY
-  // threads (i0 - 1, j0 + t - kSwTX), both wrapped periodically
-  const int t = threadIdx.x;
-  int hi = -1, hj = -1;
-  if (t < kSwTX) {
-    hi = i0 + t;
-    hj = j0 == 0 ? ny - 1 : j0 - 1;
-    if (hi >= nx) hi = -1;
-  } else if (t < kSwTX + kSwTY) {
-    hi = i0 == 0 ? nx - 1 : i0 - 1;
-    hj = j0 + (t - kSwTX);
-    if (hj >= ny) hi = -1;
-  }
-  T* psiEx = static_cast<T*>(f.psi);
-  T* psiEy = psiEx + 2L * f.npml * sz;
-  T* JD[3] = {static_cast<T*>(f.JDx), static_cast<T*>(f.JDy), static_cast<T*>(f.JDz)};
-  // H^{n+1/2} of the plane below (own cell), for the first E plane's z derivative
-  T hx_km = T(0), hy_km = T(0);
-  if (k0 > 0 && valid) {
-    T hz_unused;
-    sw_h<T>(a, src, dst, i, j, k0 - 1, false, hx_km, hy_km, hz_unused);
-  }
-  const T inv_dx = static_cast<T>(f.inv_dx);
-  for (int k = k0; k < k1; ++k) {
-    T hx = T(0), hy = T(0), hz = T(0);
-    if (valid) {
-      sw_h<T>(a, src, dst, i, j, k, true, hx, hy, hz);
-      sHx[ty + 1][tx + 1] = hx;
-      sHy[ty + 1][tx + 1] = hy;
-      sHz[ty + 1][tx + 1] = hz;
-    }
-    if (hi >= 0) {
-      T ax, ay, az;
-      sw_h<T>(a, src, dst, hi, hj, k, false, ax, ay, az);
-      if (t < kSwTX) {
-        sHx[0][t + 1] = ax;
-        sHz[0][t + 1] = az;
-      } else {
-        sHy[t - kSwTX + 1][0] = ay;
-        sHz[t - kSwTX + 1][0] = az;
-      }
-    }
-    __syncthreads();
-    if (valid) {
-      const long idx = static_cast<long>(k) * sz + static_cast<long>(j) * sy + i;
-      const T hz_jm = sHz[ty][tx + 1], hz_im = sHz[ty + 1][tx], hy_im = sHy[ty + 1][tx], hx_jm = sHx[ty][tx + 1];
-      const uint8_t* mat = f.mat;
-      const int mc[3] = {mat[idx], mat[n + idx], mat[2 * n + idx]};
-      const T* E0[3] = {src.Ex, src.Ey, src.Ez};
-      T* E1[3] = {dst.Ex, dst.Ey, dst.Ez};
-      T e0[3], jd0[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) e0[c] = E0[c][idx];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) jd0[c] = (mc[c] == f.metal_id) ? JD[c][idx] : T(0);
-      const T dHz_dy = (hz - hz_jm) * inv_dx;
-      const T dHz_dx = (hz - hz_im) * inv_dx;
-      T dHy_dz = (hy - hy_km) * inv_dx;
-      T dHx_dz = (hx - hx_km) * inv_dx;
-      const T dHy_dx = (hy - hy_im) * inv_dx;
-      const T dHx_dy = (hx - hx_jm) * inv_dx;
-      const int kk = pml_plane(k, nz, f.npml);
-      if (kk >= 0) {
-        const T b = prof<T>(f, f.lay.bE, f.lay.bEf)[k];
-        const T c = prof<T>(f, f.lay.aE, f.lay.aEf)[k];
-        const T ki = prof<T>(f, f.lay.kE, f.lay.kEf)[k];
-        const long o = kk * sz + (idx - static_cast<long>(k) * sz);
-        const T p0 = psiEx[o], p1 = psiEy[o];
-        const T pex = b * p0 + c * dHy_dz;
-        const T pey = b * p1 + c * dHx_dz;
-        psiEx[o] = pex;
-        psiEy[o] = pey;
-        dHy_dz = dHy_dz * ki + pex;
-        dHx_dz = dHx_dz * ki + pey;
-      }
-      const T curl[3] = {dHz_dy - dHy_dz, dHx_dz - dHz_dx, dHy_dx - dHx_dy};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int m = mc[c];
-        T J = T(0);
-        if (m == f.metal_id) {
-          const T jd = static_cast<T>(f.alpha_d) * jd0[c] + static_cast<T>(f.beta_d) * e0[c];
-          JD[c][idx] = jd;
-          J = jd;
-        }
-        if (c == 0 && k == f.src_k) J += static_cast<T>(f.src_term);
-        T e1 = e0[c] + ce_select<T>(f, m & 3) * (curl[c] - J);
-        if (c < 2 && k == 0) e1 = T(0);
-        E1[c][idx] = e1;
-      }
-      dst.Hx[idx] = hx;
-      dst.Hy[idx] = hy;
-      dst.Hz[idx] = hz;
-    }
-    hx_km = hx;
-    hy_km = hy;
-    __syncthreads();
-  }
-}
-
-int launch_yee_sweep(const SweepArgs& a0, bool f32, hipStream_t s) {
-  SweepArgs a = a0;
-  a.tiles_x = (a.f.nx + kSwTX - 1) / kSwTX;
-  const int tiles_y = (a.f.ny + kSwTY - 1) / kSwTY;
-  const int tiles = a.tiles_x * tiles_y;
-  // planes per chunk: enough chunks for several workgroups per CU, at most 16
-  int kc = 16;
-  while (kc > 2 && static_cast<long>(tiles) * ((a.f.nz + kc - 1) / kc) < 2048) kc /= 2;
-  a.kc = kc;
-  const dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>((a.f.nz + kc - 1) / kc));
-  if (f32)
-    hipLaunchKernelGGL(yee_sweep_kernel<float>, grid, dim3(kSwTX * kSwTY), 0, s, a);
-  else
-    hipLaunchKernelGGL(yee_sweep_kernel<double>, grid, dim3(kSwTX * kSwTY), 0, s, a);
-  return static_cast<int>(hipGetLastError());
-}
-
 static dim3 yee_grid(const FdArgs& a) {
   const long plane = static_cast<long>(a.nx) * a.ny;
   return dim3(static_cast<unsigned>((plane + 255) / 256), static_cast<unsigned>(a.nz));

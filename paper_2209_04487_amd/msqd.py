@@ -36,7 +36,7 @@ EA0 = 8.4783536255e-30
 
 EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
-           "fdtd_dft_bytes", "fdtd_spare_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
+           "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
            "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
            "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end", "dipole_readout_noalloc"]
@@ -77,8 +77,7 @@ class fdtd_fields(C.Structure):
     _fields_ = [("Ex", C.c_void_p), ("Ey", C.c_void_p), ("Ez", C.c_void_p),
                 ("Hx", C.c_void_p), ("Hy", C.c_void_p), ("Hz", C.c_void_p),
                 ("JDx", C.c_void_p), ("JDy", C.c_void_p), ("JDz", C.c_void_p),
-                ("psi", C.c_void_p), ("mat", C.c_void_p), ("dft", C.c_void_p),
-                ("spare", C.c_void_p)]
+                ("psi", C.c_void_p), ("mat", C.c_void_p), ("dft", C.c_void_p)]
 
 
 class cpl_desc(C.Structure):
@@ -133,7 +132,6 @@ _sigs = {
     "fdtd_workspace_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_psi_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_dft_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
-    "fdtd_spare_bytes": (C.c_size_t, [C.POINTER(fdtd_desc)]),
     "fdtd_init": (C.c_int, [C.POINTER(fdtd_desc), _vp, _dp, C.POINTER(fdtd_fields), _vp,
                             C.c_size_t, _vp]),
     "fdtd_step": (C.c_int, [C.POINTER(fdtd_desc), C.POINTER(fdtd_fields), _vp, C.c_int64,
@@ -429,11 +427,9 @@ def fdtd_desc_from_config(cfg, prec=None, n_freq=None):
 
 
 class Fields:
-    """Yee field buffers (torch) plus the descriptor and workspace.  With
-    spare (the default) a second set of E, H and H-CPML arrays is allocated,
-    which lets coupled_step run its field steps as fused sweeps."""
+    """Yee field buffers (torch) plus the descriptor and workspace."""
 
-    def __init__(self, desc: fdtd_desc, mat_host, freqs, spare=True):
+    def __init__(self, desc: fdtd_desc, mat_host, freqs):
         self.desc = desc
         dev = _dev()
         dt = torch.float64 if desc.prec == FP64 else torch.float32
@@ -450,13 +446,8 @@ class Fields:
         if nbytes == 0:
             raise MsqdError(MSQD_EINVAL, last_error())
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
-        if spare:
-            sp_bytes = lib.fdtd_spare_bytes(C.byref(desc))
-            self.t["spare"] = torch.empty(max(sp_bytes // (8 if desc.prec == FP64 else 4), 1), dtype=dt,
-                                          device=dev)
         self.f = fdtd_fields(*[C.c_void_p(self.t[n].data_ptr()) for n in names + ["psi", "mat"]],
-                             C.c_void_p(self.t["dft"].data_ptr()) if desc.n_freq > 0 else None,
-                             C.c_void_p(self.t["spare"].data_ptr()) if spare else None)
+                             C.c_void_p(self.t["dft"].data_ptr()) if desc.n_freq > 0 else None)
         fdtd_init(desc, mat_host, freqs, self.f, self.ws)
 
     def __getattr__(self, name):
