@@ -530,21 +530,27 @@ int launch_yee_h_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
   return static_cast<int>(hipGetLastError());
 }
 
-// g = coef * sum over the source plane of ce[mat] lambda_Ex, fixed-order tree
+// g = coef sum over the source plane of ce[mat] lambda_Ex: one workgroup of
+// 1024 threads, each summing a strided share of the plane in a fixed order,
+// then a fixed tree (the plane is a few tens of thousands of cells).
+constexpr int kSrcGradThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void src_grad_kernel(FdArgs a, double coef, double* g_out) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(kSrcGradThreads) void src_grad_kernel(FdArgs a, double coef, double* g_out) {
+  __shared__ double red[kSrcGradThreads];
   const long plane = static_cast<long>(a.nx) * a.ny;
-  const long n = plane * a.nz;
   const long o = static_cast<long>(a.src_k) * plane;
   const T* lEx = static_cast<const T*>(a.Ex);
+  const double c0 = a.ce[0], c1 = a.ce[1], c2 = a.ce[2], c3 = a.ce[3];
   double s = 0.0;
-  for (long p = threadIdx.x; p < plane; p += blockDim.x)
-    s += a.ce[a.mat[o + p] & 3] * static_cast<double>(lEx[o + p]);
-  (void)n;
+  for (long p = threadIdx.x; p < plane; p += kSrcGradThreads) {
+    const int m = a.mat[o + p] & 3;
+    const double lo = (m & 1) ? c1 : c0, hi = (m & 1) ? c3 : c2;
+    s += ((m & 2) ? hi : lo) * static_cast<double>(lEx[o + p]);
+  }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kSrcGradThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -553,9 +559,9 @@ __global__ __launch_bounds__(256) void src_grad_kernel(FdArgs a, double coef, do
 
 int launch_src_grad(const FdArgs& lam, double coef, double* g_out, bool f32, hipStream_t s) {
   if (f32)
-    hipLaunchKernelGGL(src_grad_kernel<float>, dim3(1), dim3(256), 0, s, lam, coef, g_out);
+    hipLaunchKernelGGL(src_grad_kernel<float>, dim3(1), dim3(kSrcGradThreads), 0, s, lam, coef, g_out);
   else
-    hipLaunchKernelGGL(src_grad_kernel<double>, dim3(1), dim3(256), 0, s, lam, coef, g_out);
+    hipLaunchKernelGGL(src_grad_kernel<double>, dim3(1), dim3(kSrcGradThreads), 0, s, lam, coef, g_out);
   return static_cast<int>(hipGetLastError());
 }
 
