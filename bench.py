@@ -415,6 +415,7 @@ def run_adjoint(steps, fp64_check=True):
     kn = knot_values(cfg)
     yield_and_gradient(cfg.replace(n_steps=10, ckpt_every=10), kn, cfg.omega, prec="fp32")   # warm-up
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()      # blocks cached by earlier runs would split the 57 GB history
     t = time.time()
     Y, dk, dw = yield_and_gradient(cfg, kn, cfg.omega, prec="fp32")
     torch.cuda.synchronize()

@@ -68,6 +68,7 @@ QdLayout qd_layout(int n_r, int nj) {
   L.cj_d = take(8 * J);
   L.kin_f = take(8 * nr);
   L.tw_f = take(8 * 32 * 32);
+  L.tw_fs = take(8 * 32 * 32);
   L.vph_f = take(8 * 2 * J * nr);
   L.x_f = take(4 * J);
   L.mudt_f = take(4 * nr);
@@ -117,7 +118,10 @@ size_t mol_lds_bytes(int n_r, int nj, int prec) {
   const bool staged = el == 8;
   const size_t tables =
       staged ? (el * n_r + el * static_cast<size_t>(r1) * r1 + (el / 2) * n_r + 15) / 16 * 16 + 2048 + 64 : 0;
-  return tables + el * static_cast<size_t>(lds_line_start(2 * nj, n_r / split + r2, static_cast<int>(el))) +
+  // lines, the spare row of the contractions (one round of radial points),
+  // the reduction scratch
+  return tables + el * (static_cast<size_t>(lds_line_start(2 * nj, n_r / split + r2, static_cast<int>(el))) +
+                        n_r / split) +
          16 * 4 * sizeof(double);
 }
 
@@ -469,6 +473,17 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
   };
   put_lift(L.kin_f, t.kin, static_cast<double>(nr));
   put_unit(L.tw_f, t.tw_f);
+  {
+    // the same twiddles times n_r^(-1/2), an exact power of two when log2 n_r
+    // is even: the complex64 step applies the inverse transform's 1/n_r
+    // through the twiddles of its two passes
+    int lg = 0;
+    while ((1 << lg) < nr) ++lg;
+    const float sc = (lg % 2 == 0) ? std::ldexp(1.0f, -lg / 2) : 1.0f;
+    const float* src = reinterpret_cast<const float*>(host.data() + L.tw_f);
+    float* dst = reinterpret_cast<float*>(host.data() + L.tw_fs);
+    for (size_t i = 0; i < 2 * t.tw_f.size(); ++i) dst[i] = src[i] * sc;
+  }
   put_lift(L.vph_f, t.vph, 1.0);
   putf(L.x_f, t.x);
   putf(L.mudt_f, t.mudt);

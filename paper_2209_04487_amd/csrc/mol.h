@@ -25,6 +25,7 @@ struct QdLayout {
   size_t mu_d;        // double [n_r]     mu12(r) (readout)
   size_t cj_d;        // double [nj]      <J|cos|J+1>
   size_t kin_f, tw_f, vph_f, x_f, mudt_f, mask_f;   // float versions
+  size_t tw_fs;       // cx<float> tw_f x n_r^(-1/2) when n_r is an even power of two (else tw_f)
   size_t tmfrag;      // bf16 matrix-core fragments of T and T^T (hi, lo)
   size_t tmfrag_d;    // double [2][64][4] matrix-core fragments of T and T^T
   size_t tmfrag_f;    // float  [2][64][4]

@@ -181,15 +181,29 @@ struct MolTabs {
 // offset plus an immediate.  With TWC > 0 the table is the compact one that
 // holds only the rows x < R2 that are read (exp(-2 pi i x y / NR) at
 // x * TWC + y, TWC >= R1): one lane offset x = q serves both passes.
-template <typename T, int NR, bool CONJ = false, int SP = 1, int TWC = 0>
+// With TWS (complex64, n_r an even power of two) the table holds the
+// twiddles times n_r^(-1/2): each pass then scales by n_r^(-1/2) through its
+// twiddles, and the first row and column, which have none, by an explicit
+// power of two, so that the inverse transform's 1/n_r costs no multiply per
+// element (the rounded results are those of the unscaled passes times
+// exact powers of two).
+template <int NR>
+constexpr int tw_log2() { return NR <= 1 ? 0 : 1 + tw_log2<NR / 2>(); }
+template <int NR, typename T>
+constexpr bool tw_scaled() { return sizeof(T) == 4 && tw_log2<NR>() % 2 == 0; }
+
+template <typename T, int NR, bool CONJ = false, int SP = 1, int TWC = 0, bool TWS = false>
 __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const cx<T>* __restrict__ kin,
                                              const cx<T>* __restrict__ tw2) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2, U = R1 / R2;
   // SP rounds of RH = R1/SP columns each; the slot holds R2 rows of RH + 1
   constexpr int RH = R1 / SP, UH = U / SP, RS = RH + 1;
   static_assert(U % SP == 0, "columns per lane must split evenly");
+  static_assert(!TWS || tw_scaled<NR, T>(), "scaled twiddles need complex64 and an even log2 n_r");
+  const T s_half = T(1) / T(1 << (tw_log2<NR>() / 2));   // n_r^(-1/2) (TWS)
   // pass 1: DFT over p, twiddle exp(-2 pi i q a / NR)
   dft<R1, false, T>(v);
+  if constexpr (TWS) v[0] = cscale(v[0], s_half);
 #pragma unroll
   for (int a = 1; a < R1; ++a) v[a] = cmul(v[a], TWC > 0 ? tw2[q * TWC + a] : tw2[a * R1 + q]);
 #pragma unroll
@@ -211,8 +225,14 @@ __device__ __forceinline__ void kinetic_half(cx<T>* v, cx<T>* slot, int q, const
       for (int qq = 0; qq < R2; ++qq) w[qq] = slot[qq * RS + al];
       dft<R2, false, T>(w);
 #pragma unroll
-      for (int b = 0; b < R2; ++b) w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
+      for (int b = 0; b < R2; ++b) {
+        if constexpr (TWS)
+          w[b] = CONJ ? phase_mul_conj(w[b], kin[a + R1 * b]) : phase_mul(w[b], kin[a + R1 * b]);
+        else
+          w[b] = kin_mul<T, NR, CONJ>(w[b], kin[a + R1 * b]);
+      }
       dft<R2, true, T>(w);
+      if constexpr (TWS) w[0] = cscale(w[0], s_half);
 #pragma unroll
       for (int qq = 1; qq < R2; ++qq) w[qq] = cmul_conj(w[qq], tw2[qq * (TWC > 0 ? TWC : R1) + a]);
     }
@@ -298,6 +318,34 @@ __device__ __forceinline__ void sin_vers(float a, float* s, float* v) {
 }
 
 
+// sin and 1 - cos of the four node angles a_i = md x_i of one lane, FP32.
+// The short series sin a = a - a^3/6 + a^5/120 and 1 - cos a = a^2/2 - a^4/24
+// + a^6/720 are summed for every angle; their first dropped terms are below
+// 1e-9 of the result for |a| < 1/8, far under FP32 rounding.  When any angle
+// of the wavefront is larger (one uniform branch, not taken in practice),
+// those angles are redone through the library sine and cosine.
+__device__ __forceinline__ void sin_vers4(float md, const float* xk, float* sn, float* vs) {
+  float a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    a[i] = md * xk[i];
+    const float a2 = a[i] * a[i];
+    sn[i] = __builtin_fmaf(a[i] * a2, __builtin_fmaf(a2, 1.0f / 120.0f, -1.0f / 6.0f), a[i]);
+    vs[i] = a2 * __builtin_fmaf(a2, __builtin_fmaf(a2, 1.0f / 720.0f, -1.0f / 24.0f), 0.5f);
+  }
+  const float am = fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3])));
+  if (__builtin_expect(__ballot(!(am < 0.125f)) != 0, 0)) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!(fabsf(a[i]) < 0.125f)) {
+        const SinVers32 r = sin_vers_large(a[i]);
+        sn[i] = r.s;
+        vs[i] = r.v;
+      }
+    }
+  }
+}
+
 // ----------------------------------------------- C(E) on the matrix cores
 // Mixed form: psi += T^T (R - I) T psi over the J axis, per radial point, as
 // 16x16x16 BF16 matrix-core products with FP32 accumulation.  Both operands
@@ -320,20 +368,23 @@ __device__ __forceinline__ int fresh_lane() {
 typedef short mf_short4 __attribute__((ext_vector_type(4)));
 typedef float mf_float4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  const __bf16 h = static_cast<__bf16>(x);
-  return __builtin_bit_cast(unsigned short, h);
-}
-__device__ __forceinline__ float bf16_val(unsigned short b) {
-  return __uint_as_float(static_cast<unsigned int>(b) << 16);
+// hi = bf16(v), lo = bf16(v - hi), element by element, two elements per
+// packed conversion
+typedef float mf_float2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mf_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned int bf16x2_rne(float a, float b) {
+  const mf_float2 f = {a, b};
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector(f, mf_bf16x2));
 }
 __device__ __forceinline__ void split4(const float* v, mf_short4& hi, mf_short4& lo) {
+  unsigned int h[2], l[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const unsigned short h = bf16_rne(v[i]);
-    hi[i] = static_cast<short>(h);
-    lo[i] = static_cast<short>(bf16_rne(v[i] - bf16_val(h)));
+  for (int k = 0; k < 2; ++k) {
+    h[k] = bf16x2_rne(v[2 * k], v[2 * k + 1]);
+    l[k] = bf16x2_rne(v[2 * k] - __uint_as_float(h[k] << 16), v[2 * k + 1] - __uint_as_float(h[k] & 0xffff0000u));
   }
+  hi = __builtin_bit_cast(mf_short4, (unsigned long long)h[0] | ((unsigned long long)h[1] << 32));
+  lo = __builtin_bit_cast(mf_short4, (unsigned long long)l[0] | ((unsigned long long)l[1] << 32));
 }
 __device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short4 bhi,
                                          mf_short4 blo, mf_float4 c) {
@@ -342,6 +393,26 @@ __device__ __forceinline__ mf_float4 mma3(mf_short4 ahi, mf_short4 alo, mf_short
   c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
   return c;
 }
+
+// Row offsets (elements from the lines' base) of a lane's four J rows
+// J = j0 + step i of both states, fixed for a contraction round.  Rows
+// J >= nj are the spare row after the 2 nj lines, which the kernel zeroes
+// once: the operand T is zero in the columns J >= nj, so the update writes
+// back the zero it loaded, and neither the loads nor the stores of a tile
+// branch on J.
+template <int NR, typename T>
+struct CpRows {
+  int g[4], e[4];
+  __device__ __forceinline__ CpRows(int nj, int j0, int step) {
+    const int spare = lds_row<NR, T>(2 * nj);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int J = j0 + step * i;
+      g[i] = J < nj ? lds_row<NR, T>(J) : spare;
+      e[i] = J < nj ? lds_row<NR, T>(nj + J) : spare;
+    }
+  }
+};
 
 // frag: 4 operand blocks [A_hi, A_lo, At_hi, At_lo] x 64 lanes x 4 bf16;
 // x: the angle nodes padded with zeros to 16
@@ -368,6 +439,7 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
   float xk[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) xk[i] = x[rb + i];   // x holds 16 nodes, zero beyond nj
+  const CpRows<NR, T> rows(nj, rb, 1);
 #pragma unroll 1
   for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
     const int rl = tile * 16 + col;   // radial point within the round (LDS)
@@ -376,12 +448,7 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
     float gr[4], gi[4], er[4], ei[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rb + i;
-      cx<float> g = {0.f, 0.f}, e = {0.f, 0.f};
-      if (J < nj) {
-        g = sh[lds_row<NR, T>(J) + rl];
-        e = sh[lds_row<NR, T>(nj + J) + rl];
-      }
+      const cx<float> g = sh[rows.g[i] + rl], e = sh[rows.e[i] + rl];
       gr[i] = g.x; gi[i] = g.y; er[i] = e.x; ei[i] = e.y;
     }
     mf_short4 h0, l0, h1, l1, h2, l2, h3, l3;
@@ -396,16 +463,15 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
     mf_float4 Per = mma3(Ahi, Alo, h2, l2, z);
     mf_float4 Pei = mma3(Ahi, Alo, h3, l3, z);
     // (R - I) Phi per node: dg = -v Phi_g + i s Phi_e, de = i s Phi_g - v Phi_e
-    const float md = mudt[r] * E;
+    float sn[4], vs[4];
+    sin_vers4(mudt[r] * E, xk, sn, vs);
     float dgr[4], dgi[4], der[4], dei[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float sn, vs;
-      sin_vers(md * xk[i], &sn, &vs);
-      dgr[i] = -vs * Pgr[i] - sn * Pei[i];
-      dgi[i] = -vs * Pgi[i] + sn * Per[i];
-      der[i] = -vs * Per[i] - sn * Pgi[i];
-      dei[i] = -vs * Pei[i] + sn * Pgr[i];
+      dgr[i] = -vs[i] * Pgr[i] - sn[i] * Pei[i];
+      dgi[i] = -vs[i] * Pgi[i] + sn[i] * Per[i];
+      der[i] = -vs[i] * Per[i] - sn[i] * Pgi[i];
+      dei[i] = -vs[i] * Pei[i] + sn[i] * Pgr[i];
     }
     split4(dgr, h0, l0);
     split4(dgi, h1, l1);
@@ -423,11 +489,10 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
     cei = mma3(Bthi, Btlo, h3, l3, cei);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rb + i;
-      if (J < nj) {
-        sh[lds_row<NR, T>(J) + rl] = {cgr[i], cgi[i]};
-        sh[lds_row<NR, T>(nj + J) + rl] = {cer[i], cei[i]};
-      }
+      float* og = reinterpret_cast<float*>(sh + rows.g[i] + rl);
+      float* oe = reinterpret_cast<float*>(sh + rows.e[i] + rl);
+      og[0] = cgr[i]; og[1] = cgi[i];
+      oe[0] = cer[i]; oe[1] = cei[i];
     }
   }
 }
@@ -485,14 +550,15 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
   const int col = lane & 15;
   const int grp = lane >> 4;
   T A[4], At[4], xk[4];
-  int rows[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    rows[i] = MfmaK4<T>::row(grp, i);
+    const int J = MfmaK4<T>::row(grp, i);
     A[i] = frag[(0 * 64 + lane) * 4 + i];
     At[i] = frag[(1 * 64 + lane) * 4 + i];
-    xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
+    xk[i] = (J < nj) ? x[J] : T(0);
   }
+  // this lane's rows: 4 grp + i (FP32 instruction) or 4 i + grp (FP64)
+  const CpRows<NR, T> rows(nj, MfmaK4<T>::row(grp, 0), MfmaK4<T>::row(0, 1));
 #pragma unroll 1
   for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
     const int rl = tile * 16 + col;   // radial point within the round (LDS)
@@ -500,12 +566,7 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     acc_t cgr, cgi, cer, cei;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rows[i];
-      cx<T> g = {T(0), T(0)}, e = {T(0), T(0)};
-      if (J < nj) {
-        g = sh[lds_row<NR, T>(J) + rl];
-        e = sh[lds_row<NR, T>(nj + J) + rl];
-      }
+      const cx<T> g = sh[rows.g[i] + rl], e = sh[rows.e[i] + rl];
       cgr[i] = g.x; cgi[i] = g.y; cer[i] = e.x; cei[i] = e.y;
     }
     const acc_t z = {T(0), T(0), T(0), T(0)};
@@ -519,15 +580,20 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     }
     MfmaK4<T>::settle(Pgr, Pgi, Per, Pei);
     const T md = mudt[r] * E;
+    T sn[4], vs[4];
+    if constexpr (sizeof(T) == 4) {
+      sin_vers4(md, xk, sn, vs);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sin_vers(md * xk[i], &sn[i], &vs[i]);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      T sn, vs;
-      sin_vers(md * xk[i], &sn, &vs);
       const T gr = Pgr[i], gi = Pgi[i], er = Per[i], ei = Pei[i];
-      Pgr[i] = -vs * gr - sn * ei;
-      Pgi[i] = -vs * gi + sn * er;
-      Per[i] = -vs * er - sn * gi;
-      Pei[i] = -vs * ei + sn * gr;
+      Pgr[i] = -vs[i] * gr - sn[i] * ei;
+      Pgi[i] = -vs[i] * gi + sn[i] * er;
+      Per[i] = -vs[i] * er - sn[i] * gi;
+      Pei[i] = -vs[i] * ei + sn[i] * gr;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -539,11 +605,10 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     MfmaK4<T>::settle(cgr, cgi, cer, cei);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rows[i];
-      if (J < nj) {
-        sh[lds_row<NR, T>(J) + rl] = {cgr[i], cgi[i]};
-        sh[lds_row<NR, T>(nj + J) + rl] = {cer[i], cei[i]};
-      }
+      T* og = reinterpret_cast<T*>(sh + rows.g[i] + rl);
+      T* oe = reinterpret_cast<T*>(sh + rows.e[i] + rl);
+      og[0] = cgr[i]; og[1] = cgi[i];
+      oe[0] = cer[i]; oe[1] = cei[i];
     }
   }
 }
@@ -596,12 +661,14 @@ __device__ __forceinline__ void absorb_point(cx<T>& v, T m, double& ab) {
 
 // --------------------------------------------------------------- kernel
 // Occupancy target (waves per SIMD) of the fused step.  The complex64 forms
-// (three waves per molecule at J_max = 10, n_r = 256) run four molecules per
-// CU within 168 VGPRs, which the LDS copy of a molecule also allows; the FP64
+// at n_r = 256 and 512 (three waves per molecule at J_max = 10, n_r = 256)
+// run four molecules per CU within 168 VGPRs, which the LDS copy of a
+// molecule also allows; at n_r <= 128 (16 values per lane) four waves per
+// SIMD fit in 128 VGPRs and the LDS holds more molecules than that.  The FP64
 // form is bounded by LDS (one molecule of complex128 lines per CU) and may use
 // 256 VGPRs.
-template <typename T>
-struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : 3; };
+template <typename T, int NR>
+struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : (NR <= 128 ? 4 : 3); };
 
 // coupling path: BF16 hi/lo split on 16x16x16 (mixed form) or the
 // working precision on 16x16x4 (FP32 and FP64 forms)
@@ -611,7 +678,7 @@ enum { kCpExact = 0, kCpBf16x3 = 1 };
 // step loop then has no back edge, and the register allocation needs no
 // spills.
 template <typename T, int NR, int CP, bool ONE>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T>::waves)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MolOcc<T, NR>::waves)))
 void mol_step_kernel(MolArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   static_assert(CP != kCpBf16x3 || stage_tables<NR, T>(),
@@ -619,7 +686,8 @@ void mol_step_kernel(MolArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nj = a.nj;
   const int L = 2 * nj;
-  // LDS: transform tables | lines | reduction scratch
+  // LDS: transform tables | lines | spare row (the contractions' rows
+  // J >= nj) | reduction scratch
   constexpr size_t TB = lds_table_bytes<NR, T>();
   cx<T>* kin_s = reinterpret_cast<cx<T>*>(smem);
   cx<T>* tw_s = kin_s + NR;
@@ -627,7 +695,7 @@ void mol_step_kernel(MolArgs a) {
   unsigned char* frag_s = smem + StagedTables<NR, T>::fft_bytes;
   float* x_s = reinterpret_cast<float*>(frag_s + StagedTables<NR, T>::frag_bytes);
   cx<T>* sh = reinterpret_cast<cx<T>*>(smem + TB);
-  double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * lds_row<NR, T>(L));
+  double* red = reinterpret_cast<double*>(smem + TB + sizeof(cx<T>) * (lds_row<NR, T>(L) + NR / fwd_split<NR, T>()));
 
   const int mol = blockIdx.x;
   const int tid = threadIdx.x;
@@ -647,7 +715,7 @@ void mol_step_kernel(MolArgs a) {
     tb.mask = reinterpret_cast<const T*>(ws + a.lay.mask_d);
   } else {
     tb.kin = reinterpret_cast<const cx<T>*>(ws + a.lay.kin_f);
-    tb.tw = reinterpret_cast<const cx<T>*>(ws + a.lay.tw_f);
+    tb.tw = reinterpret_cast<const cx<T>*>(ws + (tw_scaled<NR, T>() ? a.lay.tw_fs : a.lay.tw_f));
     tb.vph = reinterpret_cast<const cx<T>*>(ws + a.lay.vph_f);
     tb.x = reinterpret_cast<const T*>(ws + a.lay.x_f);
     tb.mudt = reinterpret_cast<const T*>(ws + a.lay.mudt_f);
@@ -670,6 +738,10 @@ void mol_step_kernel(MolArgs a) {
   }
   if (a.E_out != nullptr && tid == 0) a.E_out[mol] = Ed;
   const T E = static_cast<T>(Ed);
+
+  // the contractions' spare row (rows J >= nj) holds zeros; the barrier
+  // before the first contraction publishes them
+  for (int i = tid; i < NR / fwd_split<NR, T>(); i += nthr) sh[lds_row<NR, T>(L) + i] = cx<T>{T(0), T(0)};
 
   cx<T>* psi = reinterpret_cast<cx<T>*>(a.psi) + static_cast<size_t>(mol) * L * NR;
   cx<T>* slot = sh + lds_row<NR, T>(line);
@@ -707,7 +779,7 @@ void mol_step_kernel(MolArgs a) {
       mask = opaque(tb.mask);
     }
     const cx<T>* vph = opaque(tb.vph);
-    if (active) kinetic_half<T, NR, false, SP>(v, slot, q, kin, tw);
+    if (active) kinetic_half<T, NR, false, SP, 0, tw_scaled<NR, T>()>(v, slot, q, kin, tw);
 #pragma unroll
     for (int h = 0; h < SP; ++h) {
       if (active) {
@@ -740,7 +812,7 @@ void mol_step_kernel(MolArgs a) {
       }
     }
     if (active) {
-      kinetic_half<T, NR, false, SP>(v, slot, q, kin, tw);
+      kinetic_half<T, NR, false, SP, 0, tw_scaled<NR, T>()>(v, slot, q, kin, tw);
       // absorber: when it lies within the last quarter of the grid only
       // those registers are tested (one uniform branch), otherwise all
       constexpr int P0 = (3 * R1) / 4;
@@ -820,7 +892,8 @@ int launch_mol_t1(const MolArgs& a, hipStream_t s) {
   int threads = ((L * R2 + 63) / 64) * 64;
   if (threads < 64) threads = 64;
   const size_t shm = lds_table_bytes<NR, T>() +
-                     sizeof(cx<T>) * static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
+                     sizeof(cx<T>) * (static_cast<size_t>(lds_line_start(L, fwd_line_stride<NR, T>(), sizeof(cx<T>))) +
+                                      NR / fwd_split<NR, T>()) +
                      16 * 4 * sizeof(double);
   static std::atomic<unsigned long long> lds_set{0};
   if (shm > 64 * 1024) {

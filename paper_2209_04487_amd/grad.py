@@ -53,6 +53,17 @@ class CoupledYield(torch.autograd.Function):
         return dk, dw, None, None, None, None
 
 
+def _device_empty(shape, dtype, dev):
+    """torch.empty on the device; when the caching allocator cannot place a
+    buffer this large among the blocks it holds, release them and try once
+    more."""
+    try:
+        return torch.empty(shape, dtype=dtype, device=dev)
+    except torch.cuda.OutOfMemoryError:
+        torch.cuda.empty_cache()
+        return torch.empty(shape, dtype=dtype, device=dev)
+
+
 def source_gradient(sysm, ckpts, src, K):
     """dY/dsrc[n] for every step, from the final state held by sysm, by
     reverse sweeps over checkpointed segments (device float64 [n_steps])."""
@@ -63,6 +74,10 @@ def source_gradient(sysm, ckpts, src, K):
     g = torch.zeros(n_steps, dtype=torch.float64, device=dev)
     n_mol = sysm.mol.desc.n_mol
     M = sysm.mol_every
+    # one history buffer of K + 1 wavepacket slots, reused by every segment
+    # (57 GB for the differentiation workload in FP32, 115 GB in FP64)
+    psi_all = _device_empty((min(K, n_steps) + 1,) + tuple(sysm.mol.psi.shape), sysm.mol.psi.dtype, dev)
+    e_all = torch.empty((min(K, n_steps), max(n_mol, 1)), dtype=torch.float64, device=dev)
     for seg in reversed(range(len(ckpts))):
         s0 = seg * K
         s1 = min(s0 + K, n_steps)
@@ -70,9 +85,8 @@ def source_gradient(sysm, ckpts, src, K):
         # the segment's wavepackets: slot 0 is the checkpoint, and each step
         # that moves the molecules reads its slot and writes the next one
         # (coupled_step's out-of-place form), so no step copies a state
-        psi_hist = torch.empty((s1 - s0 + 1,) + tuple(sysm.mol.psi.shape), dtype=sysm.mol.psi.dtype,
-                               device=dev)
-        e_hist = torch.empty((s1 - s0, max(n_mol, 1)), dtype=torch.float64, device=dev)
+        psi_hist = psi_all[:s1 - s0 + 1]
+        e_hist = e_all[:s1 - s0]
         psi_hist[0].copy_(sysm.mol.psi)
         cur = 0
         slot_of = []                      # slot holding the state before step t
@@ -90,7 +104,7 @@ def source_gradient(sysm, ckpts, src, K):
             nxt = psi_hist[t - s0 + 1] if (t % M == 0 and n_mol > 0) else None
             msqd.adjoint_step(sysm.desc, sysm.state, psi_hist[i], e_hist[t - s0], adj, t, g[t:t + 1],
                               psi_np1=nxt)
-        del psi_hist, e_hist
+    del psi_all, e_all
     buffers.clear()
     return g
 
