@@ -36,13 +36,18 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
   const int col = lane & 15;
   const int grp = lane >> 4;
   T Tf[4], Tt[4], xk[4];
-  int rows[4];
+  int rows[4], og[4], oe[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     rows[i] = MfmaK4<T>::row(grp, i);
     Tf[i] = frag[(0 * 64 + lane) * 4 + i];
     Tt[i] = frag[(1 * 64 + lane) * 4 + i];
     xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
+    // loads of rows J >= nj read row nj - 1 instead: T is zero in those
+    // columns, so the (finite) values read there are multiplied by zero
+    const int Jc = rows[i] < nj ? rows[i] : nj - 1;
+    og[i] = Jc * LS;
+    oe[i] = (nj + Jc) * LS;
   }
   double grad = 0.0;
   const acc_t z = {T(0), T(0), T(0), T(0)};
@@ -53,18 +58,12 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     acc_t agr, agi, aer, aei, bgr, bgi, ber, bei;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rows[i];
-      cx<T> g = {T(0), T(0)}, e = {T(0), T(0)}, lg = {T(0), T(0)}, le = {T(0), T(0)};
-      if (J < nj) {
-        g = A[J * LS + r];
-        e = A[(nj + J) * LS + r];
-        if constexpr (ADJ) {
-          lg = B[J * LS + r];
-          le = B[(nj + J) * LS + r];
-        }
-      }
+      const cx<T> g = A[og[i] + r], e = A[oe[i] + r];
       agr[i] = g.x; agi[i] = g.y; aer[i] = e.x; aei[i] = e.y;
-      bgr[i] = lg.x; bgi[i] = lg.y; ber[i] = le.x; bei[i] = le.y;
+      if constexpr (ADJ) {
+        const cx<T> lg = B[og[i] + r], le = B[oe[i] + r];
+        bgr[i] = lg.x; bgi[i] = lg.y; ber[i] = le.x; bei[i] = le.y;
+      }
     }
     acc_t Pgr = z, Pgi = z, Per = z, Pei = z, Lgr = z, Lgi = z, Ler = z, Lei = z;
 #pragma unroll
@@ -83,26 +82,26 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     MfmaK4<T>::settle(Pgr, Pgi, Per, Pei);
     if constexpr (ADJ) MfmaK4<T>::settle(Lgr, Lgi, Ler, Lei);
     const T md = mudt[r] * E;
+    T sn[4], vs[4];
+    sin_vers_tile<NR>(md, xk, sn, vs);
     double gl = 0.0;
     acc_t Ogr, Ogi, Oer, Oei;   // the operand of the T^T product
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      T sn, vs;
-      sin_vers(md * xk[i], &sn, &vs);
-      const T c = T(1) - vs;
+      const T c = T(1) - vs[i];
       // Phi' = R(phi) Phi: [c Pg + i s Pe, i s Pg + c Pe]
-      const T qgr = c * Pgr[i] - sn * Pei[i], qgi = c * Pgi[i] + sn * Per[i];
-      const T qer = c * Per[i] - sn * Pgi[i], qei = c * Pei[i] + sn * Pgr[i];
+      const T qgr = c * Pgr[i] - sn[i] * Pei[i], qgi = c * Pgi[i] + sn[i] * Per[i];
+      const T qer = c * Per[i] - sn[i] * Pgi[i], qei = c * Pei[i] + sn[i] * Pgr[i];
       if constexpr (ADJ) {
         // -Im[conj(L_g) Q_e + conj(L_e) Q_g]
         const double im = static_cast<double>(Lgr[i] * qei - Lgi[i] * qer) +
                           static_cast<double>(Ler[i] * qgi - Lei[i] * qgr);
         gl -= static_cast<double>(xk[i]) * im;
         // R(-phi) Lambda: [c L_g - i s L_e, -i s L_g + c L_e]
-        Ogr[i] = c * Lgr[i] + sn * Lei[i];
-        Ogi[i] = c * Lgi[i] - sn * Ler[i];
-        Oer[i] = c * Ler[i] + sn * Lgi[i];
-        Oei[i] = c * Lei[i] - sn * Lgr[i];
+        Ogr[i] = c * Lgr[i] + sn[i] * Lei[i];
+        Ogi[i] = c * Lgi[i] - sn[i] * Ler[i];
+        Oer[i] = c * Ler[i] + sn[i] * Lgi[i];
+        Oei[i] = c * Lei[i] - sn[i] * Lgr[i];
       } else {
         Ogr[i] = qgr; Ogi[i] = qgi; Oer[i] = qer; Oei[i] = qei;
       }
@@ -119,10 +118,9 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     MfmaK4<T>::settle(cgr, cgi, cer, cei);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int J = rows[i];
-      if (J < nj) {
-        B[J * LS + r] = {cgr[i], cgi[i]};
-        B[(nj + J) * LS + r] = {cer[i], cei[i]};
+      if (rows[i] < nj) {
+        B[og[i] + r] = {cgr[i], cgi[i]};
+        B[oe[i] + r] = {cer[i], cei[i]};
       }
     }
   }

@@ -346,6 +346,25 @@ __device__ __forceinline__ void sin_vers4(float md, const float* xk, float* sn, 
   }
 }
 
+// The four node angles of a contraction tile: sin_vers4 where the register
+// budget allows (three waves per SIMD, n_r >= 256); at n_r <= 128 (four waves
+// per SIMD, 128 registers) the four values held across its library fallback
+// spill, and the angles take sin_vers one at a time.
+template <int NR>
+__device__ __forceinline__ void sin_vers_tile(float md, const float* xk, float* sn, float* vs) {
+  if constexpr (NR >= 256) {
+    sin_vers4(md, xk, sn, vs);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sin_vers(md * xk[i], &sn[i], &vs[i]);
+  }
+}
+template <int NR>
+__device__ __forceinline__ void sin_vers_tile(double md, const double* xk, double* sn, double* vs) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sin_vers(md * xk[i], &sn[i], &vs[i]);
+}
+
 // ----------------------------------------------- C(E) on the matrix cores
 // Mixed form: psi += T^T (R - I) T psi over the J axis, per radial point, as
 // 16x16x16 BF16 matrix-core products with FP32 accumulation.  Both operands
@@ -464,7 +483,7 @@ __device__ __forceinline__ void coupling_mfma(cx<float>* sh, int nj, int r0,
     mf_float4 Pei = mma3(Ahi, Alo, h3, l3, z);
     // (R - I) Phi per node: dg = -v Phi_g + i s Phi_e, de = i s Phi_g - v Phi_e
     float sn[4], vs[4];
-    sin_vers4(mudt[r] * E, xk, sn, vs);
+    sin_vers_tile<NR>(mudt[r] * E, xk, sn, vs);
     float dgr[4], dgi[4], der[4], dei[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -581,12 +600,7 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     MfmaK4<T>::settle(Pgr, Pgi, Per, Pei);
     const T md = mudt[r] * E;
     T sn[4], vs[4];
-    if constexpr (sizeof(T) == 4) {
-      sin_vers4(md, xk, sn, vs);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sin_vers(md * xk[i], &sn[i], &vs[i]);
-    }
+    sin_vers_tile<NR>(md, xk, sn, vs);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const T gr = Pgr[i], gi = Pgi[i], er = Per[i], ei = Pei[i];
