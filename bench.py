@@ -619,6 +619,9 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload (4,000 forward + reverse steps) and its "
                          "forward-only timing, for a kernel trace of the adjoint")
+    ap.add_argument("--adjoint-steps", type=int, default=4000,
+                    help="steps of the differentiation workload's gradient (4,000: the whole run; fewer for "
+                         "counter runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed coupled window of the precision form (the run a kernel trace of the "
                          "headline is taken from)")
@@ -641,7 +644,7 @@ def main():
     K, W = args.steps, args.warmup
     n0 = default_first_step(cfg) if args.n0 is None else args.n0
     if args.adjoint_only:
-        adj = run_adjoint(4000)
+        adj = run_adjoint(args.adjoint_steps, fp64_check=not args.no_fp64)
         cfg3 = get_config("cfg3")
         fwd = run_coupled(cfg3, "fp32", 200, 20, default_first_step(cfg3))
         adj["forward_ms_per_step"] = fwd["ms"] / 200
