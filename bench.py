@@ -444,6 +444,18 @@ def run_adjoint(steps, fp64_check=True):
     return out
 
 
+def run_multirate(cfg, K, n0, M=40):
+    """The precision form with the molecules stepped every M field steps
+    (the paper's M = 40), over about K field steps from the M-aligned step
+    at or before n0, after M untimed ones."""
+    k_mr = max(M, (K // M) * M)
+    log(f"multi-rate coupled run: molecules every {M} field steps, {k_mr} steps")
+    mr = run_coupled(cfg, "mixed", k_mr, M, n0 - (n0 % M), mol_every=M)
+    return {"mol_every": M, "field_steps": k_mr, "ms_per_field_step": mr["ms"] / k_mr,
+            "field_steps_per_s": k_mr / (mr["ms"] / 1e3),
+            "molecule_steps_per_s": mr["n_mol"] * (k_mr // M) / (mr["ms"] / 1e3)}
+
+
 def calibration_copy(nbytes=1 << 30, reps=3):
     """Device-to-device copies of a known size, for scaling the HBM byte
     counters of a counter run (FETCH_SIZE / WRITE_SIZE) to bytes."""
@@ -625,6 +637,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed coupled window of the precision form (the run a kernel trace of the "
                          "headline is taken from)")
+    ap.add_argument("--multirate-only", action="store_true",
+                    help="only the multi-rate window (molecules every 40 field steps), for a kernel trace")
     ap.add_argument("--kernel", choices=["mixed", "fp32", "fp64", "stencil", "jm", "jm5"], default=None,
                     help="only time the molecular-step kernel of this form, or the field stencil (for counter runs), "
                          "followed by a 1 GiB calibration copy")
@@ -649,6 +663,9 @@ def main():
         fwd = run_coupled(cfg3, "fp32", 200, 20, default_first_step(cfg3))
         adj["forward_ms_per_step"] = fwd["ms"] / 200
         print(json.dumps(adj))
+        return
+    if args.multirate_only:
+        print(json.dumps(run_multirate(cfg, K, n0)), flush=True)
         return
     if args.kernel == "stencil":
         ms = time_stencil(cfg, "mixed", K)
@@ -734,13 +751,7 @@ def main():
             "dipole_trace_rel_l2": rel_l2(dm["D"], d64["D"]),
             "flux_spectrum_rel_l2": rel_l2(dm["flux"], d64["flux"])}
 
-    M = 40
-    k_mr = max(M, (K // M) * M)
-    log(f"multi-rate coupled run: molecules every {M} field steps, {k_mr} steps")
-    mr = run_coupled(cfg, "mixed", k_mr, M, n0 - (n0 % M), mol_every=M)
-    multirate = {"mol_every": M, "field_steps": k_mr, "ms_per_field_step": mr["ms"] / k_mr,
-                 "field_steps_per_s": k_mr / (mr["ms"] / 1e3),
-                 "molecule_steps_per_s": mr["n_mol"] * (k_mr // M) / (mr["ms"] / 1e3)}
+    multirate = run_multirate(cfg, K, n0)
 
     log("(j, m)-basis coupled run: 691,200 molecules, j <= 1")
     jm = run_jm(cfg, 20, 2, n0)

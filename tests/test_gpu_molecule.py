@@ -36,6 +36,10 @@ CASES = [
     ("fp32", 128, 6, 7, 1),
     ("fp32", 256, 10, 4, 1),
     ("mixed", 64, 1, 3, 1),
+    # few J rows: most lanes of a contraction tile read and write the spare row
+    ("mixed", 128, 0, 3, 1),
+    ("fp32", 256, 2, 3, 1),
+    ("fp64", 128, 2, 3, 1),
 ]
 
 
