@@ -452,11 +452,14 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* s, cpl_adj* adj, void
  * psi_np1 is the wavepackets after step n (the recompute's next state, e.g.
  * written there by coupled_step's psi_next), or NULL: given, the molecular
  * adjoint reads the absorber's input back from it instead of recomputing
- * the second half of the forward step.  s supplies the maps, tables and
- * material map of the forward system.
+ * the second half of the forward step.  In the FP64 form the step then also
+ * uses psi_np1 as its scratch (it holds the coupling's input there), so its
+ * contents are undefined on return: a reverse sweep passes each recorded
+ * state as psi_np1 only after its last use as psi_n.  s supplies the maps,
+ * tables and material map of the forward system.
  * Errors: MSQD_EINVAL also for n < 0 and for psi_np1 misaligned or equal
  * to psi_n. */
-int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, const void* psi_np1,
+int adjoint_step(const cpl_desc* d, const cpl_state* s, const void* psi_n, void* psi_np1,
                  const double* E_mol_n, cpl_adj* adj, int64_t n, double* g_src, void* stream);
 
 #ifdef __cplusplus

@@ -10,7 +10,7 @@ struct MolAdjArgs {
   int n_mol, nj, kdiss;
   double dr;
   const void* psi_n;      // state before the step (recomputed forward inside)
-  const void* psi_np1;    // state after the step, or nullptr (then recomputed too)
+  void* psi_np1;          // state after the step (FP64: overwritten, scratch), or nullptr (then recomputed too)
   const double* E_mol;    // field used by the step (au)
   void* lpsi;             // in: adjoint after the step; out: before
   const double* labs;     // adjoint of the absorbed norm (unchanged by the step)

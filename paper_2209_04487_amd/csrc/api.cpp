@@ -1138,7 +1138,7 @@ int adjoint_init_yield(const cpl_desc* d, const cpl_state* st, cpl_adj* adj, voi
   return MSQD_OK;
 }
 
-int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, const void* psi_np1,
+int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, void* psi_np1,
                  const double* E_mol_n, cpl_adj* adj, int64_t n, double* g_src, void* stream) {
   int rc = check_adj(d, st, adj);
   if (rc) return rc;

@@ -100,7 +100,8 @@ def source_gradient(sysm, ckpts, src, K):
             e_hist[t - s0].copy_(sysm.E_mol)
         for t in reversed(range(s0, s1)):
             i = slot_of[t - s0]
-            # at a molecular step the state after it sits in slot t - s0 + 1
+            # at a molecular step the state after it sits in slot t - s0 + 1;
+            # it is not read again (the FP64 adjoint step uses it as scratch)
             nxt = psi_hist[t - s0 + 1] if (t % M == 0 and n_mol > 0) else None
             msqd.adjoint_step(sysm.desc, sysm.state, psi_hist[i], e_hist[t - s0], adj, t, g[t:t + 1],
                               psi_np1=nxt)
