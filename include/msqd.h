@@ -302,6 +302,13 @@ int map_build(int32_t n_mol, int32_t nx, int32_t ny, int32_t nz, uint64_t seed,
 int map_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t* occ_cell,
             int32_t* occ_ptr, int32_t* mol_perm, int32_t* n_occ);
 
+/* Host helper: the planes held_k0 .. held_k0 + held_nk - 1 that hold every
+ * occupied cell (occ_cell: host [n_occ] flat E_x indices of an nx x ny x nz
+ * grid), for cpl_desc's held-current array.  MSQD_EINVAL for n_occ < 1, a
+ * NULL pointer or an index outside the grid. */
+int map_planes(int32_t n_occ, const int32_t* occ_cell, int32_t nx, int32_t ny, int32_t nz,
+               int32_t* held_k0, int32_t* held_nk);
+
 typedef struct {
   qd_desc qd;
   fdtd_desc fd;
@@ -310,6 +317,9 @@ typedef struct {
   int32_t mol_every;    /* M: molecules step every M field steps (0 or 1:
                            every step); qd.dt_au must equal M fd.dt in
                            atomic units (relative 1e-9)                     */
+  int32_t held_k0;      /* with s->E_held: planes held_k0 .. held_k0 +      */
+  int32_t held_nk;      /* held_nk - 1 hold every occupied cell (ignored
+                           when s->E_held is NULL)                          */
 } cpl_desc;
 
 typedef struct {
@@ -335,6 +345,21 @@ typedef struct {
                                 keeps every step's state without copies.  With
                                 mol_every > 1 only the steps where the
                                 molecules step (n % mol_every == 0) write it. */
+  void* E_held;              /* NULL: the molecular current is subtracted from
+                                E by a pass after each E update.  Else the
+                                E update subtracts it itself, reading this
+                                array: [ncomp][held_nk][ny][nx] in the field
+                                precision (ncomp = 3 in the (j, m) basis,
+                                else 1), caller-owned, 16-byte aligned,
+                                zero-filled by the caller before its first
+                                use and again whenever the occupied cells
+                                change.  The library keeps dt/(eps0 eps_r)
+                                J_mol in it at each occupied edge; a call
+                                that starts between molecular updates
+                                rebuilds it from J_mol, so J_mol and P_c
+                                alone carry the state (checkpoints need not
+                                hold it).  An occupied cell outside the held
+                                planes sets its E components to NaN. */
 } cpl_state;
 
 /* n_steps coupled steps from step n0 (section on molecular mapping, with
@@ -347,7 +372,11 @@ typedef struct {
  * molecule taking one step of M dt under E_x^n; J_mol = (P_new - P_old)/(M dt)
  * is then applied unchanged at every field step until the next update.
  * src_values: host [n_steps], E_inc(t_{n+1/2}) in V/m.
+ * With s->E_held set the results are bit-identical to those without it: the
+ * new J_mol is formed after the molecular step and before the E update, which
+ * then subtracts it, so the steps between updates launch no separate pass.
  * Errors: MSQD_EINVAL for a step/precision mismatch (qd.dt_au != M fd.dt),
+ * for s->E_held misaligned or with held planes outside the grid,
  * and for s->psi_next set with n_steps != 1, misaligned or equal to s->psi;
  * MSQD_EUNSUP for s->psi_next set in the (j, m) basis. */
 int coupled_step(const cpl_desc* d, const cpl_state* s, const double* src_values, int64_t n0,

@@ -1,6 +1,7 @@
 // C ABI of libmsqd: argument validation, workspace tables, kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -863,6 +864,23 @@ int map_csr(int32_t n_mol, int32_t n_cells, const int32_t* cell_of_mol, int32_t*
   return MSQD_OK;
 }
 
+int map_planes(int32_t n_occ, const int32_t* occ_cell, int32_t nx, int32_t ny, int32_t nz,
+               int32_t* held_k0, int32_t* held_nk) {
+  if (n_occ < 1 || nx < 1 || ny < 1 || nz < 1) return fail(MSQD_EINVAL, "bad sizes");
+  if (!occ_cell || !held_k0 || !held_nk) return fail(MSQD_EINVAL, "NULL pointer");
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  int64_t lo = nz, hi = -1;
+  for (int32_t c = 0; c < n_occ; ++c) {
+    if (occ_cell[c] < 0 || occ_cell[c] >= plane * nz) return fail(MSQD_EINVAL, "cell index out of range");
+    const int64_t k = occ_cell[c] / plane;
+    lo = std::min(lo, k);
+    hi = std::max(hi, k);
+  }
+  *held_k0 = static_cast<int32_t>(lo);
+  *held_nk = static_cast<int32_t>(hi - lo + 1);
+  return MSQD_OK;
+}
+
 int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_values, int64_t n0,
                  int32_t n_steps, void* stream) {
   if (!d || !st) return fail(MSQD_EINVAL, "NULL descriptor or state");
@@ -887,6 +905,11 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     if (d->qd.basis != MSQD_BASIS_M0) return fail(MSQD_EUNSUP, "psi_next (out-of-place step) needs the m = 0 basis");
     if (n_steps != 1) return fail(MSQD_EINVAL, "psi_next (out-of-place step) needs n_steps = 1");
     if (!aligned16(st->psi_next) || st->psi_next == st->psi) return fail(MSQD_EINVAL, "psi_next misaligned or equal to psi");
+  }
+  if (st->E_held) {
+    if (!aligned16(st->E_held)) return fail(MSQD_EINVAL, "E_held misaligned");
+    if (d->held_nk < 1 || d->held_k0 < 0 || d->held_k0 > d->fd.nz - d->held_nk)
+      return fail(MSQD_EINVAL, "held planes outside the grid");
   }
   const int M = d->mol_every > 1 ? d->mol_every : 1;
   {
@@ -933,8 +956,25 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     da.Ez = st->f.Ez;
   }
   da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
+  const bool held = st->E_held != nullptr;
+  if (held) {
+    fa.held = st->E_held;
+    fa.held_k0 = d->held_k0;
+    fa.held_nk = d->held_nk;
+    fa.held_nc = da.ncomp;
+    da.held = st->E_held;
+    da.held_k0 = d->held_k0;
+    da.held_nk = d->held_nk;
+    da.plane = static_cast<long>(d->fd.nx) * d->fd.ny;
+  }
   for (int32_t t = 0; t < n_steps; ++t)
     if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
+  if (held && n_steps > 0 && (n0 % M) != 0) {
+    // between updates: the held array from the current J_mol
+    da.update = 0;
+    const int e = launch_deposit(da, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "held current launch");
+  }
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     const bool mol_now = (n % M) == 0;
@@ -947,11 +987,22 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
       if (rc) return rc;
       timing_mark(false, s);
     }
-    e = launch_yee_e(fa, f32, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
-    da.update = mol_now ? 1 : 0;
-    e = launch_deposit(da, f32, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+    if (held) {
+      // the new current goes into the held array; the E update subtracts it
+      if (mol_now) {
+        da.update = 1;
+        e = launch_deposit(da, f32, s);
+        if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+      }
+      e = launch_yee_e(fa, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
+    } else {
+      e = launch_yee_e(fa, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
+      da.update = mol_now ? 1 : 0;
+      e = launch_deposit(da, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
+    }
     rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
     if (rc) return rc;
   }

@@ -23,6 +23,10 @@ struct FdArgs {
   const uint8_t* mat;
   const char* ws;
   FdLayout lay;
+  // held molecular current (coupled step): E update subtracts held[c] on
+  // planes held_k0 .. held_k0 + held_nk - 1 for components c < held_nc
+  const void* held;
+  int held_k0, held_nk, held_nc;       // held_nc = 0: none
 };
 
 int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s);
@@ -55,6 +59,11 @@ struct DepArgs {
   int ncomp;                           // 1: E_x only; 3: E_x, E_y, E_z (d_mol [n][3])
   void *Ey, *Ez;
   long ncells;                         // cells per component array (material planes)
+  // non-null: write dt/(eps0 eps_r) J into held ([ncomp][held_nk][plane])
+  // instead of subtracting it from E
+  void* held;
+  int held_k0, held_nk;
+  long plane;                          // nx ny
 };
 int launch_deposit(const DepArgs& a, bool f32, hipStream_t s);
 

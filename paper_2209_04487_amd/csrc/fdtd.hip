@@ -149,11 +149,18 @@ __global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
   const int mc[3] = {mat[idx], mat[n + idx], mat[2 * n + idx]};
   T* E[3] = {f.Ex, f.Ey, f.Ez};
   T* JD[3] = {f.JDx, f.JDy, f.JDz};
-  T e0[3], jd0[3];
+  T e0[3], jd0[3], hv[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) e0[c] = E[c][idx];
 #pragma unroll
   for (int c = 0; c < 3; ++c) jd0[c] = (mc[c] == a.metal_id) ? JD[c][idx] : T(0);
+  // the held molecular current, on the planes that hold occupied cells (k is
+  // uniform over the workgroup)
+  const bool in_held = k >= a.held_k0 && k < a.held_k0 + a.held_nk;
+  const long hn = static_cast<long>(a.held_nk) * sz;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    hv[c] = (in_held && c < a.held_nc) ? static_cast<const T*>(a.held)[c * hn + idx - a.held_k0 * sz] : T(0);
   const T inv_dx = static_cast<T>(a.inv_dx);
 
   const T dHz_dy = (hz - hz_jm) * inv_dx;
@@ -193,6 +200,8 @@ __global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
     if (c == 0 && k == a.src_k) J += static_cast<T>(a.src_term);
     T e1 = e0[c] + ce_select<T>(a, m & 3) * (curl[c] - J);
     if (c < 2 && k == 0) e1 = T(0);
+    // the molecular current after the update, as the separate pass applies it
+    if (in_held && c < a.held_nc) e1 = e1 - hv[c];
     E[c][idx] = e1;
   }
 }
@@ -325,7 +334,9 @@ int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hip
 // Per occupied cell: P^{n+1} = (w e a0 / dx^3) sum_{i in cell} d_i in CSR
 // order, J = (P^{n+1} - P^n)/dt_mol, and E_x at the cell loses
 // dt/(eps0 eps_r) J.  Between molecular updates (multi-rate coupling) only
-// the held J is applied.
+// the held J is applied.  With a held array the term is stored there for the
+// E update to subtract (update = 0 then rebuilds the array from J_mol), and
+// a cell outside the held planes sets its E component to NaN.
 template <typename T>
 __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,7 +359,17 @@ __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
     }
     const int m = a.mat[static_cast<size_t>(k) * a.ncells + cell] & 3;
     T* E = static_cast<T*>(fld[k]);
-    E[cell] = E[cell] - static_cast<T>(a.ce[m] * J);
+    const T v = static_cast<T>(a.ce[m] * J);
+    if (a.held) {
+      const long kc = cell / a.plane;
+      if (kc >= a.held_k0 && kc < a.held_k0 + a.held_nk)
+        static_cast<T*>(a.held)[(static_cast<long>(k) * a.held_nk + kc - a.held_k0) * a.plane +
+                                (cell - kc * a.plane)] = v;
+      else
+        E[cell] = __builtin_nan("");
+    } else {
+      E[cell] = E[cell] - v;
+    }
   }
 }
 

@@ -36,7 +36,7 @@ EA0 = 8.4783536255e-30
 
 EXPORTS = ["msqd_last_error", "msqd_version", "qd_workspace_bytes", "qd_init", "qd_step",
            "dipole_readout", "msqd_check_status", "fdtd_workspace_bytes", "fdtd_psi_bytes",
-           "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr",
+           "fdtd_dft_bytes", "fdtd_init", "fdtd_step", "flux_readout", "map_build", "map_csr", "map_planes",
            "coupled_step", "adjoint_scratch_bytes", "adjoint_init_yield", "adjoint_step",
            "bloch_init", "bloch_step", "coupled_bloch_step", "excited_r_readout", "qd_jm_tables_size",
            "qd_jm_tables", "spectra_readout", "msqd_mol_timing_begin", "msqd_mol_timing_end", "dipole_readout_noalloc"]
@@ -82,7 +82,8 @@ class fdtd_fields(C.Structure):
 
 class cpl_desc(C.Structure):
     _fields_ = [("qd", qd_desc), ("fd", fdtd_desc), ("n_occ", C.c_int32),
-                ("mol_weight", C.c_double), ("mol_every", C.c_int32)]
+                ("mol_weight", C.c_double), ("mol_every", C.c_int32),
+                ("held_k0", C.c_int32), ("held_nk", C.c_int32)]
 
 
 class cpl_state(C.Structure):
@@ -90,7 +91,7 @@ class cpl_state(C.Structure):
                 ("E_mol", C.c_void_p), ("P_c", C.c_void_p), ("J_mol", C.c_void_p),
                 ("cell_of_mol", C.c_void_p), ("occ_cell", C.c_void_p), ("occ_ptr", C.c_void_p),
                 ("mol_perm", C.c_void_p), ("f", fdtd_fields), ("qd_ws", C.c_void_p),
-                ("fd_ws", C.c_void_p), ("psi_next", C.c_void_p)]
+                ("fd_ws", C.c_void_p), ("psi_next", C.c_void_p), ("E_held", C.c_void_p)]
 
 
 class bloch_desc(C.Structure):
@@ -141,6 +142,7 @@ _sigs = {
     "map_build": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32,
                             C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
     "map_csr": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]),
+    "map_planes": (C.c_int, [C.c_int32, _i32p, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p]),
     "coupled_step": (C.c_int, [C.POINTER(cpl_desc), C.POINTER(cpl_state), _dp, C.c_int64,
                                C.c_int32, _vp]),
     "adjoint_scratch_bytes": (C.c_size_t, [C.POINTER(cpl_desc)]),
@@ -299,6 +301,14 @@ def map_csr(cell_of_mol, n_cells):
                        ptr.ctypes.data_as(_i32p), perm.ctypes.data_as(_i32p), C.byref(n_occ)))
     k = n_occ.value
     return occ[:k].copy(), ptr[:k + 1].copy(), perm[:n_mol].copy()
+
+
+def map_planes(occ_cell, nx, ny, nz):
+    """(held_k0, held_nk): the planes that hold every occupied cell."""
+    occ = np.ascontiguousarray(occ_cell, dtype=np.int32)
+    k0, nk = C.c_int32(0), C.c_int32(0)
+    _check(lib.map_planes(len(occ), occ.ctypes.data_as(_i32p), nx, ny, nz, C.byref(k0), C.byref(nk)))
+    return k0.value, nk.value
 
 
 def coupled_step(d, st, src_values, n0, stream=None):
@@ -480,7 +490,11 @@ class Coupled:
     """The self-consistent system: molecules + fields + maps, driven by
     coupled_step."""
 
-    def __init__(self, cfg, prec=None, n_mol=None, cells=None, mat=None, n_freq=None, mol_every=1):
+    def __init__(self, cfg, prec=None, n_mol=None, cells=None, mat=None, n_freq=None, mol_every=1,
+                 held=True):
+        """held: let the E update subtract the molecular current from an
+        array over the planes of the occupied cells (coupled_step's E_held),
+        instead of a separate pass after it; the results are the same."""
         from workloads.geometry import material_map
         prec = prec or cfg.precision
         self.cfg = cfg
@@ -529,6 +543,12 @@ class Coupled:
                                C.c_void_p(self.mol_perm.data_ptr()), self.fields.f,
                                C.c_void_p(self.mol.ws.data_ptr()),
                                C.c_void_p(self.fields.ws.data_ptr()))
+        self.E_held = None
+        if held and len(occ) > 0:
+            k0, nk = map_planes(occ, cfg.nx, cfg.ny, cfg.nz)
+            self.desc.held_k0, self.desc.held_nk = k0, nk
+            self.E_held = torch.zeros((nc, nk, cfg.ny, cfg.nx), dtype=self.fields.t["Ex"].dtype, device=dev)
+            self.state.E_held = C.c_void_p(self.E_held.data_ptr())
         self.n = 0
 
     def step(self, src_values):
@@ -709,5 +729,5 @@ def version():
 
 __all__ = ["Molecules", "Fields", "Coupled", "Bloch", "CoupledBloch", "CarrierBatch", "qd_init", "qd_step",
            "dipole_readout", "fdtd_init", "fdtd_step", "flux_readout", "spectra_readout", "spectra",
-           "excited_r", "map_build", "map_csr", "coupled_step", "check_status", "jm_tables", "MsqdError", "lib",
+           "excited_r", "map_build", "map_csr", "map_planes", "coupled_step", "check_status", "jm_tables", "MsqdError", "lib",
            "LIB_PATH", "EXPORTS"]

@@ -183,3 +183,36 @@ def test_jm_basis_validation(msqd):
     assert ws(512, 4, msqd.FP32) > 0 and ws(512, 2, msqd.FP64) > 0 and ws(256, 3, msqd.FP64) > 0
     d = msqd.qd_desc(4, 128, 1, msqd.FP64, 1.0, 12.0, 1e4, 0.1379, 2.0, 8.0, 7)
     assert msqd.lib.qd_workspace_bytes(C.byref(d)) == 0
+
+
+def test_map_planes_and_held_plane_validation(msqd):
+    """map_planes gives the z range of the occupied cells; coupled_step rejects
+    a held-current array whose planes leave the grid, before any launch (the
+    device pointers are placeholders, never touched)."""
+    nx, ny, nz = 8, 6, 10
+    plane = nx * ny
+    assert msqd.map_planes(np.array([3 * plane + 5, 3 * plane + 7, 6 * plane]), nx, ny, nz) == (3, 4)
+    assert msqd.map_planes(np.array([0]), nx, ny, nz) == (0, 1)
+    assert msqd.map_planes(np.array([nz * plane - 1]), nx, ny, nz) == (nz - 1, 1)
+    for bad in [np.array([nz * plane]), np.array([-1]), np.array([], np.int32)]:
+        with pytest.raises(msqd.MsqdError):
+            msqd.map_planes(bad, nx, ny, nz)
+    from workloads import get_config
+    cfg = get_config("cfg0")
+    qd = msqd.qd_desc(64, cfg.n_r, cfg.j_max, msqd.FP64, cfg.r_min, cfg.r_max, cfg.mass,
+                      cfg.dt_au, cfg.absorb_width, cfg.r_diss)
+    fd = msqd.fdtd_desc_from_config(cfg, "fp64")
+    fake = C.c_void_p(1 << 20)
+    f = msqd.fdtd_fields(*([fake] * 11), fake)
+    st = msqd.cpl_state(fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, f, fake, fake)
+    st.E_held = fake
+    src = np.zeros(1)
+    for k0, nk in [(0, 0), (-1, 2), (cfg.nz - 1, 2)]:
+        d = msqd.cpl_desc(qd, fd, 8, 1.0, 1, k0, nk)
+        rc = msqd.lib.coupled_step(C.byref(d), C.byref(st), src.ctypes.data_as(C.POINTER(C.c_double)),
+                                   0, 1, None)
+        assert rc == msqd.MSQD_EINVAL and "held planes" in msqd.last_error(), (k0, nk, rc)
+    st.E_held = C.c_void_p((1 << 20) + 8)
+    d = msqd.cpl_desc(qd, fd, 8, 1.0, 1, 10, 4)
+    rc = msqd.lib.coupled_step(C.byref(d), C.byref(st), src.ctypes.data_as(C.POINTER(C.c_double)), 0, 1, None)
+    assert rc == msqd.MSQD_EINVAL and "E_held misaligned" in msqd.last_error()

@@ -136,3 +136,63 @@ def test_coupled_multirate_rejects_step_mismatch():
     sysm.desc.mol_every = 5            # molecules were built for 4 dt
     with pytest.raises(msqd.MsqdError):
         sysm.step(np.zeros(2))
+
+
+def _state_tensors(sysm):
+    t = {k: sysm.fields.t[k] for k in ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "JDx", "JDy", "JDz", "psi", "dft"]}
+    t.update(mol_psi=sysm.mol.psi, absorbed=sysm.mol.absorbed, d=sysm.mol.d, P_c=sysm.P_c, J_mol=sysm.J_mol,
+             E_mol=sysm.E_mol)
+    return t
+
+
+@pytest.mark.parametrize("basis,prec,mol_every", [("m0", "mixed", 1), ("m0", "mixed", 5), ("m0", "fp32", 5),
+                                                   ("m0", "fp64", 5), ("jm", "fp64", 3)])
+def test_held_current_path_is_bit_identical(basis, prec, mol_every):
+    """coupled_step with the held-current array (the E update subtracts the
+    molecular current) against the separate pass after the E update: every
+    field, wavepacket, absorbed norm, dipole and polarisation array bit for bit,
+    over calls of uneven length that start on and between molecular updates,
+    and after a restore between updates (the call rebuilds the held array)."""
+    from paper_2209_04487_amd import msqd
+    over = dict(j_max=1, basis="jm", mol_weight=3e3) if basis == "jm" else {}
+    cfg = get_config("cfg0", **over)
+    n0, nsteps = 150, 60
+    banner(f"held current {basis} {prec} M={mol_every}, steps {n0}..{n0 + nsteps}")
+    src = source_values(cfg, n0, nsteps)
+    runs = []
+    for held in (True, False):
+        sysm = msqd.Coupled(cfg, prec=prec, mol_every=mol_every, held=held)
+        assert (sysm.E_held is not None) == held
+        sysm.n = n0
+        s, snap = 0, None
+        for chunk in [3, 1, 7, 2, 11, 4, 9, 6]:
+            sysm.step(src[s:s + chunk])
+            s += chunk
+            if s == 13:
+                snap = sysm.snapshot()
+        sysm.restore(snap)                 # back to step n0 + 13
+        sysm.step(src[13:13 + 8])
+        sysm.step(src[21:21 + 5])
+        torch.cuda.synchronize()
+        runs.append({k: v.clone() for k, v in _state_tensors(sysm).items()})
+    assert float(runs[0]["J_mol"].abs().max()) > 0
+    for k in runs[0]:
+        assert torch.equal(runs[0][k], runs[1][k]), k
+
+
+def test_held_current_outside_its_planes_poisons_the_field():
+    """An occupied cell outside the held planes sets its E_x to NaN at the next
+    molecular update (cfg0's molecules sit on planes 10..13; plane 23 is given
+    as the held range)."""
+    from paper_2209_04487_amd import msqd
+    cfg = get_config("cfg0")
+    banner("held current outside its planes")
+    sysm = msqd.Coupled(cfg, prec="fp64")
+    assert (sysm.desc.held_k0, sysm.desc.held_nk) == (10, 4)
+    sysm.desc.held_k0, sysm.desc.held_nk = cfg.nz - 1, 1
+    sysm.step(source_values(cfg, 0, 1))
+    torch.cuda.synchronize()
+    ex = sysm.fields.Ex.cpu().numpy().reshape(-1)
+    occ = sysm.occ_cell.cpu().numpy()
+    assert np.isnan(ex[occ]).all()
+    assert np.isfinite(np.delete(ex, occ)).all()
