@@ -244,11 +244,15 @@ typedef struct {
                       planes k < npml then k >= nz - npml                    */
   uint8_t* mat;    /* [3][nz][ny][nx] material id per E-component location  */
   double* dft;     /* [planes][4][n_freq][ny][nx] complex128 (E_x, E_y, H_x,
-                      H_y), planes = 2 with mon_k2, else 1; or NULL         */
+                      H_y), planes = 2 with mon_k2, else 1; then the monitor's
+                      staging area, [planes][8][4][ny][nx] float64, whose
+                      contents between calls carry nothing (each call folds
+                      its staged samples in before it returns); or NULL     */
 } fdtd_fields;
 
 size_t fdtd_workspace_bytes(const fdtd_desc* d);
-/* Bytes of the CPML auxiliary buffer `psi` and of the monitor buffer `dft`. */
+/* Bytes of the CPML auxiliary buffer `psi` and of the monitor buffer `dft`
+ * (accumulators and staging area; 0 without a monitor). */
 size_t fdtd_psi_bytes(const fdtd_desc* d);
 size_t fdtd_dft_bytes(const fdtd_desc* d);
 

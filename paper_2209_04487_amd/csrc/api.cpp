@@ -689,7 +689,10 @@ size_t fdtd_psi_bytes(const fdtd_desc* d) {
 
 size_t fdtd_dft_bytes(const fdtd_desc* d) {
   if (check_fd(d) != MSQD_OK) return 0;
-  return fd_planes(d) * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx * 16;
+  if (d->n_freq <= 0) return 0;
+  // the accumulators, then the staged samples of each plane
+  const size_t plane = static_cast<size_t>(d->ny) * d->nx;
+  return fd_planes(d) * (4 * static_cast<size_t>(d->n_freq) * plane * 16 + kMonRing * 4 * plane * 8);
 }
 
 static void cpml_profile(const fdtd_desc* d, double offset, std::vector<double>& b,
@@ -770,30 +773,73 @@ int fdtd_init(const fdtd_desc* d, const uint8_t* mat_host, const double* freqs,
   return MSQD_OK;
 }
 
-static int fd_monitor(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t n,
-                      hipStream_t s) {
-  if (d->n_freq <= 0 || (n + 1) % d->mon_every != 0) return MSQD_OK;
+// The monitor samples of one call: staged in the ring behind the
+// accumulators and folded in kMonRing at a time and at the call's last
+// sample, so that every call ends with the accumulators complete; a call
+// whose only sample finds the ring empty updates them directly.
+struct MonBatch {
+  int ns = 0;
+  double tE[kMonRing], tH[kMonRing];
+};
+
+static MonArgs mon_args(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int plane_index) {
   MonArgs m{};
   m.nx = d->nx;
   m.ny = d->ny;
-  m.mon_k = d->mon_k;
+  m.mon_k = plane_index == 0 ? d->mon_k : d->mon_k2;
   m.n_freq = d->n_freq;
-  m.tE = static_cast<double>(n + 1) * d->dt;
-  m.tH = (static_cast<double>(n) + 0.5) * d->dt;
   m.wdt = d->mon_every * d->dt;
   m.Ex = f->Ex;
   m.Ey = f->Ey;
   m.Hx = f->Hx;
   m.Hy = f->Hy;
-  m.dft = f->dft;
+  const size_t plane = static_cast<size_t>(d->ny) * d->nx;
+  m.dft = f->dft + plane_index * 2 * 4 * static_cast<size_t>(d->n_freq) * plane;
+  m.ring = f->dft + fd_planes(d) * 2 * 4 * static_cast<size_t>(d->n_freq) * plane +
+           plane_index * static_cast<size_t>(kMonRing) * 4 * plane;
   m.freqs = reinterpret_cast<const double*>(static_cast<const char*>(ws) + fd_layout(d).freqs);
-  int e = launch_monitor(m, d->prec != MSQD_FP64, s);
-  if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
-  if (fd_planes(d) == 2) {
-    m.mon_k = d->mon_k2;
-    m.dft = f->dft + 2 * 4 * static_cast<size_t>(d->n_freq) * d->ny * d->nx;
-    e = launch_monitor(m, d->prec != MSQD_FP64, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
+  return m;
+}
+
+// the monitor part of step n of a call whose last step is n_last
+static int fd_monitor(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t n, int64_t n_last,
+                      MonBatch& b, hipStream_t s) {
+  if (d->n_freq <= 0 || (n + 1) % d->mon_every != 0) return MSQD_OK;
+  const bool f32 = d->prec != MSQD_FP64;
+  const bool last = n + d->mon_every > n_last;   // no further sample in this call
+  const double tE = static_cast<double>(n + 1) * d->dt, tH = (static_cast<double>(n) + 0.5) * d->dt;
+  const int planes = fd_planes(d);
+  if (b.ns == 0 && last) {
+    for (int pl = 0; pl < planes; ++pl) {
+      MonArgs m = mon_args(d, f, ws, pl);
+      m.tE = tE;
+      m.tH = tH;
+      const int e = launch_monitor(m, f32, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "monitor launch");
+    }
+    return MSQD_OK;
+  }
+  for (int pl = 0; pl < planes; ++pl) {
+    MonArgs m = mon_args(d, f, ws, pl);
+    m.slot = b.ns;
+    const int e = launch_monitor_stage(m, f32, s);
+    if (e) return check_hip(static_cast<hipError_t>(e), "monitor stage launch");
+  }
+  b.tE[b.ns] = tE;
+  b.tH[b.ns] = tH;
+  ++b.ns;
+  if (b.ns == kMonRing || last) {
+    for (int pl = 0; pl < planes; ++pl) {
+      MonArgs m = mon_args(d, f, ws, pl);
+      m.ns = b.ns;
+      for (int i = 0; i < b.ns; ++i) {
+        m.tEs[i] = b.tE[i];
+        m.tHs[i] = b.tH[i];
+      }
+      const int e = launch_monitor_fold(m, s);
+      if (e) return check_hip(static_cast<hipError_t>(e), "monitor fold launch");
+    }
+    b.ns = 0;
   }
   return MSQD_OK;
 }
@@ -814,7 +860,8 @@ int fdtd_step(const fdtd_desc* d, const fdtd_fields* f, const void* ws, int64_t 
   if (e) return check_hip(static_cast<hipError_t>(e), "H update launch");
   e = launch_yee_e(a, f32, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
-  return fd_monitor(d, f, ws, n, s);
+  MonBatch mb;
+  return fd_monitor(d, f, ws, n, n, mb, s);
 }
 
 int flux_readout(const fdtd_desc* d, const fdtd_fields* f, double* flux, void* stream) {
@@ -975,6 +1022,7 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
     const int e = launch_deposit(da, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "held current launch");
   }
+  MonBatch mb;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     const bool mol_now = (n % M) == 0;
@@ -1003,7 +1051,7 @@ int coupled_step(const cpl_desc* d, const cpl_state* st, const double* src_value
       e = launch_deposit(da, f32, s);
       if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
     }
-    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
+    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, n0 + n_steps - 1, mb, s);
     if (rc) return rc;
   }
   return MSQD_OK;
@@ -1106,6 +1154,7 @@ int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* st, const
   da.Ex = st->f.Ex;
   da.ncomp = 1;
   da.ncells = static_cast<long>(d->fd.nx) * d->fd.ny * d->fd.nz;
+  MonBatch mb;
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t n = n0 + t;
     if (!std::isfinite(src_values[t])) return fail(MSQD_EINVAL, "source value not finite");
@@ -1118,7 +1167,7 @@ int coupled_bloch_step(const cpl_bloch_desc* d, const cpl_bloch_state* st, const
     if (e) return check_hip(static_cast<hipError_t>(e), "E update launch");
     e = launch_deposit(da, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "deposit launch");
-    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, s);
+    rc = fd_monitor(&d->fd, &st->f, st->fd_ws, n, n0 + n_steps - 1, mb, s);
     if (rc) return rc;
   }
   return MSQD_OK;

@@ -32,14 +32,27 @@ struct FdArgs {
 int launch_yee_h(const FdArgs& a, bool f32, hipStream_t s);
 int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s);
 
+// samples staged behind the accumulators before one pass folds them in
+constexpr int kMonRing = 8;
+
 struct MonArgs {
   int nx, ny, mon_k, n_freq;
   double tE, tH, wdt;                  // sample times, weight (every * dt)
   const void *Ex, *Ey, *Hx, *Hy;
   double* dft;
   const double* freqs;
+  double* ring;                        // [kMonRing][4][ny][nx] staged samples of this plane
+  int slot;                            // stage: the slot written
+  int ns;                              // fold: the samples staged, in time order
+  double tEs[kMonRing], tHs[kMonRing]; // fold: their sample times
 };
+// one sample straight into the accumulators
 int launch_monitor(const MonArgs& a, bool f32, hipStream_t s);
+// one sample into ring slot a.slot
+int launch_monitor_stage(const MonArgs& a, bool f32, hipStream_t s);
+// the a.ns staged samples into the accumulators, in order (the same
+// accumulator updates, in the same order, as a.ns direct samples)
+int launch_monitor_fold(const MonArgs& a, hipStream_t s);
 int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hipStream_t s);
 
 struct DepArgs {

@@ -235,42 +235,63 @@ int launch_yee_e(const FdArgs& a, bool f32, hipStream_t s) {
 // frequencies: all of the group's loads are issued before its stores, and
 // the frequency axis spreads the update over enough workgroups to fill the
 // chip on small planes.
+// Within one call the samples are staged (monitor_stage_kernel) and folded
+// into the accumulators up to kMonRing at a time (monitor_fold_kernel): the
+// accumulators, 4 n_freq complex values per point against 4 sample values,
+// are then read and written once per batch.  Each accumulator takes the same
+// fused multiply-adds in the same order either way.
 constexpr int kMonFreqs = 4;
+
+// the four sampled values of plane point p
+template <typename T>
+__device__ __forceinline__ void mon_values(const MonArgs& a, long plane, long p, double val[4]) {
+  const long o = static_cast<long>(a.mon_k) * plane + p;
+  val[0] = static_cast<const T*>(a.Ex)[o];
+  val[1] = static_cast<const T*>(a.Ey)[o];
+  val[2] = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hx)[o - plane]) + static_cast<const T*>(a.Hx)[o]);
+  val[3] = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hy)[o - plane]) + static_cast<const T*>(a.Hy)[o]);
+}
+
+// cos and sin of w_f t_E and w_f t_H, times the weight
+__device__ __forceinline__ void mon_phases(const MonArgs& a, int f, double tE, double tH, double* ph) {
+  double s, c;
+  sincos(a.freqs[f] * tE, &s, &c);
+  ph[0] = c * a.wdt;
+  ph[1] = s * a.wdt;
+  sincos(a.freqs[f] * tH, &s, &c);
+  ph[2] = c * a.wdt;
+  ph[3] = s * a.wdt;
+}
+
+// accumulator c of frequency f at point p
+__device__ __forceinline__ long mon_acc(const MonArgs& a, int c, int f, long plane, long p) {
+  return (static_cast<long>(c) * a.n_freq + f) * plane + p;
+}
+
+__device__ __forceinline__ void mon_add(double2& w, double v, const double* ph, int c) {
+  w.x = fma(v, ph[c < 2 ? 0 : 2], w.x);
+  w.y = fma(v, ph[c < 2 ? 1 : 3], w.y);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void monitor_kernel(MonArgs a) {
-  __shared__ double ph[kMonFreqs][4];  // cos tE, sin tE, cos tH, sin tH (times the weight)
+  __shared__ double ph[kMonFreqs][4];
   const int f0 = static_cast<int>(blockIdx.y) * kMonFreqs;
   const int nf = min(kMonFreqs, a.n_freq - f0);
-  if (threadIdx.x < nf) {
-    const int f = f0 + threadIdx.x;
-    double s, c;
-    sincos(a.freqs[f] * a.tE, &s, &c);
-    ph[threadIdx.x][0] = c * a.wdt;
-    ph[threadIdx.x][1] = s * a.wdt;
-    sincos(a.freqs[f] * a.tH, &s, &c);
-    ph[threadIdx.x][2] = c * a.wdt;
-    ph[threadIdx.x][3] = s * a.wdt;
-  }
+  if (threadIdx.x < nf) mon_phases(a, f0 + threadIdx.x, a.tE, a.tH, ph[threadIdx.x]);
   __syncthreads();
   const long plane = static_cast<long>(a.nx) * a.ny;
   const long p = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= plane) return;
-  const long o = static_cast<long>(a.mon_k) * plane + p;
-  const double ex = static_cast<const T*>(a.Ex)[o];
-  const double ey = static_cast<const T*>(a.Ey)[o];
-  const double hx = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hx)[o - plane]) +
-                           static_cast<const T*>(a.Hx)[o]);
-  const double hy = 0.5 * (static_cast<double>(static_cast<const T*>(a.Hy)[o - plane]) +
-                           static_cast<const T*>(a.Hy)[o]);
-  const double val[4] = {ex, ey, hx, hy};
+  double val[4];
+  mon_values<T>(a, plane, p, val);
   double2* acc = reinterpret_cast<double2*>(a.dft);
   double2 z[kMonFreqs][4];
 #pragma unroll
   for (int fi = 0; fi < kMonFreqs; ++fi) {
     if (fi < nf) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) z[fi][c] = acc[(static_cast<long>(c) * a.n_freq + f0 + fi) * plane + p];
+      for (int c = 0; c < 4; ++c) z[fi][c] = acc[mon_acc(a, c, f0 + fi, plane, p)];
     }
   }
 #pragma unroll
@@ -278,26 +299,98 @@ __global__ __launch_bounds__(256) void monitor_kernel(MonArgs a) {
     if (fi < nf) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const double cw = ph[fi][c < 2 ? 0 : 2];
-        const double sw = ph[fi][c < 2 ? 1 : 3];
-        double2 w = z[fi][c];
-        w.x += val[c] * cw;
-        w.y += val[c] * sw;
-        acc[(static_cast<long>(c) * a.n_freq + f0 + fi) * plane + p] = w;
+        mon_add(z[fi][c], val[c], ph[fi], c);
+        acc[mon_acc(a, c, f0 + fi, plane, p)] = z[fi][c];
       }
     }
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void monitor_stage_kernel(MonArgs a) {
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const long p = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= plane) return;
+  double val[4];
+  mon_values<T>(a, plane, p, val);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) a.ring[(static_cast<long>(a.slot) * 4 + c) * plane + p] = val[c];
+}
+
+__global__ __launch_bounds__(256) void monitor_fold_kernel(MonArgs a) {
+  __shared__ double ph[kMonRing][kMonFreqs][4];
+  const int f0 = static_cast<int>(blockIdx.y) * kMonFreqs;
+  const int nf = min(kMonFreqs, a.n_freq - f0);
+  const int ns = a.ns;
+  if (threadIdx.x < kMonRing * kMonFreqs) {
+    const int sl = threadIdx.x / kMonFreqs, fi = threadIdx.x % kMonFreqs;
+    if (sl < ns && fi < nf) mon_phases(a, f0 + fi, a.tEs[sl], a.tHs[sl], ph[sl][fi]);
+  }
+  __syncthreads();
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const long p = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= plane) return;
+  double2* acc = reinterpret_cast<double2*>(a.dft);
+  double2 z[kMonFreqs][4];
+#pragma unroll
+  for (int fi = 0; fi < kMonFreqs; ++fi) {
+    if (fi < nf) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) z[fi][c] = acc[mon_acc(a, c, f0 + fi, plane, p)];
+    }
+  }
+  for (int sl = 0; sl < ns; ++sl) {
+    double val[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) val[c] = a.ring[(static_cast<long>(sl) * 4 + c) * plane + p];
+#pragma unroll
+    for (int fi = 0; fi < kMonFreqs; ++fi) {
+      if (fi < nf) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mon_add(z[fi][c], val[c], ph[sl][fi], c);
+      }
+    }
+  }
+#pragma unroll
+  for (int fi = 0; fi < kMonFreqs; ++fi) {
+    if (fi < nf) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[mon_acc(a, c, f0 + fi, plane, p)] = z[fi][c];
+    }
+  }
+}
+
+static dim3 mon_grid(const MonArgs& a) {
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  return dim3(static_cast<unsigned>((plane + 255) / 256),
+              static_cast<unsigned>((a.n_freq + kMonFreqs - 1) / kMonFreqs));
+}
+
 int launch_monitor(const MonArgs& a, bool f32, hipStream_t s) {
   if (a.n_freq <= 0) return 0;
-  const long plane = static_cast<long>(a.nx) * a.ny;
-  const dim3 grid(static_cast<unsigned>((plane + 255) / 256),
-                  static_cast<unsigned>((a.n_freq + kMonFreqs - 1) / kMonFreqs));
   if (f32)
-    hipLaunchKernelGGL(monitor_kernel<float>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(monitor_kernel<float>, mon_grid(a), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(monitor_kernel<double>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(monitor_kernel<double>, mon_grid(a), dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_monitor_stage(const MonArgs& a, bool f32, hipStream_t s) {
+  if (a.n_freq <= 0) return 0;
+  if (a.slot < 0 || a.slot >= kMonRing) return static_cast<int>(hipErrorInvalidValue);
+  const long plane = static_cast<long>(a.nx) * a.ny;
+  const dim3 grid(static_cast<unsigned>((plane + 255) / 256));
+  if (f32)
+    hipLaunchKernelGGL(monitor_stage_kernel<float>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(monitor_stage_kernel<double>, grid, dim3(256), 0, s, a);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_monitor_fold(const MonArgs& a, hipStream_t s) {
+  if (a.n_freq <= 0 || a.ns <= 0) return 0;
+  if (a.ns > kMonRing) return static_cast<int>(hipErrorInvalidValue);
+  hipLaunchKernelGGL(monitor_fold_kernel, mon_grid(a), dim3(256), 0, s, a);
   return static_cast<int>(hipGetLastError());
 }
 

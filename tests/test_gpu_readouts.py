@@ -150,3 +150,32 @@ def test_ensemble_sums_match_per_molecule_sums(basis, j_max, n_mol):
         np.testing.assert_allclose(s[c], dd[:, c].sum(), rtol=1e-12, atol=1e-12 * np.abs(dd).sum())
     np.testing.assert_allclose(s[nc], nrm.cpu().numpy()[:n_mol].sum(), rtol=1e-13)
     np.testing.assert_allclose(s[nc + 1], yld.cpu().numpy()[:n_mol].sum(), rtol=1e-13)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_staged_monitor_samples_equal_direct_samples(prec):
+    """The monitor's accumulators of both detection planes are the same bits
+    whether the samples are staged and folded in batches (one long call: 75
+    samples, batches of 8 and a last one of 3), in calls of uneven length
+    (batches cut at every call end), or taken one per call (straight into the
+    accumulators)."""
+    from paper_2209_04487_amd import msqd
+    nsteps = 300
+    cfg = get_config("cfg0", pulse="cw", mon_k2=9, mol_weight=3e3, n_freq=8)
+    banner(f"staged monitor samples, cfg0 {prec}, two planes, {nsteps} steps")
+    src = source_values(cfg, 0, nsteps)
+    plans = [[nsteps], [1, 7, 2, 33, 4, 40, 13, 200], [1] * nsteps]
+    acc = []
+    for plan in plans:
+        sysm = msqd.Coupled(cfg, prec=prec)
+        s = 0
+        for k in plan:
+            sysm.step(src[s:s + k])
+            s += k
+        assert s == nsteps
+        torch.cuda.synchronize()
+        n_acc = 2 * 4 * cfg.n_freq * cfg.ny * cfg.nx
+        acc.append(sysm.fields.t["dft"][:n_acc].clone())
+    assert float(acc[0].abs().max()) > 0
+    for a in acc[1:]:
+        assert torch.equal(a, acc[0])
