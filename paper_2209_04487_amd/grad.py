@@ -7,9 +7,11 @@ hand-written adjoint of the coupled step (adjoint_step in libmsqd) in
 reverse, with checkpoint-and-recompute: the forward run stores the full
 state every K steps; the backward pass restores each checkpoint in turn,
 recomputes its K steps keeping the wavepackets and gathered fields of every
-step in device memory, and sweeps back through them.  The last stage, the
-chain rule from dY/dE_inc(t_n) to the pulse parameters, is a small
-contraction with the pulse's Jacobian.
+step in device memory, and sweeps back through them.  The forward run keeps
+the history of its last segment in that same buffer, so the reverse sweep
+starts without a recompute.  The last stage, the chain rule from
+dY/dE_inc(t_n) to the pulse parameters, is a small contraction with the
+pulse's Jacobian.
 """
 
 from __future__ import annotations
@@ -30,20 +32,32 @@ class CoupledYield(torch.autograd.Function):
         w = float(omega.detach().cpu())
         src = source_values(cfg, 0, n_steps, knots=kn, omega=w)
         sysm = msqd.Coupled(cfg, prec=prec, mol_every=mol_every)
+        hist = _history_buffers(sysm, K, n_steps)
         ckpts = []
+        slot_of = []
         for s0 in range(0, n_steps, K):
-            ckpts.append(sysm.snapshot())
-            sysm.step(src[s0:min(s0 + K, n_steps)])
+            s1 = min(s0 + K, n_steps)
+            if s1 < n_steps:
+                ckpts.append(sysm.snapshot())
+                sysm.step(src[s0:s1])
+            else:
+                # the last segment straight into the history buffer; the live
+                # wavepackets then take its final state
+                ckpts.append(None)
+                slot_of, cur = _segment_history(sysm, src, s0, s1, *hist)
+                sysm.mol.psi.copy_(hist[0][cur])
         # the objective: the mean over molecules of the library's FP64 sum of
         # the per-molecule dissociated populations (dipole_readout)
         Y = sysm.ensemble_sums()[-1].detach().clone() / sysm.mol.desc.n_mol
         ctx.sysm, ctx.ckpts, ctx.src, ctx.K = sysm, ckpts, src, K
+        ctx.hist, ctx.last_slots = hist, slot_of
         ctx.cfg, ctx.kn, ctx.w = cfg, kn, w
         return Y
 
     @staticmethod
     def backward(ctx, gY):
-        g = source_gradient(ctx.sysm, ctx.ckpts, ctx.src, ctx.K)
+        g = source_gradient(ctx.sysm, ctx.ckpts, ctx.src, ctx.K, hist=ctx.hist, last_slots=ctx.last_slots)
+        ctx.hist = None
         from workloads.pulses import source_jacobian
         jac = source_jacobian(ctx.cfg, 0, len(ctx.src), knots=ctx.kn, omega=ctx.w)
         dp = jac @ g.cpu().numpy()
@@ -64,9 +78,46 @@ def _device_empty(shape, dtype, dev):
         return torch.empty(shape, dtype=dtype, device=dev)
 
 
-def source_gradient(sysm, ckpts, src, K):
+def _history_buffers(sysm, K, n_steps):
+    """One history buffer of K + 1 wavepacket slots and K gathered fields,
+    reused by every segment (57 GB for the differentiation workload in FP32,
+    115 GB in FP64)."""
+    dev = sysm.mol.psi.device
+    n_mol = sysm.mol.desc.n_mol
+    psi_all = _device_empty((min(K, n_steps) + 1,) + tuple(sysm.mol.psi.shape), sysm.mol.psi.dtype, dev)
+    e_all = torch.empty((min(K, n_steps), max(n_mol, 1)), dtype=torch.float64, device=dev)
+    return psi_all, e_all
+
+
+def _segment_history(sysm, src, s0, s1, psi_all, e_all):
+    """Advance sysm over steps s0..s1-1 from its current state, keeping the
+    segment's wavepackets and gathered fields: slot 0 is the state at s0, and
+    each step that moves the molecules reads its slot and writes the next one
+    (coupled_step's out-of-place form), so no step copies a state.  Returns
+    the slot holding the state before each step, and the slot of the final
+    state.  The live wavepackets are left as they were."""
+    n_mol = sysm.mol.desc.n_mol
+    M = sysm.mol_every
+    psi_all[0].copy_(sysm.mol.psi)
+    cur = 0
+    slot_of = []
+    for t in range(s0, s1):
+        slot_of.append(cur)
+        if t % M == 0 and n_mol > 0:
+            sysm.step_out_of_place(src[t], psi_all[cur], psi_all[t - s0 + 1])
+            cur = t - s0 + 1
+        else:
+            sysm.step(src[t:t + 1])
+        e_all[t - s0].copy_(sysm.E_mol)
+    return slot_of, cur
+
+
+def source_gradient(sysm, ckpts, src, K, hist=None, last_slots=None):
     """dY/dsrc[n] for every step, from the final state held by sysm, by
-    reverse sweeps over checkpointed segments (device float64 [n_steps])."""
+    reverse sweeps over checkpointed segments (device float64 [n_steps]).
+    ckpts[seg] is the state at the start of segment seg; hist, when given, is
+    the history buffer, and last_slots the slots of the last segment already
+    in it (its checkpoint may then be None)."""
     n_steps = len(src)
     dev = sysm.mol.psi.device
     adj, buffers = sysm.adjoint_buffers()
@@ -74,36 +125,22 @@ def source_gradient(sysm, ckpts, src, K):
     g = torch.zeros(n_steps, dtype=torch.float64, device=dev)
     n_mol = sysm.mol.desc.n_mol
     M = sysm.mol_every
-    # one history buffer of K + 1 wavepacket slots, reused by every segment
-    # (57 GB for the differentiation workload in FP32, 115 GB in FP64)
-    psi_all = _device_empty((min(K, n_steps) + 1,) + tuple(sysm.mol.psi.shape), sysm.mol.psi.dtype, dev)
-    e_all = torch.empty((min(K, n_steps), max(n_mol, 1)), dtype=torch.float64, device=dev)
+    psi_all, e_all = hist if hist is not None else _history_buffers(sysm, K, n_steps)
+    last = len(ckpts) - 1
     for seg in reversed(range(len(ckpts))):
         s0 = seg * K
         s1 = min(s0 + K, n_steps)
-        sysm.restore(ckpts[seg])
-        # the segment's wavepackets: slot 0 is the checkpoint, and each step
-        # that moves the molecules reads its slot and writes the next one
-        # (coupled_step's out-of-place form), so no step copies a state
-        psi_hist = psi_all[:s1 - s0 + 1]
-        e_hist = e_all[:s1 - s0]
-        psi_hist[0].copy_(sysm.mol.psi)
-        cur = 0
-        slot_of = []                      # slot holding the state before step t
-        for t in range(s0, s1):
-            slot_of.append(cur)
-            if t % M == 0 and n_mol > 0:
-                sysm.step_out_of_place(src[t], psi_hist[cur], psi_hist[t - s0 + 1])
-                cur = t - s0 + 1
-            else:
-                sysm.step(src[t:t + 1])
-            e_hist[t - s0].copy_(sysm.E_mol)
+        if seg == last and last_slots:
+            slot_of = last_slots
+        else:
+            sysm.restore(ckpts[seg])
+            slot_of, _ = _segment_history(sysm, src, s0, s1, psi_all, e_all)
         for t in reversed(range(s0, s1)):
             i = slot_of[t - s0]
             # at a molecular step the state after it sits in slot t - s0 + 1;
             # it is not read again (the FP64 adjoint step uses it as scratch)
-            nxt = psi_hist[t - s0 + 1] if (t % M == 0 and n_mol > 0) else None
-            msqd.adjoint_step(sysm.desc, sysm.state, psi_hist[i], e_hist[t - s0], adj, t, g[t:t + 1],
+            nxt = psi_all[t - s0 + 1] if (t % M == 0 and n_mol > 0) else None
+            msqd.adjoint_step(sysm.desc, sysm.state, psi_all[i], e_all[t - s0], adj, t, g[t:t + 1],
                               psi_np1=nxt)
     del psi_all, e_all
     buffers.clear()
