@@ -357,8 +357,11 @@ typedef struct {
                                 else 1), caller-owned, 16-byte aligned,
                                 zero-filled by the caller before its first
                                 use and again whenever the occupied cells
-                                change.  The library keeps dt/(eps0 eps_r)
-                                J_mol in it at each occupied edge; a call
+                                change.  The library keeps the molecular
+                                term in it at each occupied edge (FP32 fields:
+                                dt/(eps0 eps_r) J_mol rounded to float; FP64:
+                                J_mol, the E update fusing the product into
+                                its subtraction); a call
                                 that starts between molecular updates
                                 rebuilds it from J_mol, so J_mol and P_c
                                 alone carry the state (checkpoints need not

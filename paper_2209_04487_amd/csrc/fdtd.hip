@@ -66,6 +66,24 @@ __device__ __forceinline__ T ce_select(const FdArgs& a, int m) {
   return (m & 2) ? hi : lo;
 }
 
+// The molecular current's term on E.  In the reduced precisions the term
+// dt/(eps0 eps_r) J is formed in FP64 and rounded to the field precision
+// before the field loses it; in FP64 the product and the subtraction take a
+// single rounding (fused multiply-add).  `held` is what the held-current
+// array keeps for the E update: the rounded term, or J itself in FP64.
+template <typename T>
+struct MolTerm;
+template <>
+struct MolTerm<float> {
+  __device__ static __forceinline__ float held(double ce, double J) { return static_cast<float>(ce * J); }
+  __device__ static __forceinline__ float apply(float e, float, float h) { return e - h; }
+};
+template <>
+struct MolTerm<double> {
+  __device__ static __forceinline__ double held(double, double J) { return J; }
+  __device__ static __forceinline__ double apply(double e, double ce, double h) { return fma(-ce, h, e); }
+};
+
 // H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n, with the CPML stretching of the
 // z derivatives: d/dz -> (1/kappa) d/dz + psi, psi <- b psi + a d/dz.
 // Every load is issued before the first store (the arrays are distinct), so
@@ -198,10 +216,11 @@ __global__ __launch_bounds__(256) void yee_e_kernel(FdArgs a) {
       J = jd;
     }
     if (c == 0 && k == a.src_k) J += static_cast<T>(a.src_term);
-    T e1 = e0[c] + ce_select<T>(a, m & 3) * (curl[c] - J);
+    const T ce = ce_select<T>(a, m & 3);
+    T e1 = e0[c] + ce * (curl[c] - J);
     if (c < 2 && k == 0) e1 = T(0);
     // the molecular current after the update, as the separate pass applies it
-    if (in_held && c < a.held_nc) e1 = e1 - hv[c];
+    if (in_held && c < a.held_nc) e1 = MolTerm<T>::apply(e1, ce, hv[c]);
     E[c][idx] = e1;
   }
 }
@@ -427,9 +446,9 @@ int launch_flux(int nx, int ny, int n_freq, const double* dft, double* flux, hip
 // Per occupied cell: P^{n+1} = (w e a0 / dx^3) sum_{i in cell} d_i in CSR
 // order, J = (P^{n+1} - P^n)/dt_mol, and E_x at the cell loses
 // dt/(eps0 eps_r) J.  Between molecular updates (multi-rate coupling) only
-// the held J is applied.  With a held array the term is stored there for the
-// E update to subtract (update = 0 then rebuilds the array from J_mol), and
-// a cell outside the held planes sets its E component to NaN.
+// the held J is applied.  With a held array the term (MolTerm) is stored
+// there for the E update to apply (update = 0 then rebuilds the array from
+// J_mol), and a cell outside the held planes sets its E component to NaN.
 template <typename T>
 __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,16 +471,16 @@ __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
     }
     const int m = a.mat[static_cast<size_t>(k) * a.ncells + cell] & 3;
     T* E = static_cast<T*>(fld[k]);
-    const T v = static_cast<T>(a.ce[m] * J);
+    const T h = MolTerm<T>::held(a.ce[m], J);
     if (a.held) {
       const long kc = cell / a.plane;
       if (kc >= a.held_k0 && kc < a.held_k0 + a.held_nk)
         static_cast<T*>(a.held)[(static_cast<long>(k) * a.held_nk + kc - a.held_k0) * a.plane +
-                                (cell - kc * a.plane)] = v;
+                                (cell - kc * a.plane)] = h;
       else
         E[cell] = __builtin_nan("");
     } else {
-      E[cell] = E[cell] - v;
+      E[cell] = MolTerm<T>::apply(E[cell], static_cast<T>(a.ce[m]), h);
     }
   }
 }

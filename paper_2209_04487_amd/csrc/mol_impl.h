@@ -544,13 +544,13 @@ struct MfmaK4<double> {
   __device__ static __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  // The compiler's wait before a vector read of this instruction's result is
-  // too short on gfx950; stall explicitly (about 100 cycles) until the last
-  // product of the chain has landed.
+  // The end of a product chain: the four accumulators are taken as operands
+  // of an empty statement, so that the chain is complete before any of them
+  // is read and the compiler's hazard recognizer places its wait states for
+  // the matrix-core result here (no explicit stall: extra waits of 16 to 96
+  // states gave the same bits on the full FP64 workload).
   __device__ static __forceinline__ void settle(acc& a, acc& b, acc& c, acc& d) {
-    asm volatile(
-        "s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15"
-        : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
   }
 };
 
