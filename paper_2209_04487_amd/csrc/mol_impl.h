@@ -805,6 +805,11 @@ void mol_step_kernel(MolArgs a) {
         }
       }
       __syncthreads();
+      // the contraction runs at raised wave priority: a workgroup's waves wait
+      // for its slowest one at the next barrier, so on a SIMD shared with
+      // other workgroups' transforms its issue comes first (0.7% faster at the
+      // 100,000-molecule launch, alternating builds on one box)
+      __builtin_amdgcn_s_setprio(1);
       // contraction operands: from the LDS copy (complex64 forms) or the workspace
       if constexpr (CP == kCpBf16x3) {
         coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(frag_s),
@@ -816,6 +821,7 @@ void mol_step_kernel(MolArgs a) {
         const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
         coupling_mfma_exact<T, NR>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
       }
+      __builtin_amdgcn_s_setprio(0);
       __syncthreads();
       if (active) {
 #pragma unroll
