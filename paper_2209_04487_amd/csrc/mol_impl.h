@@ -684,9 +684,14 @@ __device__ __forceinline__ void absorb_point(cx<T>& v, T m, double& ab) {
 template <typename T, int NR>
 struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : (NR <= 128 ? 4 : 3); };
 
+
 // coupling path: BF16 hi/lo split on 16x16x16 (mixed form) or the
 // working precision on 16x16x4 (FP32 and FP64 forms)
 enum { kCpExact = 0, kCpBf16x3 = 1 };
+
+// raised wave priority over the contraction rounds (see the step loop)
+template <typename T, int NR, int CP>
+inline constexpr bool kPrioContraction = CP == kCpBf16x3 && NR >= 256;
 
 // ONE: the launch advances exactly one step (the coupled step's case); the
 // step loop then has no back edge, and the register allocation needs no
@@ -805,11 +810,13 @@ void mol_step_kernel(MolArgs a) {
         }
       }
       __syncthreads();
-      // the contraction runs at raised wave priority: a workgroup's waves wait
-      // for its slowest one at the next barrier, so on a SIMD shared with
-      // other workgroups' transforms its issue comes first (0.7% faster at the
-      // 100,000-molecule launch, alternating builds on one box)
-      __builtin_amdgcn_s_setprio(1);
+      // in the mixed form at N_r >= 256 the contraction runs at raised wave
+      // priority: a workgroup's waves wait for its slowest one at the next
+      // barrier, so on a SIMD shared with other workgroups' transforms its
+      // issue comes first (0.3-0.9% faster at the 100,000-molecule launch; in
+      // the FP32 form it measured 0.7% slower at N_r = 256 and 1.5% at 128,
+      // in FP64 the same)
+      if constexpr (kPrioContraction<T, NR, CP>) __builtin_amdgcn_s_setprio(1);
       // contraction operands: from the LDS copy (complex64 forms) or the workspace
       if constexpr (CP == kCpBf16x3) {
         coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(frag_s),
@@ -821,7 +828,7 @@ void mol_step_kernel(MolArgs a) {
         const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
         coupling_mfma_exact<T, NR>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
       }
-      __builtin_amdgcn_s_setprio(0);
+      if constexpr (kPrioContraction<T, NR, CP>) __builtin_amdgcn_s_setprio(0);
       __syncthreads();
       if (active) {
 #pragma unroll
