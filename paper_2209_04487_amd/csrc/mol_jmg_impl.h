@@ -87,6 +87,38 @@ __device__ __forceinline__ int zigzag_task(int pass, int tid) {
   return pass * NTHR + ((NTHR % 64 == 0 && (pass & 1)) ? NTHR - 1 - tid : tid);
 }
 
+// Workgroups of more than four whole wavefronts (nine at j_max = 5) put more
+// of them on some SIMDs than on others, and with a fixed share of the tasks
+// per wavefront those SIMDs set the pace of every stage.  Their stages
+// therefore hand out the tasks dynamically: each wavefront takes the next 64
+// (heaviest first) from an LDS counter, so the wavefronts that share a SIMD
+// take fewer.  Every task writes only its own outputs, so the results do not
+// depend on which wavefront takes it.
+template <int NTHR>
+inline constexpr bool kDynStages = NTHR % 64 == 0 && NTHR > 4 * 64;
+
+// Run body(t) for t in [0, nt): dynamically (ctr: an LDS counter that is zero
+// on entry) or in the zigzag passes.
+template <int NTHR, typename F>
+__device__ __forceinline__ void stage_tasks(int* ctr, int nt, int tid, F&& body) {
+  if constexpr (kDynStages<NTHR>) {
+    const int lane = tid & 63;
+    for (;;) {
+      int c = 0;
+      if (lane == 0) c = atomicAdd(ctr, 1);
+      c = __builtin_amdgcn_readfirstlane(c);
+      if (c * 64 >= nt) break;
+      const int t = c * 64 + lane;
+      if (t < nt) body(t);
+    }
+  } else {
+    for (int pass = 0; pass * NTHR < nt; ++pass) {
+      const int t = zigzag_task<NTHR>(pass, tid);
+      if (t < nt) body(t);
+    }
+  }
+}
+
 // Rotation of the j block of state s at radial point rl: to the field frame
 // (BACK = false) or back (BACK = true).  dmr holds d^j(beta) row-major
 // [m + j][m' + j] and dmt its transpose, each row padded to 16 bytes at
@@ -157,17 +189,15 @@ __device__ __forceinline__ void jmg_rot_dispatch(int j, cx<T>* sh, const T* dmr,
 // spread over the workgroup.
 template <typename T, int NR, int JM, bool BACK>
 __device__ __forceinline__ void jmg_rotate(cx<T>* sh, const T* dmr, const T* dmt, const cx<T>* ph, int tid,
-                                           int nthr) {
+                                           int* ctr) {
   constexpr int NRH = JmgShape<T, NR, JM>::NRH;
   constexpr int NT = 2 * JM * NRH;
-  for (int pass = 0; pass * nthr < NT; ++pass) {
-    const int t = zigzag_task<JmgShape<T, NR, JM>::threads>(pass, tid);
-    if (t >= NT) continue;
+  stage_tasks<JmgShape<T, NR, JM>::threads>(ctr, NT, tid, [&](int t) {
     const int jr = t / (2 * NRH);
     const int rem = t - jr * 2 * NRH;
     const int s = rem / NRH;
     jmg_rot_dispatch<T, NR, JM, JM, BACK>(JM - jr, sh, dmr, dmt, ph, s, rem - s * NRH);
-  }
+  });
 }
 
 // Stage B on the block m' (|m'| = A) at radial point rl: the states
@@ -248,18 +278,16 @@ __device__ __forceinline__ void jmg_couple_dispatch(int a, cx<T>* sh, const T* q
 // All (m', r) tasks of a round, m' in the order 0, 1, -1, 2, -2, ...
 template <typename T, int NR, int JM>
 __device__ __forceinline__ void jmg_couple(cx<T>* sh, const T* qm, const T* xe, const T* mudt_h, int tid,
-                                           int nthr) {
+                                           int* ctr) {
   constexpr int NRH = JmgShape<T, NR, JM>::NRH;
   constexpr int NT = (2 * JM + 1) * NRH;
-  for (int pass = 0; pass * nthr < NT; ++pass) {
-    const int t = zigzag_task<JmgShape<T, NR, JM>::threads>(pass, tid);
-    if (t >= NT) continue;
+  stage_tasks<JmgShape<T, NR, JM>::threads>(ctr, NT, tid, [&](int t) {
     const int u = t / NRH;
     const int rl = t - u * NRH;
     const int a = (u + 1) >> 1;
     const int mp = (u & 1) ? a : -a;
     jmg_couple_dispatch<T, NR, JM, JM>(a, sh, qm, xe, mp, mudt_h[rl], rl);
-  }
+  });
 }
 
 // The terms of the dipole vector at radial point rl from the basis states of
@@ -332,6 +360,9 @@ void mol_jmg_kernel(MolArgs a) {
   T* qm = dmt + S::n_pad;
   T* xe = qm + TB.n_q;
   double* red = reinterpret_cast<double*>(smem + TBL::bytes + S::rows_bytes + S::ph_bytes + S::mt_bytes);
+  // the stages' task counters live in the reduction area, which is used
+  // only after the last stage
+  int* ctr = reinterpret_cast<int*>(red);
 
   const int mol = blockIdx.x;
   const int tid = threadIdx.x;
@@ -464,12 +495,14 @@ void mol_jmg_kernel(MolArgs a) {
         vv[p] = phase_mul(vv[p], vph[voff + R2 * p]);
         slot[q + R2 * pp] = vv[p];
       }
+      // the previous round's stages ended at a barrier: reset their counters
+      if (kDynStages<nthr> && tid == 0) ctr[0] = ctr[1] = ctr[2] = 0;
       __syncthreads();
-      jmg_rotate<T, NR, JM, false>(sh, dmr, dmt, ph, tid, nthr);
+      jmg_rotate<T, NR, JM, false>(sh, dmr, dmt, ph, tid, ctr);
       __syncthreads();
-      jmg_couple<T, NR, JM>(sh, qm, xe, mudt + h * NRH, tid, nthr);
+      jmg_couple<T, NR, JM>(sh, qm, xe, mudt + h * NRH, tid, ctr + 1);
       __syncthreads();
-      jmg_rotate<T, NR, JM, true>(sh, dmr, dmt, ph, tid, nthr);
+      jmg_rotate<T, NR, JM, true>(sh, dmr, dmt, ph, tid, ctr + 2);
       __syncthreads();
 #pragma unroll
       for (int pp = 0; pp < PH; ++pp) {
