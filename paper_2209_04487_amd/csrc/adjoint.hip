@@ -26,12 +26,14 @@ namespace msqd {
 //   lambda_in = T^T R(-phi) Lambda -> B.
 // Returns this lane's share of dY/dE (zero for the forward).
 // A's rows are LSA elements apart (the LDS line stride, or N_r for chi in
-// device memory), B's LS.
-template <typename T, int NR, bool ADJ, int LSA>
+// device memory), B's LS.  KH: N_J <= kHalfKMaxNJ, two of the four K
+// instructions per product, rows as in the forward step (mf_row).
+template <typename T, int NR, bool ADJ, int LSA, bool KH>
 __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, int LS, int nj,
                                                     const T* __restrict__ frag, const T* __restrict__ x,
                                                     const T* __restrict__ mudt, T E) {
   typedef typename MfmaK4<T>::acc acc_t;
+  constexpr int NK = KH ? 2 : 4;
   const int lane = fresh_lane();
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int nwaves = (blockDim.x + 63) >> 6;
@@ -41,7 +43,7 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
   int rows[4], og[4], oe[4], oga[4], oea[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    rows[i] = MfmaK4<T>::row(grp, i);
+    rows[i] = i < NK ? mf_row<T, KH>(grp, i) : kMaxNJ;
     Tf[i] = frag[(0 * 64 + lane) * 4 + i];
     Tt[i] = frag[(1 * 64 + lane) * 4 + i];
     xk[i] = (rows[i] < nj) ? x[rows[i]] : T(0);
@@ -59,9 +61,9 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
   for (int tile = wave; tile * 16 < NR; tile += nwaves) {
     const int r = tile * 16 + col;
     // chi (and lambda_out) rows of this lane at radial point r
-    acc_t agr, agi, aer, aei, bgr, bgi, ber, bei;
+    acc_t agr = z, agi = z, aer = z, aei = z, bgr = z, bgi = z, ber = z, bei = z;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       const cx<T> g = A[oga[i] + r], e = A[oea[i] + r];
       agr[i] = g.x; agi[i] = g.y; aer[i] = e.x; aei[i] = e.y;
       if constexpr (ADJ) {
@@ -71,7 +73,7 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     }
     acc_t Pgr = z, Pgi = z, Per = z, Pei = z, Lgr = z, Lgi = z, Ler = z, Lei = z;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       Pgr = MfmaK4<T>::mma(Tf[i], agr[i], Pgr);
       Pgi = MfmaK4<T>::mma(Tf[i], agi[i], Pgi);
       Per = MfmaK4<T>::mma(Tf[i], aer[i], Per);
@@ -89,9 +91,9 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     T sn[4], vs[4];
     sin_vers_tile<NR>(md, xk, sn, vs);
     double gl = 0.0;
-    acc_t Ogr, Ogi, Oer, Oei;   // the operand of the T^T product
+    acc_t Ogr = z, Ogi = z, Oer = z, Oei = z;   // the operand of the T^T product
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       const T c = T(1) - vs[i];
       // Phi' = R(phi) Phi: [c Pg + i s Pe, i s Pg + c Pe]
       const T qgr = c * Pgr[i] - sn[i] * Pei[i], qgi = c * Pgi[i] + sn[i] * Per[i];
@@ -113,7 +115,7 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     if constexpr (ADJ) grad += static_cast<double>(mudt[r]) * gl;
     acc_t cgr = z, cgi = z, cer = z, cei = z;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       cgr = MfmaK4<T>::mma(Tt[i], Ogr[i], cgr);
       cgi = MfmaK4<T>::mma(Tt[i], Ogi[i], cgi);
       cer = MfmaK4<T>::mma(Tt[i], Oer[i], cer);
@@ -121,7 +123,7 @@ __device__ __forceinline__ double coupling_adj_mfma(const cx<T>* A, cx<T>* B, in
     }
     MfmaK4<T>::settle(cgr, cgi, cer, cei);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       if (rows[i] < nj) {
         B[og[i] + r] = {cgr[i], cgi[i]};
         B[oe[i] + r] = {cer[i], cei[i]};
@@ -224,7 +226,10 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
     __syncthreads();
   } else {
     __syncthreads();
-    coupling_adj_mfma<T, NR, false, LS>(A, B, LS, nj, frag, xk, mudt, E);
+    if (nj <= kHalfKMaxNJ)
+      coupling_adj_mfma<T, NR, false, LS, true>(A, B, LS, nj, frag, xk, mudt, E);
+    else
+      coupling_adj_mfma<T, NR, false, LS, false>(A, B, LS, nj, frag, xk, mudt, E);
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -274,10 +279,17 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   }
   __syncthreads();
   double grad;
-  if constexpr (CHI_DEV)
-    grad = coupling_adj_mfma<T, NR, true, NR>(chi_g, B, LS, nj, frag, xk, mudt, E);
-  else
-    grad = coupling_adj_mfma<T, NR, true, LS>(A, B, LS, nj, frag, xk, mudt, E);
+  if constexpr (CHI_DEV) {
+    if (nj <= kHalfKMaxNJ)
+      grad = coupling_adj_mfma<T, NR, true, NR, true>(chi_g, B, LS, nj, frag, xk, mudt, E);
+    else
+      grad = coupling_adj_mfma<T, NR, true, NR, false>(chi_g, B, LS, nj, frag, xk, mudt, E);
+  } else {
+    if (nj <= kHalfKMaxNJ)
+      grad = coupling_adj_mfma<T, NR, true, LS, true>(A, B, LS, nj, frag, xk, mudt, E);
+    else
+      grad = coupling_adj_mfma<T, NR, true, LS, false>(A, B, LS, nj, frag, xk, mudt, E);
+  }
   __syncthreads();
   if (active) {
 #pragma unroll

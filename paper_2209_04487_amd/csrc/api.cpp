@@ -494,16 +494,22 @@ int qd_init(const qd_desc* d, const double* U_g, const double* U_e, const double
     double* fd = reinterpret_cast<double*>(host.data() + L.tmfrag_d);
     float* ff = reinterpret_cast<float*>(host.data() + L.tmfrag_f);
     // lane l, element i owns row 4 (l/16) + i (FP32 instruction) or
-    // 4 i + l/16 (FP64 instruction) of the 16-row operand blocks
+    // 4 i + l/16 (FP64 instruction) of the 16-row operand blocks (entry()
+    // is zero for rows or columns >= nj, kMaxNJ included)
     auto entry = [&](int row, int k) { return (row < nj && k < nj) ? t.tm[static_cast<size_t>(row) * nj + k] : 0.0; };
+    // With nj <= kHalfKMaxNJ the FP32 blocks take the half-K order: operand
+    // position m = 4g + i holds row 2g + i for i < 2 and nothing otherwise,
+    // and element i of lane group g feeds row 2g + i (i < 2)
+    const bool half = nj <= kHalfKMaxNJ;
+    auto pos_row = [&](int m) { return half ? ((m & 3) < 2 ? 2 * (m >> 2) + (m & 3) : kMaxNJ) : m; };
     for (int lane = 0; lane < 64; ++lane)
       for (int i = 0; i < 4; ++i) {
         const int c = lane % 16, g = lane / 16;
-        const int kf = 4 * g + i, kd = 4 * i + g;
+        const int kf = half ? (i < 2 ? 2 * g + i : kMaxNJ) : 4 * g + i, kd = 4 * i + g;
         fd[(0 * 64 + lane) * 4 + i] = entry(c, kd);
         fd[(1 * 64 + lane) * 4 + i] = entry(kd, c);
-        ff[(0 * 64 + lane) * 4 + i] = static_cast<float>(entry(c, kf));
-        ff[(1 * 64 + lane) * 4 + i] = static_cast<float>(entry(kf, c));
+        ff[(0 * 64 + lane) * 4 + i] = static_cast<float>(entry(pos_row(c), kf));
+        ff[(1 * 64 + lane) * 4 + i] = static_cast<float>(entry(kf, pos_row(c)));
       }
   }
 

@@ -9,6 +9,13 @@ namespace msqd {
 
 constexpr int kMaxNJ = 16;
 
+// With N_J <= 8 the exact-form contractions (16x16x4 matrix-core products)
+// take two of the four K = 4 instructions: the J rows and angle nodes are
+// placed in the operand positions those two read (FP64: rows 0-7 already;
+// FP32: position 4g + i holds row 2g + i for i < 2, the FP32 fragment table
+// is built in that order), the other positions are zero.
+constexpr int kHalfKMaxNJ = 8;
+
 // Tables in the qd workspace.  All offsets are bytes from the start of ws,
 // each region 256-byte aligned.  The float64 tables feed the FP64 form, the
 // float32 ones the FP32 / mixed forms; the bf16 blocks are the J<->angle

@@ -554,15 +554,25 @@ struct MfmaK4<double> {
   }
 };
 
+// The J (or node) row fed by element i of lane group g: MfmaK4::row, or in
+// the half-K order (N_J <= kHalfKMaxNJ, elements i < 2 only) 2g + i in FP32
+// (whose fragment table is built in that order) and the same 4i + g in FP64.
+template <typename T, bool KH>
+__device__ __forceinline__ int mf_row(int g, int i) {
+  return (KH && sizeof(T) == 4) ? 2 * g + i : MfmaK4<T>::row(g, i);
+}
+
 // frag: [2][64 lanes][4]: block 0 A_i = T[l%16][row(l/16, i)], block 1 the
-// transpose T[row(l/16, i)][l%16]; zero outside nj.
-template <typename T, int NR>
+// transpose T[row(l/16, i)][l%16]; zero outside nj (in the half-K order for
+// FP32 when KH).  KH: N_J <= kHalfKMaxNJ, two of the four K instructions.
+template <typename T, int NR, bool KH>
 __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
                                                     const T* __restrict__ frag,
                                                     const T* __restrict__ x,
                                                     const T* __restrict__ mudt, T E) {
   typedef typename MfmaK4<T>::acc acc_t;
   constexpr int NRH = NR / fwd_split<NR, T>();
+  constexpr int NK = KH ? 2 : 4;
   const int lane = fresh_lane();
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int nwaves = (blockDim.x + 63) >> 6;
@@ -571,27 +581,28 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
   T A[4], At[4], xk[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int J = MfmaK4<T>::row(grp, i);
+    const int J = mf_row<T, KH>(grp, i);
     A[i] = frag[(0 * 64 + lane) * 4 + i];
     At[i] = frag[(1 * 64 + lane) * 4 + i];
-    xk[i] = (J < nj) ? x[J] : T(0);
+    xk[i] = (i < NK && J < nj) ? x[J] : T(0);
   }
-  // this lane's rows: 4 grp + i (FP32 instruction) or 4 i + grp (FP64)
-  const CpRows<NR, T> rows(nj, MfmaK4<T>::row(grp, 0), MfmaK4<T>::row(0, 1));
+  // this lane's rows: 4 grp + i (FP32 instruction) or 4 i + grp (FP64);
+  // 2 grp + i in the FP32 half-K order
+  const CpRows<NR, T> rows(nj, mf_row<T, KH>(grp, 0), mf_row<T, KH>(0, 1) - mf_row<T, KH>(0, 0));
 #pragma unroll 1
   for (int tile = wave; tile * 16 < NRH; tile += nwaves) {
     const int rl = tile * 16 + col;   // radial point within the round (LDS)
     const int r = r0 + rl;            // on the grid (tables)
-    acc_t cgr, cgi, cer, cei;
+    const acc_t z = {T(0), T(0), T(0), T(0)};
+    acc_t cgr = z, cgi = z, cer = z, cei = z;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       const cx<T> g = sh[rows.g[i] + rl], e = sh[rows.e[i] + rl];
       cgr[i] = g.x; cgi[i] = g.y; cer[i] = e.x; cei[i] = e.y;
     }
-    const acc_t z = {T(0), T(0), T(0), T(0)};
     acc_t Pgr = z, Pgi = z, Per = z, Pei = z;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       Pgr = MfmaK4<T>::mma(A[i], cgr[i], Pgr);
       Pgi = MfmaK4<T>::mma(A[i], cgi[i], Pgi);
       Per = MfmaK4<T>::mma(A[i], cer[i], Per);
@@ -602,7 +613,7 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     T sn[4], vs[4];
     sin_vers_tile<NR>(md, xk, sn, vs);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       const T gr = Pgr[i], gi = Pgi[i], er = Per[i], ei = Pei[i];
       Pgr[i] = -vs[i] * gr - sn[i] * ei;
       Pgi[i] = -vs[i] * gi + sn[i] * er;
@@ -610,7 +621,7 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
       Pei[i] = -vs[i] * ei + sn[i] * gr;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       cgr = MfmaK4<T>::mma(At[i], Pgr[i], cgr);
       cgi = MfmaK4<T>::mma(At[i], Pgi[i], cgi);
       cer = MfmaK4<T>::mma(At[i], Per[i], cer);
@@ -618,7 +629,7 @@ __device__ __forceinline__ void coupling_mfma_exact(cx<T>* sh, int nj, int r0,
     }
     MfmaK4<T>::settle(cgr, cgi, cer, cei);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NK; ++i) {
       T* og = reinterpret_cast<T*>(sh + rows.g[i] + rl);
       T* oe = reinterpret_cast<T*>(sh + rows.e[i] + rl);
       og[0] = cgr[i]; og[1] = cgi[i];
@@ -822,11 +833,18 @@ void mol_step_kernel(MolArgs a) {
         coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(frag_s),
                           reinterpret_cast<const float*>(x_s), tb.mudt, E);
       } else if constexpr (stage_tables<NR, T>()) {
-        coupling_mfma_exact<T, NR>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
-                                   reinterpret_cast<const T*>(x_s), tb.mudt, E);
+        if (nj <= kHalfKMaxNJ)
+          coupling_mfma_exact<T, NR, true>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
+                                           reinterpret_cast<const T*>(x_s), tb.mudt, E);
+        else
+          coupling_mfma_exact<T, NR, false>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
+                                            reinterpret_cast<const T*>(x_s), tb.mudt, E);
       } else {
         const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
-        coupling_mfma_exact<T, NR>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
+        if (nj <= kHalfKMaxNJ)
+          coupling_mfma_exact<T, NR, true>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
+        else
+          coupling_mfma_exact<T, NR, false>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
       }
       if constexpr (kPrioContraction<T, NR, CP>) __builtin_amdgcn_s_setprio(0);
       __syncthreads();
