@@ -141,7 +141,9 @@ constexpr bool adj_chi_in_device_memory(bool next) { return next && sizeof(T) ==
 // NEXT: the state after the step (psi^{n+1} = m psi_pre) is given, so the
 // recompute stops at chi = V K psi; otherwise the whole forward step is
 // recomputed to obtain psi_pre.
-template <typename T, int NR, bool NEXT>
+// KH: N_J <= kHalfKMaxNJ (two of the four K instructions per product),
+// chosen at launch so that a kernel holds one contraction path.
+template <typename T, int NR, bool NEXT, bool KH>
 __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   constexpr int R1 = FftShape<NR, T>::R1, R2 = FftShape<NR, T>::R2;
   constexpr int LS = line_stride<NR, T>();
@@ -226,10 +228,7 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
     __syncthreads();
   } else {
     __syncthreads();
-    if (nj <= kHalfKMaxNJ)
-      coupling_adj_mfma<T, NR, false, LS, true>(A, B, LS, nj, frag, xk, mudt, E);
-    else
-      coupling_adj_mfma<T, NR, false, LS, false>(A, B, LS, nj, frag, xk, mudt, E);
+    coupling_adj_mfma<T, NR, false, LS, KH>(A, B, LS, nj, frag, xk, mudt, E);
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -279,17 +278,10 @@ __global__ __launch_bounds__(512) void mol_adj_kernel(MolAdjArgs a) {
   }
   __syncthreads();
   double grad;
-  if constexpr (CHI_DEV) {
-    if (nj <= kHalfKMaxNJ)
-      grad = coupling_adj_mfma<T, NR, true, NR, true>(chi_g, B, LS, nj, frag, xk, mudt, E);
-    else
-      grad = coupling_adj_mfma<T, NR, true, NR, false>(chi_g, B, LS, nj, frag, xk, mudt, E);
-  } else {
-    if (nj <= kHalfKMaxNJ)
-      grad = coupling_adj_mfma<T, NR, true, LS, true>(A, B, LS, nj, frag, xk, mudt, E);
-    else
-      grad = coupling_adj_mfma<T, NR, true, LS, false>(A, B, LS, nj, frag, xk, mudt, E);
-  }
+  if constexpr (CHI_DEV)
+    grad = coupling_adj_mfma<T, NR, true, NR, KH>(chi_g, B, LS, nj, frag, xk, mudt, E);
+  else
+    grad = coupling_adj_mfma<T, NR, true, LS, KH>(A, B, LS, nj, frag, xk, mudt, E);
   __syncthreads();
   if (active) {
 #pragma unroll
@@ -316,7 +308,7 @@ static size_t adj_lds_bytes(int n_r, int nj, bool f32, bool next) {
 }
 size_t mol_adj_lds_bytes(int n_r, int nj, bool f32) { return adj_lds_bytes(n_r, nj, f32, false); }
 
-template <typename T, int NR, bool NEXT>
+template <typename T, int NR, bool NEXT, bool KH>
 static int launch_mol_adj_n(const MolAdjArgs& a, hipStream_t s) {
   constexpr int R2 = FftShape<NR, T>::R2;
   const int L = 2 * a.nj;
@@ -325,16 +317,18 @@ static int launch_mol_adj_n(const MolAdjArgs& a, hipStream_t s) {
   const size_t shm = adj_lds_bytes(NR, a.nj, sizeof(T) == 4, NEXT);
   static std::atomic<unsigned long long> lds_set{0};
   if (shm > 64 * 1024) {
-    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR, NEXT>), lds_set);
+    const hipError_t e = allow_large_lds(reinterpret_cast<const void*>(&mol_adj_kernel<T, NR, NEXT, KH>), lds_set);
     if (e != hipSuccess) return static_cast<int>(e);
   }
-  hipLaunchKernelGGL((mol_adj_kernel<T, NR, NEXT>), dim3(a.n_mol), dim3(threads), shm, s, a);
+  hipLaunchKernelGGL((mol_adj_kernel<T, NR, NEXT, KH>), dim3(a.n_mol), dim3(threads), shm, s, a);
   return static_cast<int>(hipGetLastError());
 }
 
 template <typename T, int NR>
 static int launch_mol_adj_t(const MolAdjArgs& a, hipStream_t s) {
-  return a.psi_np1 ? launch_mol_adj_n<T, NR, true>(a, s) : launch_mol_adj_n<T, NR, false>(a, s);
+  if (a.nj <= kHalfKMaxNJ)
+    return a.psi_np1 ? launch_mol_adj_n<T, NR, true, true>(a, s) : launch_mol_adj_n<T, NR, false, true>(a, s);
+  return a.psi_np1 ? launch_mol_adj_n<T, NR, true, false>(a, s) : launch_mol_adj_n<T, NR, false, false>(a, s);
 }
 
 int launch_mol_adj(const MolAdjArgs& a, int n_r, bool f32, hipStream_t s) {

@@ -698,7 +698,10 @@ struct MolOcc { static constexpr int waves = sizeof(T) == 8 ? 2 : (NR <= 128 ? 4
 
 // coupling path: BF16 hi/lo split on 16x16x16 (mixed form) or the
 // working precision on 16x16x4 (FP32 and FP64 forms)
-enum { kCpExact = 0, kCpBf16x3 = 1 };
+// (kCpExactHalf: the working precision with N_J <= kHalfKMaxNJ, two of the
+// four K instructions; a launch picks it from N_J, so that a kernel holds
+// one contraction path)
+enum { kCpExact = 0, kCpBf16x3 = 1, kCpExactHalf = 2 };
 
 // raised wave priority over the contraction rounds (see the step loop)
 template <typename T, int NR, int CP>
@@ -833,18 +836,11 @@ void mol_step_kernel(MolArgs a) {
         coupling_mfma<NR>(sh, nj, h * NRH, reinterpret_cast<const unsigned short*>(frag_s),
                           reinterpret_cast<const float*>(x_s), tb.mudt, E);
       } else if constexpr (stage_tables<NR, T>()) {
-        if (nj <= kHalfKMaxNJ)
-          coupling_mfma_exact<T, NR, true>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
-                                           reinterpret_cast<const T*>(x_s), tb.mudt, E);
-        else
-          coupling_mfma_exact<T, NR, false>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
-                                            reinterpret_cast<const T*>(x_s), tb.mudt, E);
+        coupling_mfma_exact<T, NR, CP == kCpExactHalf>(sh, nj, h * NRH, reinterpret_cast<const T*>(frag_s),
+                                                       reinterpret_cast<const T*>(x_s), tb.mudt, E);
       } else {
         const T* frag = reinterpret_cast<const T*>(ws + (sizeof(T) == 8 ? a.lay.tmfrag_d : a.lay.tmfrag_f));
-        if (nj <= kHalfKMaxNJ)
-          coupling_mfma_exact<T, NR, true>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
-        else
-          coupling_mfma_exact<T, NR, false>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
+        coupling_mfma_exact<T, NR, CP == kCpExactHalf>(sh, nj, h * NRH, frag, tb.x, tb.mudt, E);
       }
       if constexpr (kPrioContraction<T, NR, CP>) __builtin_amdgcn_s_setprio(0);
       __syncthreads();
@@ -953,6 +949,9 @@ int launch_mol_t1(const MolArgs& a, hipStream_t s) {
 // 4% faster); the FP64 form measured no gain from it
 template <typename T, int NR, int CP>
 int launch_mol_t(const MolArgs& a, hipStream_t s) {
+  if constexpr (CP == kCpExact) {
+    if (a.nj <= kHalfKMaxNJ) return launch_mol_t<T, NR, kCpExactHalf>(a, s);
+  }
   if constexpr (sizeof(T) == 4) {
     if (a.n_steps == 1) return launch_mol_t1<T, NR, CP, true>(a, s);
   }
