@@ -31,7 +31,8 @@ class CoupledYield(torch.autograd.Function):
         kn = knots.detach().cpu().numpy().astype(np.float64)
         w = float(omega.detach().cpu())
         src = source_values(cfg, 0, n_steps, knots=kn, omega=w)
-        sysm = msqd.Coupled(cfg, prec=prec, mol_every=mol_every)
+        # no monitor: the objective does not involve the transmitted flux
+        sysm = msqd.Coupled(cfg, prec=prec, mol_every=mol_every, n_freq=0)
         hist = _history_buffers(sysm, K, n_steps)
         ckpts = []
         slot_of = []
@@ -91,7 +92,8 @@ def _history_buffers(sysm, K, n_steps):
 
 def _segment_history(sysm, src, s0, s1, psi_all, e_all):
     """Advance sysm over steps s0..s1-1 from its current state, keeping the
-    segment's wavepackets and gathered fields: slot 0 is the state at s0, and
+    segment's wavepackets and the fields gathered at its molecular steps
+    (e_all[t - s0]; sysm.E_mol is not updated): slot 0 is the state at s0, and
     each step that moves the molecules reads its slot and writes the next one
     (coupled_step's out-of-place form), so no step copies a state.  Returns
     the slot holding the state before each step, and the slot of the final
@@ -104,11 +106,12 @@ def _segment_history(sysm, src, s0, s1, psi_all, e_all):
     for t in range(s0, s1):
         slot_of.append(cur)
         if t % M == 0 and n_mol > 0:
-            sysm.step_out_of_place(src[t], psi_all[cur], psi_all[t - s0 + 1])
+            # the gathered field straight into its history slot (the reverse
+            # sweep reads it at these steps only)
+            sysm.step_out_of_place(src[t], psi_all[cur], psi_all[t - s0 + 1], E_out=e_all[t - s0])
             cur = t - s0 + 1
         else:
             sysm.step(src[t:t + 1])
-        e_all[t - s0].copy_(sysm.E_mol)
     return slot_of, cur
 
 

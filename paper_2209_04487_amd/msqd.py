@@ -556,18 +556,23 @@ class Coupled:
         coupled_step(self.desc, self.state, src_values, self.n)
         self.n += len(src_values)
 
-    def step_out_of_place(self, src_value, psi_in, psi_out):
+    def step_out_of_place(self, src_value, psi_in, psi_out, E_out=None):
         """One coupled step whose molecules read psi_in and write the stepped
         wavepackets to psi_out (coupled_step's psi_next); the fields, the
-        absorbed norms and the polarisation advance as in step()."""
+        absorbed norms and the polarisation advance as in step().  E_out:
+        where the molecular step records the field it gathered (float64
+        [n_mol]) instead of self.E_mol."""
         src_values = np.atleast_1d(np.asarray(src_value, np.float64))
         self.state.psi = C.c_void_p(psi_in.data_ptr())
         self.state.psi_next = C.c_void_p(psi_out.data_ptr())
+        if E_out is not None:
+            self.state.E_mol = C.c_void_p(E_out.data_ptr())
         try:
             coupled_step(self.desc, self.state, src_values, self.n)
         finally:
             self.state.psi = C.c_void_p(self.mol.psi.data_ptr())
             self.state.psi_next = None
+            self.state.E_mol = C.c_void_p(self.E_mol.data_ptr())
         self.n += 1
 
     # -------------------------------------------------- checkpoint / restore
