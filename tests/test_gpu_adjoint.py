@@ -25,8 +25,8 @@ from workloads.pulses import knot_values, source_values
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(n_steps=120):
-    return get_config("cfg0", n_r=128, j_max=6, pulse="knots", n_knots=64, knot_seed=4,
+def _cfg(n_steps=120, j_max=6):
+    return get_config("cfg0", n_r=128, j_max=j_max, pulse="knots", n_knots=64, knot_seed=4,
                       n_steps=n_steps, omega_h=0.10, ckpt_every=40)
 
 
@@ -62,15 +62,17 @@ def _dot_state(sysm, vec):
     return s
 
 
-@pytest.mark.parametrize("next_state", [False, True])
-def test_adjoint_step_dot_product_fp64(next_state):
+@pytest.mark.parametrize("next_state,j_max", [(False, 6), (True, 6), (True, 10)])
+def test_adjoint_step_dot_product_fp64(next_state, j_max):
     """With next_state the forward step is taken out of place (coupled_step's
     psi_next), which must equal the in-place step bit for bit and leave its
     input untouched, and the reverse step reads the state after the step
-    (adjoint_step's psi_np1) instead of recomputing it."""
+    (adjoint_step's psi_np1) instead of recomputing it.  j_max = 6 (N_J = 7)
+    takes the half-K contractions, j_max = 10 all four K instructions."""
     from paper_2209_04487_amd import msqd
-    cfg = _cfg()
-    banner(f"adjoint step dot product fp64, state after the step {'given' if next_state else 'recomputed'}")
+    cfg = _cfg(j_max=j_max)
+    banner(f"adjoint step dot product fp64, j_max {j_max}, state after the step "
+           f"{'given' if next_state else 'recomputed'}")
     mat = _mat_with_metal(cfg)
     kn = knot_values(cfg) * 30.0
     src = source_values(cfg, 0, 60, knots=kn)

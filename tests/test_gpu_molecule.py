@@ -40,6 +40,12 @@ CASES = [
     ("mixed", 128, 0, 3, 1),
     ("fp32", 256, 2, 3, 1),
     ("fp64", 128, 2, 3, 1),
+    # either side of N_J = 8, where the exact forms switch from two of the
+    # four K = 4 matrix-core instructions (half-K order) to all four
+    ("fp32", 128, 7, 3, 1),
+    ("fp64", 128, 7, 3, 2),
+    ("fp32", 128, 8, 3, 1),
+    ("fp64", 128, 8, 3, 1),
 ]
 
 
