@@ -27,9 +27,6 @@ struct FdAdjArgs {
   void* scratch;           // 6 x n cells, field element type
 };
 int launch_yee_e_adj(const FdAdjArgs& a, bool f32, hipStream_t s);
-int launch_yee_h_adj(const FdAdjArgs& a, bool f32, hipStream_t s);
-// g = (2/(eta0 dx)) sum over the source plane of ce[mat] lambda_Ex
-int launch_src_grad(const FdArgs& lam, double coef, double* g_out, bool f32, hipStream_t s);
 
 struct CplAdjArgs {
   int n_occ;
@@ -51,8 +48,14 @@ struct CplAdjArgs {
   int update;
   double inv_mdt;
 };
-int launch_deposit_adj(const CplAdjArgs& a, bool f32, hipStream_t s);
-int launch_gather_adj(const CplAdjArgs& a, bool f32, hipStream_t s);
+// One launch: g = (2/(eta0 dx)) sum over the source plane of ce[mat]
+// lambda_Ex, and the deposit's adjoint over dep.n_occ occupied cells (none
+// when dep.n_occ is 0).  Both read lambda_Ex before the E update's adjoint.
+int launch_src_grad_deposit_adj(const FdArgs& lam, double coef, double* g_out, const CplAdjArgs& dep, bool f32,
+                                hipStream_t s);
+// The H update's adjoint; the gather's adjoint over gat.n_occ occupied cells
+// (none when 0) rides in its first launch, which touches no lambda_E.
+int launch_yee_h_adj(const FdAdjArgs& a, const CplAdjArgs& gat, bool f32, hipStream_t s);
 
 // lambda_psi = scale * 2 dr psi for r > r_diss, else 0; labs = scale
 int launch_yield_adj_init(void* lpsi, double* labs, const void* psi, int n_mol, int lines, int n_r,

@@ -471,9 +471,20 @@ __global__ __launch_bounds__(256) void yee_e_adj_k2(FdAdjArgs aa) {
   f.Hx[idx] += (b_xz[idx] - xz_up + b_xy[idx] - b_xy[jp]) * inv_dx;
 }
 
-// H update, first half: difference adjoints a_* and the CPML auxiliaries.
 template <typename T>
-__global__ __launch_bounds__(256) void yee_h_adj_k1(FdAdjArgs aa) {
+__device__ __forceinline__ void gather_adj_cell(const CplAdjArgs& a, int c);
+
+// H update, first half: difference adjoints a_* and the CPML auxiliaries.
+// The blocks from cell_blocks on take the gather's adjoint, one occupied
+// cell per thread: it adds to lambda_Ex, which this half neither reads nor
+// writes, and the second half adds to lambda_E after it as before.
+template <typename T>
+__global__ __launch_bounds__(256) void yee_h_adj_k1(FdAdjArgs aa, CplAdjArgs gat, int cell_blocks) {
+  if (static_cast<int>(blockIdx.x) >= cell_blocks) {
+    const int c = (static_cast<int>(blockIdx.x) - cell_blocks) * 256 + static_cast<int>(threadIdx.x);
+    if (c < gat.n_occ) gather_adj_cell<T>(gat, c);
+    return;
+  }
   const FdArgs& a = aa.f;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long n = static_cast<long>(nx) * ny * nz;
@@ -563,14 +574,15 @@ int launch_yee_e_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
   return static_cast<int>(hipGetLastError());
 }
 
-int launch_yee_h_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
+int launch_yee_h_adj(const FdAdjArgs& a, const CplAdjArgs& gat, bool f32, hipStream_t s) {
   const long n = static_cast<long>(a.f.nx) * a.f.ny * a.f.nz;
   const int blocks = static_cast<int>((n + 255) / 256);
+  const int gblocks = gat.n_occ > 0 ? (gat.n_occ + 255) / 256 : 0;
   if (f32) {
-    hipLaunchKernelGGL(yee_h_adj_k1<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_adj_k1<float>, dim3(blocks + gblocks), dim3(256), 0, s, a, gat, blocks);
     hipLaunchKernelGGL(yee_h_adj_k2<float>, dim3(blocks), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(yee_h_adj_k1<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(yee_h_adj_k1<double>, dim3(blocks + gblocks), dim3(256), 0, s, a, gat, blocks);
     hipLaunchKernelGGL(yee_h_adj_k2<double>, dim3(blocks), dim3(256), 0, s, a);
   }
   return static_cast<int>(hipGetLastError());
@@ -582,7 +594,7 @@ int launch_yee_h_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
 constexpr int kSrcGradThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kSrcGradThreads) void src_grad_kernel(FdArgs a, double coef, double* g_out) {
+__device__ __forceinline__ void src_grad_block(const FdArgs& a, double coef, double* g_out) {
   __shared__ double red[kSrcGradThreads];
   const long plane = static_cast<long>(a.nx) * a.ny;
   const long o = static_cast<long>(a.src_k) * plane;
@@ -603,20 +615,10 @@ __global__ __launch_bounds__(kSrcGradThreads) void src_grad_kernel(FdArgs a, dou
   if (threadIdx.x == 0) g_out[0] = coef * red[0];
 }
 
-int launch_src_grad(const FdArgs& lam, double coef, double* g_out, bool f32, hipStream_t s) {
-  if (f32)
-    hipLaunchKernelGGL(src_grad_kernel<float>, dim3(1), dim3(kSrcGradThreads), 0, s, lam, coef, g_out);
-  else
-    hipLaunchKernelGGL(src_grad_kernel<double>, dim3(1), dim3(kSrcGradThreads), 0, s, lam, coef, g_out);
-  return static_cast<int>(hipGetLastError());
-}
-
 // -------------------------------------------------------------- coupling
 // Forward: E_x[cell] -= ce (P' - P)/dt with P' = pfac sum_i d_i.
 template <typename T>
-__global__ __launch_bounds__(256) void deposit_adj_kernel(CplAdjArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_occ) return;
+__device__ __forceinline__ void deposit_adj_cell(const CplAdjArgs& a, int c) {
   const int cell = a.occ_cell[c];
   const double ce = a.ce[a.mat[cell] & 3];
   const double lex = static_cast<double>(static_cast<const T*>(a.lEx)[cell]);
@@ -645,9 +647,7 @@ __global__ __launch_bounds__(256) void deposit_adj_kernel(CplAdjArgs a) {
 
 // Forward: E_mol,i = E_x[cell(i)] / E_au.
 template <typename T>
-__global__ __launch_bounds__(256) void gather_adj_kernel(CplAdjArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_occ) return;
+__device__ __forceinline__ void gather_adj_cell(const CplAdjArgs& a, int c) {
   double s = 0.0;
   for (int t = a.occ_ptr[c]; t < a.occ_ptr[c + 1]; ++t) s += a.lE[a.mol_perm[t]];
   T* lEx = static_cast<T*>(a.lEx);
@@ -655,23 +655,29 @@ __global__ __launch_bounds__(256) void gather_adj_kernel(CplAdjArgs a) {
   lEx[cell] = lEx[cell] + static_cast<T>(s * a.inv_eau);
 }
 
-int launch_deposit_adj(const CplAdjArgs& a, bool f32, hipStream_t s) {
-  if (a.n_occ <= 0) return 0;
-  const int blocks = (a.n_occ + 255) / 256;
-  if (f32)
-    hipLaunchKernelGGL(deposit_adj_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(deposit_adj_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
-  return static_cast<int>(hipGetLastError());
+// Block 0 forms the source gradient, the blocks after it take the deposit's
+// adjoint, one occupied cell per thread: both read lambda_Ex as the E
+// update's adjoint left it and write disjoint outputs.
+template <typename T>
+__global__ __launch_bounds__(kSrcGradThreads) void src_grad_deposit_adj_kernel(FdArgs f, double coef, double* g_out,
+                                                                             CplAdjArgs dep) {
+  if (blockIdx.x == 0) {
+    src_grad_block<T>(f, coef, g_out);
+    return;
+  }
+  const int c = (static_cast<int>(blockIdx.x) - 1) * kSrcGradThreads + static_cast<int>(threadIdx.x);
+  if (c < dep.n_occ) deposit_adj_cell<T>(dep, c);
 }
 
-int launch_gather_adj(const CplAdjArgs& a, bool f32, hipStream_t s) {
-  if (a.n_occ <= 0) return 0;
-  const int blocks = (a.n_occ + 255) / 256;
+int launch_src_grad_deposit_adj(const FdArgs& lam, double coef, double* g_out, const CplAdjArgs& dep, bool f32,
+                                hipStream_t s) {
+  const int blocks = 1 + (dep.n_occ > 0 ? (dep.n_occ + kSrcGradThreads - 1) / kSrcGradThreads : 0);
   if (f32)
-    hipLaunchKernelGGL(gather_adj_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(src_grad_deposit_adj_kernel<float>, dim3(blocks), dim3(kSrcGradThreads), 0, s, lam, coef,
+                       g_out, dep);
   else
-    hipLaunchKernelGGL(gather_adj_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(src_grad_deposit_adj_kernel<double>, dim3(blocks), dim3(kSrcGradThreads), 0, s, lam, coef,
+                       g_out, dep);
   return static_cast<int>(hipGetLastError());
 }
 

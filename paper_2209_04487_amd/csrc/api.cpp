@@ -1277,13 +1277,13 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, void
   ca.lJ = M > 1 ? adj->lJ : nullptr;
   ca.update = update ? 1 : 0;
   ca.inv_mdt = 1.0 / (M * d->fd.dt);
-  // reverse order of the forward step: deposit, E update, molecules, gather, H update
-  int e = launch_src_grad(lam, 2.0 / (kEta0 * d->fd.dx), g_src, f32, s);
-  if (e) return check_hip(static_cast<hipError_t>(e), "source gradient launch");
-  if (d->qd.n_mol > 0 && d->n_occ > 0) {
-    e = launch_deposit_adj(ca, f32, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "deposit adjoint launch");
-  }
+  // reverse order of the forward step: deposit, E update, molecules, gather,
+  // H update; the source gradient shares the deposit's launch and the gather
+  // the H update's first one
+  CplAdjArgs dep = ca;
+  if (d->qd.n_mol <= 0) dep.n_occ = 0;
+  int e = launch_src_grad_deposit_adj(lam, 2.0 / (kEta0 * d->fd.dx), g_src, dep, f32, s);
+  if (e) return check_hip(static_cast<hipError_t>(e), "source gradient and deposit adjoint launch");
   e = launch_yee_e_adj(fa, f32, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "E adjoint launch");
   if (d->qd.n_mol > 0 && update) {
@@ -1308,10 +1308,10 @@ int adjoint_step(const cpl_desc* d, const cpl_state* st, const void* psi_n, void
     ma.lay = m.lay;
     e = launch_mol_adj(ma, d->qd.n_r, f32, s);
     if (e) return check_hip(static_cast<hipError_t>(e), "molecular adjoint launch");
-    e = launch_gather_adj(ca, f32, s);
-    if (e) return check_hip(static_cast<hipError_t>(e), "gather adjoint launch");
   }
-  e = launch_yee_h_adj(fa, f32, s);
+  CplAdjArgs gat = ca;
+  if (!(d->qd.n_mol > 0 && update)) gat.n_occ = 0;
+  e = launch_yee_h_adj(fa, gat, f32, s);
   if (e) return check_hip(static_cast<hipError_t>(e), "H adjoint launch");
   return MSQD_OK;
 }
