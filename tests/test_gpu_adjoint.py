@@ -62,21 +62,29 @@ def _dot_state(sysm, vec):
     return s
 
 
-@pytest.mark.parametrize("next_state,j_max", [(False, 6), (True, 6), (True, 10)])
-def test_adjoint_step_dot_product_fp64(next_state, j_max):
+@pytest.mark.parametrize("next_state,j_max,n_mol", [(False, 6, None), (True, 6, None), (True, 10, None),
+                                                    (False, 6, 0)])
+def test_adjoint_step_dot_product_fp64(next_state, j_max, n_mol):
     """With next_state the forward step is taken out of place (coupled_step's
     psi_next), which must equal the in-place step bit for bit and leave its
     input untouched, and the reverse step reads the state after the step
     (adjoint_step's psi_np1) instead of recomputing it.  j_max = 6 (N_J = 7)
-    takes the half-K contractions, j_max = 10 all four K instructions."""
+    takes the half-K contractions, j_max = 10 all four K instructions.
+    n_mol = 0: the fields alone (the source gradient's launch without the
+    deposit's transpose, the H transpose without the gather's)."""
     from paper_2209_04487_amd import msqd
     cfg = _cfg(j_max=j_max)
-    banner(f"adjoint step dot product fp64, j_max {j_max}, state after the step "
+    if n_mol is not None:
+        cfg = cfg.replace(n_mol=n_mol)
+    banner(f"adjoint step dot product fp64, j_max {j_max}, {cfg.n_mol} molecules, state after the step "
            f"{'given' if next_state else 'recomputed'}")
     mat = _mat_with_metal(cfg)
     kn = knot_values(cfg) * 30.0
     src = source_values(cfg, 0, 60, knots=kn)
-    sysm = msqd.Coupled(cfg, prec="fp64", mat=mat)
+    sysm = msqd.Coupled(cfg, prec="fp64", mat=mat,
+                        cells=np.zeros(0, np.int32) if cfg.n_mol == 0 else None)
+    if cfg.n_mol == 0:
+        assert sysm.desc.n_occ == 0
     sysm.step(src[:40])
     x = sysm.snapshot()
     gen = torch.Generator(device="cpu").manual_seed(0)
@@ -135,7 +143,7 @@ def test_adjoint_step_dot_product_fp64(next_state, j_max):
     for k in STATE:
         buf[k].copy_(lam[k])
     buf["lpsi"].copy_(lam["mol_psi"])
-    buf["labs"].copy_(lam["absorbed"])
+    buf["labs"][: lam["absorbed"].numel()].copy_(lam["absorbed"])
     buf["lP"][: lam["P_c"].numel()].copy_(lam["P_c"])
     g = torch.zeros(1, dtype=torch.float64, device="cuda")
     msqd.adjoint_step(sysm.desc, sysm.state, psi_n, e_n, adj, 40, g, psi_np1=psi_np1)
@@ -144,7 +152,7 @@ def test_adjoint_step_dot_product_fp64(next_state, j_max):
     for k in STATE:
         jtl += float((buf[k] * delta[k]).sum())
     jtl += float((torch.conj(buf["lpsi"]) * delta["mol_psi"]).real.sum())
-    jtl += float((buf["labs"] * delta["absorbed"]).sum())
+    jtl += float((buf["labs"][: lam["absorbed"].numel()] * delta["absorbed"]).sum())
     jtl += float((buf["lP"][: lam["P_c"].numel()] * delta["P_c"]).sum())
     jtl += float(g[0]) * ds
     assert abs(jv - jtl) <= 1e-7 * max(abs(jv), abs(jtl)), (jv, jtl)
