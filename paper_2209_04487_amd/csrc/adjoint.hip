@@ -394,17 +394,37 @@ __global__ __launch_bounds__(256) void yee_e_adj_k1(FdAdjArgs aa) {
   T* sc = static_cast<T*>(aa.scratch);
   T* E[3] = {f.Ex, f.Ey, f.Ez};
   T* JD[3] = {f.JDx, f.JDy, f.JDz};
+  // every load of the cell before its first store: the arrays are distinct,
+  // and with the stores in between each load would wait on the one before
+  int m[3];
+  T le[3], jd[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    m[c] = a.mat[c * n + idx];
+    le[c] = E[c][idx];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) jd[c] = (m[c] == a.metal_id) ? JD[c][idx] : T(0);
+  const int kk = pml_plane_a(k, nz, a.npml);
+  const long plane = static_cast<long>(nx) * ny;
+  const long np = 2L * a.npml * plane;
+  const long o = kk * plane + (idx - static_cast<long>(k) * plane);
+  T* psiEx = f.psi;
+  T* psiEy = f.psi + np;
+  T pex = T(0), pey = T(0);
+  if (kk >= 0) {
+    pex = psiEx[o];
+    pey = psiEy[o];
+  }
   T lcurl[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const int m = a.mat[c * n + idx];
-    T le = E[c][idx];
-    if (c < 2 && k == 0) le = T(0);  // those components are held at zero
-    const T ce = static_cast<T>(a.ce[m & 3]);
-    lcurl[c] = ce * le;
-    T lE = le;
-    if (m == a.metal_id) {
-      const T ljd = JD[c][idx] - ce * le;
+    if (c < 2 && k == 0) le[c] = T(0);  // those components are held at zero
+    const T ce = static_cast<T>(a.ce[m[c] & 3]);
+    lcurl[c] = ce * le[c];
+    T lE = le[c];
+    if (m[c] == a.metal_id) {
+      const T ljd = jd[c] - ce * le[c];
       JD[c][idx] = static_cast<T>(a.alpha_d) * ljd;
       lE += static_cast<T>(a.beta_d) * ljd;
     }
@@ -413,22 +433,18 @@ __global__ __launch_bounds__(256) void yee_e_adj_k1(FdAdjArgs aa) {
   // curl_x = dHz_dy - dHy_dz~, curl_y = dHx_dz~ - dHz_dx, curl_z = dHy_dx - dHx_dy
   T b_zy = lcurl[0], b_yz = -lcurl[0], b_xz = lcurl[1], b_zx = -lcurl[1];
   const T b_yx = lcurl[2], b_xy = -lcurl[2];
-  const int kk = pml_plane_a(k, nz, a.npml);
   if (kk >= 0) {
     const T b = prof_a<T>(a, a.lay.bE, a.lay.bEf)[k];
     const T c = prof_a<T>(a, a.lay.aE, a.lay.aEf)[k];
     const T ki = prof_a<T>(a, a.lay.kE, a.lay.kEf)[k];
-    const long plane = static_cast<long>(nx) * ny;
-    const long np = 2L * a.npml * plane;
-    const long o = kk * plane + (idx - static_cast<long>(k) * plane);
-    T* psiEx = f.psi;
-    T* psiEy = f.psi + np;
-    const T tx = psiEx[o] + b_yz;   // adjoint of psi_Ex' (total)
-    const T ty = psiEy[o] + b_xz;
+    const T tx = pex + b_yz;   // adjoint of psi_Ex' (total)
+    const T ty = pey + b_xz;
     psiEx[o] = b * tx;
     psiEy[o] = b * ty;
-    b_yz = ki * b_yz + c * tx;
-    b_xz = ki * b_xz + c * ty;
+    // ki b + c t with the fused product stated: left to the compiler, which
+    // of the two it fuses follows the order of the code around it
+    b_yz = fma_t(c, tx, ki * b_yz);
+    b_xz = fma_t(ki, b_xz, c * ty);
   }
   sc[0 * n + idx] = b_zy;
   sc[1 * n + idx] = b_zx;
@@ -462,13 +478,18 @@ __global__ __launch_bounds__(256) void yee_e_adj_k2(FdAdjArgs aa) {
   const T* b_xz = sc + 3 * n;
   const T* b_yx = sc + 4 * n;
   const T* b_xy = sc + 5 * n;
+  // every load before the first store (see yee_e_adj_k1)
+  const T hz = f.Hz[idx], hy = f.Hy[idx], hx = f.Hx[idx];
   // dHz_dy(c) = Hz[c] - Hz[c - y]; dHz_dx(c) = Hz[c] - Hz[c - x]
-  f.Hz[idx] += (b_zy[idx] - b_zy[jp] + b_zx[idx] - b_zx[ip]) * inv_dx;
+  const T dz = (b_zy[idx] - b_zy[jp] + b_zx[idx] - b_zx[ip]) * inv_dx;
   // dHy_dz(c) = Hy[c] - Hy[c - z] (Hy below k = 0 is zero); dHy_dx(c) = Hy[c] - Hy[c - x]
   const T yz_up = (k + 1 < nz) ? b_yz[idx + sz] : T(0);
-  f.Hy[idx] += (b_yz[idx] - yz_up + b_yx[idx] - b_yx[ip]) * inv_dx;
+  const T dy = (b_yz[idx] - yz_up + b_yx[idx] - b_yx[ip]) * inv_dx;
   const T xz_up = (k + 1 < nz) ? b_xz[idx + sz] : T(0);
-  f.Hx[idx] += (b_xz[idx] - xz_up + b_xy[idx] - b_xy[jp]) * inv_dx;
+  const T dx = (b_xz[idx] - xz_up + b_xy[idx] - b_xy[jp]) * inv_dx;
+  f.Hz[idx] = hz + dz;
+  f.Hy[idx] = hy + dy;
+  f.Hx[idx] = hx + dx;
 }
 
 template <typename T>
@@ -552,13 +573,18 @@ __global__ __launch_bounds__(256) void yee_h_adj_k2(FdAdjArgs aa) {
   const T* a_xz = sc + 3 * n;
   const T* a_yx = sc + 4 * n;
   const T* a_xy = sc + 5 * n;
+  // every load before the first store (see yee_e_adj_k1)
+  const T ez = f.Ez[idx], ey = f.Ey[idx], ex = f.Ex[idx];
   // dEz_dy(c) = Ez[c + y] - Ez[c]; dEz_dx(c) = Ez[c + x] - Ez[c]
-  f.Ez[idx] += (a_zy[jm] - a_zy[idx] + a_zx[im] - a_zx[idx]) * inv_dx;
+  const T dz = (a_zy[jm] - a_zy[idx] + a_zx[im] - a_zx[idx]) * inv_dx;
   // dEy_dz(c) = Ey[c + z] - Ey[c] (Ey above the top is zero); dEy_dx(c) = Ey[c + x] - Ey[c]
   const T yz_dn = (k > 0) ? a_yz[idx - sz] : T(0);
-  f.Ey[idx] += (yz_dn - a_yz[idx] + a_yx[im] - a_yx[idx]) * inv_dx;
+  const T dy = (yz_dn - a_yz[idx] + a_yx[im] - a_yx[idx]) * inv_dx;
   const T xz_dn = (k > 0) ? a_xz[idx - sz] : T(0);
-  f.Ex[idx] += (xz_dn - a_xz[idx] + a_xy[jm] - a_xy[idx]) * inv_dx;
+  const T dx = (xz_dn - a_xz[idx] + a_xy[jm] - a_xy[idx]) * inv_dx;
+  f.Ez[idx] = ez + dz;
+  f.Ey[idx] = ey + dy;
+  f.Ex[idx] = ex + dx;
 }
 
 int launch_yee_e_adj(const FdAdjArgs& a, bool f32, hipStream_t s) {
