@@ -456,20 +456,34 @@ __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
   const int nc = a.ncomp;
   const int cell = a.occ_cell[c];
   void* fld[3] = {a.Ex, a.Ey, a.Ez};
-  for (int k = 0; k < nc; ++k) {
+  // the cell's loads before its first store: the material bytes may alias
+  // any array, so a load after a store would wait on it
+  int mk[3];
+  double pj[3];   // P_c before the update, or the held J_mol
+  T e_old[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= nc) break;
+    mk[k] = a.mat[static_cast<size_t>(k) * a.ncells + cell] & 3;
+    pj[k] = a.update ? a.P_c[static_cast<size_t>(c) * nc + k] : a.J_mol[static_cast<size_t>(c) * nc + k];
+    e_old[k] = a.held ? T(0) : static_cast<const T*>(fld[k])[cell];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= nc) break;
     double J;
     if (a.update) {
       double s = 0.0;
       const int b = a.occ_ptr[c], e = a.occ_ptr[c + 1];
       for (int t = b; t < e; ++t) s += a.d_mol[static_cast<size_t>(a.mol_perm[t]) * nc + k];
       const double p_new = s * a.pfac;
-      J = (p_new - a.P_c[static_cast<size_t>(c) * nc + k]) * a.inv_dt;
+      J = (p_new - pj[k]) * a.inv_dt;
       a.P_c[static_cast<size_t>(c) * nc + k] = p_new;
       a.J_mol[static_cast<size_t>(c) * nc + k] = J;
     } else {
-      J = a.J_mol[static_cast<size_t>(c) * nc + k];
+      J = pj[k];
     }
-    const int m = a.mat[static_cast<size_t>(k) * a.ncells + cell] & 3;
+    const int m = mk[k];
     T* E = static_cast<T*>(fld[k]);
     const T h = MolTerm<T>::held(a.ce[m], J);
     if (a.held) {
@@ -480,7 +494,7 @@ __global__ __launch_bounds__(256) void deposit_kernel(DepArgs a) {
       else
         E[cell] = __builtin_nan("");
     } else {
-      E[cell] = MolTerm<T>::apply(E[cell], static_cast<T>(a.ce[m]), h);
+      E[cell] = MolTerm<T>::apply(e_old[k], static_cast<T>(a.ce[m]), h);
     }
   }
 }
